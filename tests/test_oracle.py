@@ -1,0 +1,444 @@
+"""Pins for the CPU oracle, against things other than itself.
+
+Every check here compares the oracle with an independent statement of the mathematics:
+dense brute force (oracle/dense.py), LAPACK getrf via scipy, closed-form inverses,
+textbook GMRES (scipy), exact condition numbers (numpy), hand-derived orderings, and
+backward-error bounds.  A dropped term, a wrong sign or index, or a transposed operand
+anywhere in oracle.c breaks at least one of them.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import kkt_synth as ks
+import oracle
+from oracle import dense
+
+
+def csr_of(A):
+    M = sp.csr_matrix(A)
+    M.sort_indices()
+    return M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data.astype(np.float64)
+
+
+def csr_pattern_of_edges(n, edges, diag=True):
+    rows, cols = [], []
+    for a, b in edges:
+        rows += [a, b]
+        cols += [b, a]
+    if diag:
+        rows += list(range(n))
+        cols += list(range(n))
+    M = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, n))
+    M.sum_duplicates()
+    M.sort_indices()
+    return M.indptr.astype(np.int64), M.indices.astype(np.int32)
+
+
+def random_sparse(n, density, seed, sym_pattern=False):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) * (rng.random((n, n)) < density)
+    if sym_pattern:
+        mask = (A != 0) | (A.T != 0)
+        A = np.where(mask, rng.standard_normal((n, n)), 0.0)
+    A[np.arange(n), np.arange(n)] += rng.standard_normal(n)
+    return A
+
+
+def lu_to_dense(f):
+    n = f.n
+    Ls = np.zeros((n, n))
+    Us = np.zeros((n, n))
+    for j in range(n):
+        Ls[f.Li[f.Lp[j]:f.Lp[j + 1]], j] = f.Lx[f.Lp[j]:f.Lp[j + 1]]
+        Us[f.Ui[f.Up[j]:f.Up[j + 1]], j] = f.Ux[f.Up[j]:f.Up[j + 1]]
+    return Ls, Us
+
+
+# ----------------------------------------------------------------------------------------
+# generator
+# ----------------------------------------------------------------------------------------
+
+def test_generator_deterministic_and_shaped():
+    p1 = ks.make_pattern(1)
+    ks.make_pattern.cache_clear()
+    p2 = ks.make_pattern(1)
+    assert p1.N == 7000 and p1.n == 4000 and p1.m == 3000
+    assert np.array_equal(p1.rowptr, p2.rowptr) and np.array_equal(p1.colidx, p2.colidx)
+    v1, b1 = p1.system(1)
+    v2, b2 = p2.system(1)
+    assert np.array_equal(v1, v2) and np.array_equal(b1, b2)
+    # a = 4n + 7m full nonzeros: 1.5n edges twice, n + m diagonal, 3m J and 3m J^T
+    assert p1.nnz == 4 * p1.n + 7 * p1.m
+    K = sp.csr_matrix((v1, p1.colidx, p1.rowptr), shape=(p1.N, p1.N))
+    assert abs(K - K.T).max() == 0.0
+    assert oracle.check_csr(p1.rowptr, p1.colidx)
+    d = K.diagonal()
+    assert np.all(d[p1.n:] == -ks.DUAL_REG)
+    # later steps keep the pattern, change the values
+    v3, b3 = p1.system(3)
+    assert v3.shape == v1.shape and not np.array_equal(v3, v1) and not np.array_equal(b3, b1)
+
+
+# ----------------------------------------------------------------------------------------
+# ordering (hand-derived cases follow the nested-dissection rules step by step)
+# ----------------------------------------------------------------------------------------
+
+def test_order_path7():
+    rp, ci = csr_pattern_of_edges(7, [(i, i + 1) for i in range(6)])
+    # root 0 (min degree, smallest); levels {0}..{6}; separator level 3; halves {0,1,2}
+    # -> [0, 2, 1] and {4,5,6} -> [4, 6, 5]
+    assert oracle.order(rp, ci, leaf=1).tolist() == [0, 2, 1, 4, 6, 5, 3]
+    assert oracle.order(rp, ci).tolist() == list(range(7))  # a leaf at the default size
+
+
+def test_order_star():
+    rp, ci = csr_pattern_of_edges(7, [(0, i) for i in range(1, 7)])
+    # root 1; levels {1},{0},{2..6}; s clamped to 1 -> separator {0}; {2..6} splits into
+    # five single-vertex components
+    assert oracle.order(rp, ci, leaf=1).tolist() == [1, 2, 3, 4, 5, 6, 0]
+
+
+def test_order_grid3x3():
+    edges = []
+    for r in range(3):
+        for c in range(3):
+            v = 3 * r + c
+            if c < 2:
+                edges.append((v, v + 1))
+            if r < 2:
+                edges.append((v, v + 3))
+    rp, ci = csr_pattern_of_edges(9, edges)
+    # root 0; levels {0},{1,3},{2,4,6},{5,7},{8}; separator {2,4,6}; {0,1,3} -> [1,3,0];
+    # {5,7,8} -> [5,7,8]
+    assert oracle.order(rp, ci, leaf=1).tolist() == [1, 3, 0, 5, 7, 8, 2, 4, 6]
+
+
+def test_order_two_components():
+    # component A = path 3-4-5 (smallest vertex 3), component B = path 0-6-7-1... wait:
+    # B = path 0-1-2 (smallest vertex 0) -> B first
+    edges = [(3, 4), (4, 5), (0, 1), (1, 2)]
+    rp, ci = csr_pattern_of_edges(6, edges)
+    assert oracle.order(rp, ci, leaf=1).tolist() == [0, 2, 1, 3, 5, 4]
+
+
+def test_order_is_permutation_and_reduces_fill():
+    p = ks.make_pattern(1)
+    v, _ = p.system(1)
+    Q = oracle.order(p.rowptr, p.colidx)
+    assert sorted(Q.tolist()) == list(range(p.N))
+    f_nd = oracle.LU(p.rowptr, p.colidx, v, Q=Q)
+    f_nat = oracle.LU(p.rowptr, p.colidx, v, Q=np.arange(p.N, dtype=np.int32))
+    assert f_nd.lnz + f_nd.unz < 0.5 * (f_nat.lnz + f_nat.unz)
+
+
+# ----------------------------------------------------------------------------------------
+# pivoted LU
+# ----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("tau", [0.1, 1.0])
+def test_factor_matches_dense_bruteforce_kkt(seed, tau):
+    p = ks.small_kkt(30 + 3 * seed, 20 + 2 * seed, seed)
+    v, _ = p.system(1 + seed % 3)
+    Q = oracle.order(p.rowptr, p.colidx, leaf=4)
+    f = oracle.LU(p.rowptr, p.colidx, v, Q=Q, tau=tau)
+    A = ks.to_dense(p.rowptr, p.colidx, v, p.N)
+    prow, Lf, Uf = dense.dense_lu(A, Q, tau)
+    assert np.array_equal(prow, f.prow)
+    Ls, Us = lu_to_dense(f)
+    assert np.array_equal(Ls, Lf) and np.array_equal(Us, Uf)   # bit-identical values
+    # the structural pattern contains every numeric nonzero (symmetric KKT values can
+    # cancel exactly, so it may hold a few more)
+    assert f.lnz >= np.count_nonzero(Lf) and f.unz >= np.count_nonzero(Uf)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_factor_matches_dense_bruteforce_general(seed):
+    n = 40
+    A = random_sparse(n, 0.08, 100 + seed)
+    rp, ci, v = csr_of(A)
+    Q = np.random.default_rng(seed).permutation(n).astype(np.int32)
+    f = oracle.LU(rp, ci, v, Q=Q, tau=0.5)
+    prow, Lf, Uf = dense.dense_lu(A, Q, 0.5)
+    Ls, Us = lu_to_dense(f)
+    assert np.array_equal(prow, f.prow)
+    assert np.array_equal(Ls, Lf) and np.array_equal(Us, Uf)
+    # the structural patterns equal a boolean elimination with the same pivot sequence
+    Lpat, Upat = dense.dense_symbolic(A != 0, Q, prow)
+    Lsp = np.zeros((n, n), bool)
+    Usp = np.zeros((n, n), bool)
+    for j in range(n):
+        Lsp[f.Li[f.Lp[j]:f.Lp[j + 1]], j] = True
+        Usp[f.Ui[f.Up[j]:f.Up[j + 1]], j] = True
+    assert np.array_equal(Lsp, Lpat) and np.array_equal(Usp, Upat)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_partial_pivoting_matches_lapack(seed):
+    n = 60
+    A = random_sparse(n, 0.1, 200 + seed)
+    rp, ci, v = csr_of(A)
+    f = oracle.LU(rp, ci, v, Q=np.arange(n, dtype=np.int32), tau=1.0)
+    lu, piv = sla.lu_factor(A)
+    perm = np.arange(n)
+    for k in range(n):
+        perm[[k, piv[k]]] = perm[[piv[k], k]]
+    assert np.array_equal(perm, f.prow)
+    Ls, Us = lu_to_dense(f)
+    Lst = Ls[f.prow] + np.eye(n)   # rows in step order, unit diagonal
+    assert np.allclose(Lst, np.tril(lu, -1) + np.eye(n), rtol=1e-12, atol=1e-13)
+    assert np.allclose(Us, np.triu(lu), rtol=1e-12, atol=1e-12 * np.abs(lu).max())
+
+
+@pytest.mark.parametrize("cfg_seed", range(4))
+def test_factor_backward_error_bound(cfg_seed):
+    p = ks.small_kkt(120, 80, 10 + cfg_seed)
+    v, _ = p.system(2)
+    f = oracle.LU(p.rowptr, p.colidx, v, Q=oracle.order(p.rowptr, p.colidx, leaf=8))
+    A = ks.to_dense(p.rowptr, p.colidx, v, p.N)
+    Ls, Us = lu_to_dense(f)
+    Lst = Ls[f.prow] + np.eye(p.N)
+    PAQ = A[f.prow][:, f.Q]
+    err = np.abs(PAQ - Lst @ Us).max()
+    bound = p.N * np.finfo(float).eps * (np.abs(Lst) @ np.abs(Us)).max()
+    assert err <= bound
+
+
+def test_closed_form_decoupled_kkt():
+    # m = n, J = I, H diagonal: independent blocks [[a, 1], [1, -delta]], a = h + d
+    nb = 50
+    rng = np.random.default_rng(7)
+    a = 10.0 ** rng.uniform(-6, 6, nb)
+    delta = 1e-8
+    N = 2 * nb
+    A = np.zeros((N, N))
+    A[np.arange(nb), np.arange(nb)] = a
+    A[np.arange(nb), nb + np.arange(nb)] = 1.0
+    A[nb + np.arange(nb), np.arange(nb)] = 1.0
+    A[nb + np.arange(nb), nb + np.arange(nb)] = -delta
+    rp, ci, v = csr_of(A)
+    Q = np.arange(N, dtype=np.int32)
+    f = oracle.LU(rp, ci, v, Q=Q, tau=0.1)
+    # pivot rule: first column of block i has candidates {i: a_i, nb+i: 1}
+    for i in range(nb):
+        expect = i if a[i] >= 0.1 else nb + i
+        assert f.prow[i] == expect
+    b = rng.standard_normal(N)
+    x = f.solve(b)
+    det = -a * delta - 1.0
+    x1 = (-delta * b[:nb] - b[nb:]) / det
+    x2 = (-b[:nb] + a * b[nb:]) / det
+    xt = np.r_[x1, x2]
+    assert np.abs(x - xt).max() <= 1e-13 * np.abs(xt).max()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_solve_matches_numpy_and_manufactured(seed):
+    p = ks.small_kkt(80, 50, 30 + seed, dlog=(-2.0, 2.0))
+    v, b = p.system(1)
+    A = ks.to_dense(p.rowptr, p.colidx, v, p.N)
+    xs, f = oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=oracle.order(p.rowptr, p.colidx, leaf=8))
+    xn = np.linalg.solve(A, b)
+    kappa = np.linalg.cond(A, 1)
+    assert np.linalg.norm(xs - xn) / np.linalg.norm(xn) <= 100 * np.finfo(float).eps * kappa
+    xt = np.random.default_rng(seed).standard_normal(p.N)
+    bt = A @ xt
+    xm = f.solve(bt)
+    assert np.linalg.norm(xm - xt) / np.linalg.norm(xt) <= 100 * np.finfo(float).eps * kappa
+    # dense brute-force solve with the same factors is bit-identical
+    prow, Lf, Uf = dense.dense_lu(A, f.Q, 0.1)
+    assert np.array_equal(dense.dense_solve(prow, Lf, Uf, f.Q, b), xs)
+
+
+def test_metrics_definitions_on_known_residual():
+    A = np.array([[4.0, -1.0, 0.0], [-1.0, 4.0, -1.0], [0.0, -1.0, 4.0]])
+    rp, ci, v = csr_of(A)
+    x = np.array([1.0, 2.0, -3.0])
+    b = np.array([0.5, 10.0, -12.0])
+    r = b - A @ x
+    m = oracle.metrics(rp, ci, v, x, b)
+    knorm = 6.0
+    assert m["knorm"] == knorm
+    assert m["nrbe"] == pytest.approx(np.linalg.norm(r) / (knorm * np.linalg.norm(x) + np.linalg.norm(b)), rel=1e-15)
+    assert m["nsr"] == pytest.approx(np.abs(r).max() / (knorm * np.abs(x).max()), rel=1e-15)
+    assert m["rel_resid"] == pytest.approx(np.linalg.norm(r) / np.linalg.norm(b), rel=1e-15)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_direct_solve_nrbe_near_machine_eps(cfg):
+    p = ks.make_pattern(cfg)
+    v, b = p.system(1)
+    x, f = oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=oracle.order(p.rowptr, p.colidx))
+    assert oracle.metrics(p.rowptr, p.colidx, v, x, b)["nrbe"] <= 1e-14
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_condest_bounds(seed):
+    p = ks.small_kkt(60, 40, 50 + seed, dlog=(-3.0, 3.0))
+    v, _ = p.system(1)
+    f = oracle.LU(p.rowptr, p.colidx, v, Q=oracle.order(p.rowptr, p.colidx, leaf=8))
+    A = ks.to_dense(p.rowptr, p.colidx, v, p.N)
+    k1 = np.linalg.cond(A, 1)
+    ke = f.condest(p.rowptr, v)
+    assert ke <= k1 * (1 + 1e-8)
+    assert ke >= k1 / 10
+
+
+# ----------------------------------------------------------------------------------------
+# static-pivot refactorization
+# ----------------------------------------------------------------------------------------
+
+def test_refactor_first_system_bit_identical():
+    p = ks.make_pattern(1)
+    v, _ = p.system(1)
+    f = oracle.LU(p.rowptr, p.colidx, v)
+    Lx, Ux, ng = f.refactor64(p.rowptr, p.colidx, v)
+    assert ng == 0
+    assert np.array_equal(Lx, f.Lx) and np.array_equal(Ux, f.Ux)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_refactor_matches_dense_static(seed):
+    p = ks.small_kkt(40, 25, 60 + seed, dlog=(-1.0, 1.0))
+    v1, _ = p.system(1)
+    v2, _ = p.system(2)
+    f = oracle.LU(p.rowptr, p.colidx, v1, Q=oracle.order(p.rowptr, p.colidx, leaf=4))
+    A2 = ks.to_dense(p.rowptr, p.colidx, v2, p.N)
+    Lx, Ux, ng = f.refactor64(p.rowptr, p.colidx, v2)
+    Lf, Uf = dense.dense_lu_static(A2, f.Q, f.prow, np.float64)
+    g = oracle.LU.__new__(oracle.LU)
+    g.__dict__.update({k: getattr(f, k) for k in ("n", "Lp", "Li", "Up", "Ui")})
+    g.Lx, g.Ux = Lx, Ux
+    Ls, Us = lu_to_dense(g)
+    assert ng == 0
+    assert np.array_equal(Ls, Lf) and np.array_equal(Us, Uf)
+    Lx32, Ux32, ng32 = f.refactor32(p.rowptr, p.colidx, v2)
+    Lf32, Uf32 = dense.dense_lu_static(A2, f.Q, f.prow, np.float32)
+    g.Lx, g.Ux = Lx32.astype(np.float64), Ux32.astype(np.float64)
+    Ls32, Us32 = lu_to_dense(g)
+    assert ng32 == 0
+    assert np.array_equal(Ls32, Lf32.astype(np.float64)) and np.array_equal(Us32, Uf32.astype(np.float64))
+    # FP32 solve agrees with a float32 dense solve
+    b = np.random.default_rng(seed).standard_normal(p.N)
+    x32 = f.solve32(b, Lx32, Ux32)
+    xd = np.linalg.solve(A2, b)
+    assert np.linalg.norm(x32 - xd) / np.linalg.norm(xd) < 1e-3
+
+
+def test_refactor_pivot_guard():
+    # K_1 = [[4, 2], [2, 3]]: both diagonal pivots.  K_2 = [[4, 2], [2, 1]] makes the second
+    # static pivot 1 - 2*2/4 = 0 exactly: guarded to +u * colmax = 2^-53 * 2.
+    A1 = np.array([[4.0, 2.0], [2.0, 3.0]])
+    A2 = np.array([[4.0, 2.0], [2.0, 1.0]])
+    rp, ci, v1 = csr_of(A1)
+    _, _, v2 = csr_of(A2)
+    f = oracle.LU(rp, ci, v1, Q=np.arange(2, dtype=np.int32), tau=0.1)
+    assert f.prow.tolist() == [0, 1]
+    Lx, Ux, ng = f.refactor64(rp, ci, v2)
+    assert ng == 1
+    assert Ux[-1] == 2.0 * 2.0 ** -53
+    with pytest.raises(oracle.OracleError) as e:
+        f.refactor64(rp, ci, v2, guard_policy=1)
+    assert e.value.code == oracle.ESINGULAR
+    Lx32, Ux32, ng32 = f.refactor32(rp, ci, v2)
+    assert ng32 == 1 and Ux32[-1] == np.float32(2.0 * 2.0 ** -24)
+
+
+def test_singular_column_reported():
+    A = np.array([[1.0, 1.0, 0.0], [1.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    rp, ci, v = csr_of(A)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.LU(rp, ci, v, Q=np.arange(3, dtype=np.int32))
+    assert e.value.code == oracle.ESINGULAR
+
+
+def test_bad_csr_rejected():
+    rp = np.array([0, 2, 3], np.int64)
+    ci = np.array([1, 0, 1], np.int32)   # unsorted row 0
+    assert not oracle.check_csr(rp, ci)
+    ci2 = np.array([0, 5, 1], np.int32)  # out of range
+    assert not oracle.check_csr(rp, ci2)
+
+
+# ----------------------------------------------------------------------------------------
+# FGMRES-IR
+# ----------------------------------------------------------------------------------------
+
+def identity_lu(n):
+    rp = np.arange(n + 1, dtype=np.int64)
+    ci = np.arange(n, dtype=np.int32)
+    return oracle.LU(rp, ci, np.ones(n), Q=np.arange(n, dtype=np.int32))
+
+
+def test_fgmres_identity_preconditioner_is_gmres():
+    n = 120
+    rng = np.random.default_rng(3)
+    A = sp.random(n, n, density=0.05, random_state=4, format="csr") + sp.eye(n) * 4.0
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    rp, ci, v = A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data
+    b = rng.standard_normal(n)
+    fI = identity_lu(n)
+    R = 8
+    x, info = fI.fgmres_ir(rp, ci, v, b, restart=R, max_restarts=0, eta=1e-30, mode=1)
+    # scipy GMRES from the same initial guess x0 = M^-1 b = b, one cycle of R steps
+    hist = []
+    r0 = np.linalg.norm(b - A @ b)
+    spla.gmres(A, b, x0=b.copy(), restart=R, maxiter=1, rtol=1e-30, atol=0.0,
+               callback=lambda pr: hist.append(pr), callback_type="pr_norm")
+    ours = info["hist"][:R] / np.linalg.norm(b)   # scipy reports ||r_i|| / ||b||
+    assert len(hist) >= R - 1 and r0 > 0
+    k = min(len(hist), R)
+    assert np.allclose(ours[:k], np.array(hist[:k]), rtol=1e-8)
+    # one full cycle of GMRES minimises the residual over the Krylov space
+    xs, _ = spla.gmres(A, b, x0=b.copy(), restart=R, maxiter=1, rtol=1e-30, atol=0.0)
+    assert np.linalg.norm(b - A @ x) == pytest.approx(np.linalg.norm(b - A @ xs), rel=1e-8)
+
+
+def test_fgmres_distinct_eigenvalues():
+    n = 90
+    d = np.repeat([2.0, 3.0, 7.0], n // 3)   # x0 = b, so rho0 = (1 - d) b keeps all three
+    rp = np.arange(n + 1, dtype=np.int64)
+    ci = np.arange(n, dtype=np.int32)
+    b = np.random.default_rng(5).standard_normal(n)
+    fI = identity_lu(n)
+    x, info = fI.fgmres_ir(rp, ci, d, b, restart=10, max_restarts=0, eta=1e-13, mode=1)
+    assert info["converged"] and info["iters"] == 3
+    assert np.abs(d * x - b).max() < 1e-12
+
+
+def test_fgmres_estimate_equals_true_residual_at_restart():
+    n = 150
+    A = sp.random(n, n, density=0.04, random_state=8, format="csr") + sp.eye(n) * 3.0
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    rp, ci, v = A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data
+    b = np.random.default_rng(9).standard_normal(n)
+    fI = identity_lu(n)
+    x, info = fI.fgmres_ir(rp, ci, v, b, restart=5, max_restarts=0, eta=1e-30, mode=1)
+    assert info["est"] == pytest.approx(info["true_resid"], rel=1e-6)
+    assert np.all(np.diff(info["hist"]) <= 1e-12 * info["hist"][0])   # non-increasing
+
+
+def test_fgmres_ir_exact_preconditioner_and_sequence():
+    p = ks.make_pattern(1)
+    v1, b1 = p.system(1)
+    f = oracle.LU(p.rowptr, p.colidx, v1)
+    # exact factors: x0 already meets the NRBE target, so refinement is skipped
+    x, info = f.fgmres_ir(p.rowptr, p.colidx, v1, b1, mode=0, eta=1e-12)
+    assert info["iters"] == 0 and info["converged"]
+    # paper's relative-residual control on a static-pivot system of a longer sequence
+    p2 = ks.make_pattern(2)
+    w1, _ = p2.system(1)
+    g = oracle.LU(p2.rowptr, p2.colidx, w1)
+    w3, b3 = p2.system(3)
+    Lx, Ux, _ = g.refactor64(p2.rowptr, p2.colidx, w3)
+    x0 = g.solve(b3, Lx, Ux)
+    m0 = oracle.metrics(p2.rowptr, p2.colidx, w3, x0, b3)
+    x, info = g.fgmres_ir(p2.rowptr, p2.colidx, w3, b3, Lx=Lx, Ux=Ux, restart=10, mode=1, eta=1e-14)
+    m = oracle.metrics(p2.rowptr, p2.colidx, w3, x, b3)
+    assert info["converged"] and 1 <= info["iters"] <= 30
+    assert m["nrbe"] <= 1e-12 and m["resid"] < 1e-3 * m0["resid"]
