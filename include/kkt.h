@@ -1,0 +1,184 @@
+/*
+ * kkt.h -- C ABI of a GPU-resident solver for sequences of sparse KKT systems that share
+ * one sparsity pattern, on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Swirydowicz, Koukpaizan, Alam, Regev, Saunders, Peles, "Iterative Methods in
+ * GPU-Resident Linear Solvers for Nonlinear Constrained Optimization"):
+ *   - the systems K_k dx_k = r_k of eq. (kktlinear) share one pattern (Section 1.2, "Summary");
+ *   - the first system gets a full symbolic analysis and a factorization with pivoting on the
+ *     host; every later system gets a numeric refactorization on the GPU that reuses the
+ *     pattern and the pivot sequence (static pivoting, Section 1.3);
+ *   - the direct solution x0 = Q U^-1 L^-1 P r is refined by FGMRES with the LU factors as a
+ *     right preconditioner, CGS2 orthogonalization, the estimated residual as stopping test
+ *     and the solution formed only at restart/convergence (Section 2.1); refinement runs only
+ *     when ||r - K x0|| / ||r|| >= delta_tol (Section 2.3).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are CSR: int64 row pointers (N+1), int32 column indices sorted ascending
+ *     within each row with no duplicates, float64 values.  The FULL symmetric matrix is
+ *     passed (both triangles).  Indices are 0-based.
+ *   - "host" pointers are read during the call only; the library keeps its own copies.
+ *   - "device" pointers are caller-owned HIP device memory, read or written only on the
+ *     given stream for the duration of the call (the call returns after the work on that
+ *     stream has been issued, or after it completes where stated).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - No exception crosses the ABI: every call returns a kkt_status_t; kkt_last_error()
+ *     gives a message for the last failing call on the handle.
+ *   - One handle is used by one host thread at a time; distinct handles are independent.
+ */
+#ifndef KKT_H
+#define KKT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kkt_handle_s *kkt_handle_t;
+
+typedef enum {
+    KKT_OK = 0,
+    KKT_EINVAL = 1,     /* invalid argument or input (bad CSR, non-finite values, ...) */
+    KKT_ENOMEM = 2,     /* host allocation failed or the workspace is too small */
+    KKT_ESINGULAR = 3,  /* singular column in the pivoted analysis, or a guarded pivot with
+                           guard_policy = KKT_GUARD_FAIL */
+    KKT_ENOCONV = 4,    /* FGMRES-IR did not meet the tolerance; x holds the last iterate */
+    KKT_EDEVICE = 5,    /* a HIP call failed; the handle accepts only kkt_release() */
+    KKT_ESTATE = 6      /* call out of order (solve before refactor, no workspace, ...) */
+} kkt_status_t;
+
+enum { KKT_PREC_FP64 = 0, KKT_PREC_MIXED = 1 };     /* factor / preconditioner precision */
+enum { KKT_GUARD_PERTURB = 0, KKT_GUARD_FAIL = 1 }; /* tiny static pivot policy */
+enum { KKT_STOP_PAPER = 0, KKT_STOP_NRBE = 1 };     /* FGMRES-IR stopping control */
+
+typedef struct {
+    int32_t nd_leaf;        /* ordering: sets of <= nd_leaf vertices are not dissected (64) */
+    double pivot_tau;       /* threshold partial pivoting: keep the diagonal row when
+                               |x_c| >= tau * max |x_i| (0.1) */
+    int32_t restart;        /* FGMRES restart length R (10, Section 4.1.1) */
+    int32_t max_restarts;   /* cycles after the first (20) */
+    double delta_tol;       /* refine/stop tolerance delta_tol (1e-14, Section 4.1.2) */
+    double nrbe_target;     /* accept only when NRBE (eq. (nbre)) <= this (1e-12) */
+    int32_t precision;      /* KKT_PREC_FP64 or KKT_PREC_MIXED (FP32 factors and triangular
+                               solves as preconditioner, FP64 Krylov) */
+    int32_t guard_policy;   /* KKT_GUARD_PERTURB: replace a static pivot with
+                               |u_jj| <= u * max_i |K(i,Q[j])| by sign(u_jj) u colmax and count
+                               it; KKT_GUARD_FAIL: report KKT_ESINGULAR */
+    int32_t stop_mode;      /* KKT_STOP_PAPER: refine iff ||rho0||/||r|| >= delta_tol, stop
+                               on estimated RR < delta_tol, accept iff also NRBE <=
+                               nrbe_target; KKT_STOP_NRBE: refine iff NRBE(x0) > nrbe_target,
+                               inner test |g| <= nrbe_target (||K||inf ||x|| + ||r||) */
+    int32_t mixed_fallback; /* mixed precision: on non-convergence refactor in FP64 and
+                               solve again (1) or return KKT_ENOCONV (0) */
+} kkt_opts_t;
+
+typedef struct {
+    int64_t n;              /* N */
+    int64_t nnz;            /* nonzeros of K (full) */
+    int64_t nnz_l;          /* strictly lower nonzeros of L */
+    int64_t nnz_u;          /* nonzeros of U including the diagonal */
+    int64_t offdiag_pivots; /* analysis pivots not on the diagonal of K(:,Q) */
+    int64_t levels_refactor;/* depth of the column dependency DAG of the refactorization */
+    int64_t levels_l;       /* depth of the row DAG of the L solve */
+    int64_t levels_u;       /* depth of the row DAG of the U solve */
+    int64_t updates;        /* scalar multiply-subtract updates per refactorization */
+    double analysis_seconds;/* host time spent in kkt_analyze */
+} kkt_analysis_info_t;
+
+typedef struct {
+    int32_t converged;       /* 1 if the accept test passed */
+    int32_t iterations;      /* FGMRES (Arnoldi) iterations in total */
+    int32_t cycles;          /* restart cycles run (0 when refinement was skipped) */
+    int32_t refined;         /* 1 if the refine test asked for FGMRES */
+    int32_t precision;       /* precision of the factors that produced x */
+    int32_t fallback;        /* 1 if a mixed solve fell back to FP64 factors */
+    int64_t pivots_perturbed;/* guarded static pivots in the last refactorization */
+    double nrbe;             /* ||r - K x||_2 / (||K||_inf ||x||_2 + ||r||_2) */
+    double nrbe0;            /* the same for the direct solution x0 */
+    double rel_resid;        /* ||r - K x||_2 / ||r||_2 */
+    double rr;               /* ||r - K x||_2 / ||r - K x0||_2 (true residuals) */
+    double est_resid;        /* last estimated FGMRES residual norm */
+    double true_resid;       /* ||r - K x||_2 */
+    double knorm_inf;        /* ||K||_inf */
+} kkt_solve_info_t;
+
+/* Fill *opts with the defaults listed above. */
+void kkt_opts_default(kkt_opts_t *opts);
+
+/* Analyse a pattern on the host with the values of the first system (Section 1.3: symbolic
+ * analysis plus factorization with pivoting on system 1): validates the CSR, computes the
+ * nested-dissection ordering Q and a threshold-pivoted left-looking LU of K(:,Q), and builds
+ * every schedule the GPU kernels need.  rowptr/colidx/values_first are HOST pointers.  Does
+ * not touch the GPU.  On success *out owns a new handle (release with kkt_release).
+ * Errors: KKT_EINVAL (bad CSR, N < 1, non-finite value), KKT_ESINGULAR (no nonzero pivot
+ * candidate; the column is named in kkt_last_error), KKT_ENOMEM. */
+kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowptr,
+                         const int32_t *colidx, const double *values_first, kkt_handle_t *out);
+
+/* Sizes and schedule statistics of the analysis (host only). */
+kkt_status_t kkt_get_analysis_info(kkt_handle_t h, kkt_analysis_info_t *info);
+
+/* Pivot sequence and ordering: prow[k] = row of K pivoted at step k, q[k] = column of K
+ * eliminated at step k, so that P K Q = L U (host arrays of n entries). */
+kkt_status_t kkt_get_permutations(kkt_handle_t h, int32_t *prow, int32_t *q);
+
+/* Factor patterns in column-compressed form (host arrays): L strictly lower with ORIGINAL
+ * row indices of K ascending per column (lp: n+1, li: nnz_l); U upper with pivot-step row
+ * indices ascending per column, diagonal last (up: n+1, ui: nnz_u). */
+kkt_status_t kkt_get_factor_pattern(kkt_handle_t h, int64_t *lp, int32_t *li, int64_t *up,
+                                    int32_t *ui);
+
+/* Values of the host analysis factorization (system 1), in the layout of
+ * kkt_get_factor_pattern (host arrays, nnz_l and nnz_u entries). */
+kkt_status_t kkt_get_analysis_values(kkt_handle_t h, double *lx, double *ux);
+
+/* Device bytes needed by kkt_bind_workspace (factor values in FP64 and FP32, structure
+ * arrays, Krylov basis V and Z for the restart length, scratch). */
+kkt_status_t kkt_workspace_size(kkt_handle_t h, size_t *bytes);
+
+/* Bind caller-owned device memory (>= kkt_workspace_size bytes, 256-byte aligned) and upload
+ * the structure arrays on `stream` (synchronous on return).  The current HIP device at this
+ * call is the handle's device.  Rebinding replaces the previous workspace. */
+kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, void *stream);
+
+/* Numeric refactorization of a new system with the fixed pattern and pivot sequence
+ * (Section 1.3 / 2.1).  dev_values: DEVICE array of nnz float64 values in the CSR order of
+ * the analysed pattern; copied into the workspace, so it may be reused after the call's
+ * work completes.  Work is enqueued on `stream`; tiny-pivot guards are counted on the device
+ * and reported by the next kkt_solve.  Errors: KKT_ESTATE (no workspace). */
+kkt_status_t kkt_refactor(kkt_handle_t h, const double *dev_values, void *stream);
+
+/* Solve K x = b for the last refactored K: direct solve, refine decision, FGMRES-IR
+ * (Section 2).  dev_b, dev_x: DEVICE arrays of n float64 (distinct).  tol <= 0 uses
+ * opts.delta_tol.  Synchronizes `stream` once per restart cycle and before returning; *info
+ * (may be NULL) is filled on return.  Errors: KKT_ESTATE (no refactor yet), KKT_EINVAL
+ * (non-finite K values or b), KKT_ESINGULAR (guard_policy = FAIL and a guarded pivot),
+ * KKT_ENOCONV (tolerance not met; x holds the last iterate, info is filled). */
+kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, double tol,
+                       kkt_solve_info_t *info, void *stream);
+
+/* Apply the current preconditioner once: x = Q U^-1 L^-1 P b with the last refactored
+ * factors (the direct solve of Section 1.3, no refinement).  DEVICE arrays of n float64.
+ * Enqueued on `stream`, not synchronized. */
+kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x, void *stream);
+
+/* Copy the current device factor values (last kkt_refactor) to HOST arrays in the layout
+ * of kkt_get_factor_pattern; precision 0 = FP64 factors, 1 = FP32 factors widened to
+ * float64.  Synchronizes `stream`. */
+kkt_status_t kkt_get_factor_values(kkt_handle_t h, int32_t precision, double *lx, double *ux,
+                                   void *stream);
+
+/* Free the handle and its host memory (the workspace stays owned by the caller). */
+kkt_status_t kkt_release(kkt_handle_t h);
+
+/* Message for the last failing call on h ("" if none; h may be NULL for kkt_analyze
+ * failures, which keep a per-thread message). */
+const char *kkt_last_error(kkt_handle_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KKT_H */

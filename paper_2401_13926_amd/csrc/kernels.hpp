@@ -1,0 +1,60 @@
+// Device-side data structures shared by the kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kkt {
+
+constexpr int kRestartMax = 64;        // largest supported FGMRES restart length
+constexpr int kStreamBlock = 256;      // threads per block of the streaming kernels
+constexpr int kStreamGridMax = 1024;   // blocks of the streaming kernels (partials rows)
+constexpr int kCoopBlock = 256;        // threads per block of the dependency-driven kernels
+constexpr int kRefactorLds = 1024;     // factor entries staged in LDS per wavefront
+// Spin limit of one dependency wait (iterations of a short sleep, a few seconds in all);
+// exceeding it marks Control::hang and lets every wave run to completion.
+constexpr unsigned int kSpinLimit = 1u << 22;
+
+// Scalars shared between kernels of one refactor/solve (device memory).
+struct Control {
+    unsigned long long knorm_bits;  // max_i sum_j |K_ij| as the bits of a non-negative double
+    unsigned int nonfinite;         // a non-finite matrix value was ingested
+    unsigned int guard_fail;        // a guarded pivot under the FAIL policy
+    unsigned long long nguard;      // guarded (perturbed) pivots
+    unsigned int counter;           // arrival counter of the "last block reduces" pattern
+    int stop;                       // current FGMRES cycle has ended
+    int jdone;                      // Arnoldi steps completed in the current cycle
+    int breakdown;                  // happy breakdown in the current cycle
+    int nonfinite_b;                // non-finite right-hand side
+    unsigned int hang;              // a dependency wait exceeded its spin limit
+    double beta;                    // ||rho|| at the start of the cycle
+    double inner_tol;               // stop when the estimated residual <= inner_tol
+    double est;                     // estimated residual |g_{j+1}|
+    double wnorm_in;                // ||K z_j|| before orthogonalization
+    double hn;                      // ||w|| after CGS2
+    double rnorm2, xnorm2, bnorm2;  // sums of squares from the residual kernel
+    double h1[kRestartMax + 1];     // first CGS pass coefficients
+    double h2[kRestartMax + 1];     // second CGS pass coefficients
+    double g[kRestartMax + 1];      // rotated right-hand side of the least-squares problem
+    double cs[kRestartMax], sn[kRestartMax];
+    double y[kRestartMax];          // least-squares solution of the cycle
+    double H[(kRestartMax + 1) * kRestartMax];  // rotated Hessenberg (upper triangular), column-major
+    unsigned int work_refactor;     // next column-order index to hand out (refactorization)
+    unsigned int work_lower;        // next task index to hand out (L solve)
+    unsigned int work_upper;        // next task index to hand out (U solve)
+};
+
+// Host-visible summary copied back once per cycle.
+struct ControlSummary {
+    unsigned long long knorm_bits;
+    unsigned int nonfinite;
+    unsigned int guard_fail;
+    unsigned long long nguard;
+    unsigned int counter;
+    int stop, jdone, breakdown, nonfinite_b;
+    unsigned int hang;
+    double beta, inner_tol, est, wnorm_in, hn, rnorm2, xnorm2, bnorm2;
+};
+
+}  // namespace kkt

@@ -1,0 +1,1367 @@
+// GPU refactorization, triangular solves and FGMRES-IR for sequences of sparse KKT systems on
+// MI355X (gfx950), and the C ABI declared in include/kkt.h.
+//
+// Paper: Swirydowicz et al., "Iterative Methods in GPU-Resident Linear Solvers for Nonlinear
+// Constrained Optimization".  Section 1.3: refactorization with static pivoting; Section 2.1:
+// FGMRES iterative refinement with the LU factors as right preconditioner and CGS2;
+// Section 2.2: NRBE (eq. (nbre)); Section 2.3: the refine decision.
+//
+// Kernels (all wave64):
+//   k_ingest / k_rownorm     new values -> factor storage (fill = 0), ||K||_inf, finiteness
+//   k_refactor<T>            eager left-looking numeric LU, one wavefront per column, columns
+//                            in dependency-level order on a co-resident grid; a column starts
+//                            its update chain at once and waits per source column on a done
+//                            flag (acquire fence once per batch of ready sources)
+//   k_trsv<T, LOWER>         row-oriented triangular solve; rows in level order, a wavefront
+//                            takes up to 64/g rows of one level (g lanes per row); a solution
+//                            entry is its own ready flag (a NaN sentinel until written)
+//   k_spmv_dots, k_cgs_*, k_normalize, k_resid, k_lsq, k_xupdate   Krylov kernels with
+//                            deterministic two-level reductions (last block reduces)
+//
+// Floating point: compiled with -ffp-contract=off, so the refactorization performs exactly
+// the roundings of a left-looking column LU with ascending updates (reproducible factors).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kkt.h"
+#include "analysis.hpp"
+#include "kernels.hpp"
+
+namespace kkt {
+
+// ---------------------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------------------
+
+// Sentinels: signalling-NaN bit patterns no arithmetic result can take.
+constexpr unsigned long long kSent64 = 0x7FF4DEADBEEF0001ull;
+constexpr unsigned int kSent32 = 0x7FA0BEEFu;
+
+template <typename T> struct Bits;
+template <> struct Bits<double> {
+    using U = unsigned long long;
+    static constexpr U sent = kSent64;
+};
+template <> struct Bits<float> {
+    using U = unsigned int;
+    static constexpr U sent = kSent32;
+};
+
+template <typename T> __device__ __forceinline__ T sentinel() {
+    return __builtin_bit_cast(T, Bits<T>::sent);
+}
+template <typename T> __device__ __forceinline__ bool is_sentinel(T v) {
+    return __builtin_bit_cast(typename Bits<T>::U, v) == Bits<T>::sent;
+}
+
+template <typename T> __device__ __forceinline__ void store_ready(T *p, T v) {
+    using U = typename Bits<T>::U;
+    __hip_atomic_store(reinterpret_cast<U *>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Value of a solution entry produced by another wavefront: a plain load first (it can only
+// return the sentinel or the final value), then coherent polling until it is written.  A
+// wait longer than kSpinLimit sets *hang and gives up (every later wait then returns at
+// once), so a broken schedule ends the kernel with an error instead of never finishing.
+template <typename T> __device__ __forceinline__ T load_ready(const T *p, unsigned int *hang) {
+    using U = typename Bits<T>::U;
+    T v = *p;
+    if (!is_sentinel(v)) return v;
+    U b;
+    unsigned int spins = 0;
+    do {
+        __builtin_amdgcn_s_sleep(1);
+        b = __hip_atomic_load(reinterpret_cast<const U *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (++spins >= kSpinLimit ||
+            ((spins & 1023u) == 0 && __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            __hip_atomic_store(hang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return T(0);
+        }
+    } while (b == Bits<T>::sent);
+    return __builtin_bit_cast(T, b);
+}
+
+// Wave-uniform: lane 0 takes `chunk` consecutive work items from *counter.
+__device__ __forceinline__ unsigned int grab(unsigned int *counter, unsigned int chunk) {
+    unsigned int v = 0;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(counter, chunk);
+    return __shfl(v, 0, 64);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename T> __device__ __forceinline__ T wave_max(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide sum of one double per thread (blockDim = kStreamBlock); result in all threads.
+__device__ double block_sum(double v, double *red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kStreamBlock / 64; ++w) s += red[w];
+    return s;
+}
+
+// Arrival of a block in a two-level reduction; true in every thread of the last block.
+__device__ bool last_block(unsigned int *counter) {
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+// Row range of block b when `total` rows are split into gridDim.x contiguous chunks.
+__device__ __forceinline__ void block_rows(int64_t total, int64_t &r0, int64_t &r1) {
+    const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+    r0 = (int64_t)blockIdx.x * chunk;
+    r1 = r0 + chunk < total ? r0 + chunk : total;
+}
+
+// ---------------------------------------------------------------------------------------
+// ingest: K values into the workspace and into the factor layout (fill entries = 0)
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_prep_solve(Control *c) {
+    c->hang = 0;
+    c->nonfinite_b = 0;
+    c->counter = 0;
+    c->stop = 0;
+}
+
+__global__ void k_prep_refactor(Control *c) {
+    c->work_refactor = 0;
+    c->hang = 0;
+    c->knorm_bits = 0;
+    c->nonfinite = 0;
+    c->guard_fail = 0;
+    c->nguard = 0;
+    c->counter = 0;
+}
+
+// kval == nullptr: the values are already in the workspace (re-ingest for a fallback).
+__global__ void k_ingest(int64_t nnz, const double *vals, double *kval, int64_t f,
+                         const int64_t *__restrict__ fsrc, double *__restrict__ F64,
+                         float *__restrict__ F32, int mixed, Control *c) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    if (kval)
+        for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += stride) {
+            const double v = vals[p];
+            kval[p] = v;
+            bad |= !isfinite(v);
+        }
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < f; t += stride) {
+        const int64_t s = fsrc[t];
+        const double v = s >= 0 ? vals[s] : 0.0;
+        if (mixed) F32[t] = (float)v;
+        else F64[t] = v;
+    }
+    if (bad) atomicOr(&c->nonfinite, 1u);
+}
+
+__global__ void k_rownorm(int64_t n, const int64_t *__restrict__ rp, const double *__restrict__ kval,
+                          Control *c) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double s = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += fabs(kval[p]);
+        m = fmax(m, s);
+    }
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(&c->knorm_bits, __double_as_longlong(m));
+}
+
+// ---------------------------------------------------------------------------------------
+// refactorization (static pivots): one wavefront per column, eager left-looking
+// ---------------------------------------------------------------------------------------
+
+template <typename T> struct RefactorArgs {
+    int64_t n;
+    const int64_t *fp;
+    const int32_t *fi;
+    const int32_t *fdiag;
+    const int64_t *relptr;
+    const int32_t *relpos;
+    const int32_t *order;
+    const int32_t *f2t;
+    T *F;                // factor values (ingested on entry, final on exit)
+    T *Tv;               // solve layout copy
+    unsigned int *flag;  // per column: epoch when done
+    unsigned int epoch;
+    unsigned int chunk;  // columns taken per grab
+    int guard_fail_policy;
+    Control *ctl;
+};
+
+template <typename T> __device__ __forceinline__ T unit_roundoff();
+template <> __device__ __forceinline__ double unit_roundoff<double>() { return 0x1p-53; }
+template <> __device__ __forceinline__ float unit_roundoff<float>() { return 0x1p-24f; }
+
+// Applies the update chain of column j to x (LDS or the column's own global storage).
+template <typename T, bool kLds>
+__device__ void refactor_chain(const RefactorArgs<T> &a, int j, int64_t c0, int nu, T *x) {
+    const int lane = threadIdx.x & 63;
+    int64_t rp = a.relptr[j];
+    int t0 = 0;
+    unsigned int spins = 0;
+    while (t0 < nu) {
+        const int cnt = nu - t0 < 64 ? nu - t0 : 64;
+        bool ready = true;
+        if (lane < cnt) {
+            const int k = a.fi[c0 + t0 + lane];
+            ready = __hip_atomic_load(a.flag + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.epoch;
+        }
+        const unsigned long long waiting = __ballot(!ready);
+        int nready = waiting ? __builtin_ctzll(waiting) : cnt;
+        if (nready == 0) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins >= kSpinLimit ||
+                ((spins & 1023u) == 0 &&
+                 __hip_atomic_load(&a.ctl->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                if (lane == 0) __hip_atomic_store(&a.ctl->hang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                nready = cnt;  // give up: finish with whatever values are there
+            } else {
+                continue;
+            }
+        }
+        spins = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the ready sources' values
+        for (int s = 0; s < nready; ++s) {
+            const int k = a.fi[c0 + t0 + s];
+            const T u = x[t0 + s];
+            const int64_t l0 = a.fp[k] + a.fdiag[k] + 1;
+            const int64_t nl = a.fp[k + 1] - l0;
+            for (int64_t e = lane; e < nl; e += 64) {
+                const T lv = a.F[l0 + e];
+                const int pos = a.relpos[rp + e];
+                const T prod = lv * u;
+                x[pos] = x[pos] - prod;
+            }
+            rp += nl;
+            if (kLds) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+        t0 += nready;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
+    __shared__ T lds[(kCoopBlock / 64) * kRefactorLds];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T *xs = lds + wid * kRefactorLds;
+    (void)wid;
+    // Columns are handed out in dependency-level order, a chunk at a time, to running
+    // wavefronts only: the earliest unfinished column is always held by a running wave
+    // whose earlier work is done, so the kernel finishes whatever the residency.
+    for (;;) {
+        const unsigned int c0w = grab(&a.ctl->work_refactor, a.chunk);
+        if ((int64_t)c0w >= a.n) break;
+        const int64_t cend = (int64_t)c0w + a.chunk < a.n ? (int64_t)c0w + a.chunk : a.n;
+        for (int64_t t = c0w; t < cend; ++t) {
+        const int j = a.order[t];
+        const int64_t c0 = a.fp[j];
+        const int len = (int)(a.fp[j + 1] - c0);
+        const int nu = a.fdiag[j];
+        const bool in_lds = len <= kRefactorLds;
+        T cm = 0;
+        for (int e = lane; e < len; e += 64) {
+            const T v = a.F[c0 + e];
+            if (in_lds) xs[e] = v;
+            cm = fmax(cm, fabs(v));
+        }
+        cm = wave_max(cm);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (in_lds) refactor_chain<T, true>(a, j, c0, nu, xs);
+        else refactor_chain<T, false>(a, j, c0, nu, a.F + c0);
+        const T *x = in_lds ? xs : a.F + c0;
+        T d = x[nu];
+        const T ur = unit_roundoff<T>();
+        const T cmx = cm > T(0) ? cm : T(1);
+        if (!(fabs(d) > ur * cmx) || !isfinite(d)) {
+            d = (d < T(0) ? T(-1) : T(1)) * ur * cmx;
+            if (lane == 0) {
+                atomicAdd(&a.ctl->nguard, 1ull);
+                if (a.guard_fail_policy) atomicOr(&a.ctl->guard_fail, 1u);
+            }
+        }
+        for (int e = lane; e < len; e += 64) {
+            T v = x[e];
+            if (e == nu) v = d;
+            else if (e > nu) v = v / d;
+            a.F[c0 + e] = v;
+            a.Tv[a.f2t[c0 + e]] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // column j visible before its flag
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) __hip_atomic_store(a.flag + j, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// triangular solves in solve layout (step space), rows in level order
+// ---------------------------------------------------------------------------------------
+
+template <typename T> struct TrsvArgs {
+    int64_t ntasks;
+    const int32_t *task;   // task boundaries into rows
+    const int8_t *tlog;    // log2 of lanes per row of each task
+    const int32_t *rows;
+    const int64_t *rp;
+    const int32_t *ci;
+    const T *val;
+    const T *diag;         // upper only
+    const double *rhs64;   // lower: right-hand side in original order (gathered by prow)
+    const int32_t *prow;   // lower: pivot rows
+    const T *rhs_step;     // upper: L-solve result (step order)
+    T *out;                // step-order result; sentinel on entry
+    double *xout;          // upper: solution scattered to original order by q
+    const int32_t *q;
+    const Control *stopflag;  // when non-null, skip if the FGMRES cycle has stopped
+    unsigned int *work;       // task counter (zeroed before the launch)
+    unsigned int *hang;
+    unsigned int chunk;       // tasks taken per grab
+};
+
+template <typename T, bool kLower>
+__global__ void __launch_bounds__(kCoopBlock) k_trsv(TrsvArgs<T> a) {
+    if (a.stopflag && a.stopflag->stop) return;
+    const int lane = threadIdx.x & 63;
+    // tasks in level order, handed to running wavefronts only (see k_refactor)
+    for (;;) {
+      const unsigned int t0w = grab(a.work, a.chunk);
+      if ((int64_t)t0w >= a.ntasks) break;
+      const int64_t tend = (int64_t)t0w + a.chunk < a.ntasks ? (int64_t)t0w + a.chunk : a.ntasks;
+      for (int64_t t = t0w; t < tend; ++t) {
+        const int lg = a.tlog[t];
+        const int g = 1 << lg;
+        const int grp = lane >> lg, sub = lane & (g - 1);
+        const int idx = a.task[t] + grp;
+        const bool active = idx < a.task[t + 1];
+        const int i = active ? a.rows[idx] : 0;
+        T acc = 0;
+        if (active) {
+            for (int64_t p = a.rp[i] + sub; p < a.rp[i + 1]; p += g) {
+                const T xk = load_ready(a.out + a.ci[p], a.hang);
+                const T prod = a.val[p] * xk;
+                acc = acc + prod;
+            }
+        }
+        for (int o = 1; o < g; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
+        if (active && sub == 0) {
+            T r;
+            if (kLower) r = (T)a.rhs64[a.prow[i]] - acc;
+            else r = (a.rhs_step[i] - acc) / a.diag[i];
+            store_ready(a.out + i, r);
+            if (!kLower) a.xout[a.q[i]] = (double)r;
+        }
+      }
+    }
+}
+
+template <typename T>
+__global__ void k_fill_sentinel(int64_t n, T *a, T *b, Control *ctl) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->work_lower = 0;
+        ctl->work_upper = 0;
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        a[i] = sentinel<T>();
+        b[i] = sentinel<T>();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Krylov kernels (FP64).  Streaming grid: G blocks of kStreamBlock threads, block b owns a
+// contiguous chunk of rows; partial sums go to part[b * kPartStride + t] and the last block
+// to arrive reduces them in block order (deterministic).
+// ---------------------------------------------------------------------------------------
+
+constexpr int kPartStride = kRestartMax + 4;
+
+struct KrylovArgs {
+    int64_t n;
+    const int64_t *rp;
+    const int32_t *ci;
+    const double *kval;
+    double *V;        // (R+1) columns of n
+    double *Z;        // R columns of n
+    double *w;
+    double *part;
+    Control *ctl;
+};
+
+// w = K z_j; partial dots V_t . w (t <= j) and w . w
+__global__ void __launch_bounds__(kStreamBlock) k_spmv_dots(KrylovArgs a, int j) {
+    __shared__ double red[kStreamBlock / 64];
+    if (a.ctl->stop) return;
+    int64_t r0, r1;
+    block_rows(a.n, r0, r1);
+    const double *z = a.Z + (int64_t)j * a.n;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        double s = 0.0;
+        for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+            const double prod = a.kval[p] * z[a.ci[p]];
+            s = s + prod;
+        }
+        a.w[i] = s;
+    }
+    __syncthreads();
+    for (int t = 0; t <= j + 1; ++t) {
+        const double *v = t <= j ? a.V + (int64_t)t * a.n : a.w;
+        double s = 0.0;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) s += v[i] * a.w[i];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * kPartStride + t] = s;
+    }
+    if (last_block(&a.ctl->counter)) {
+        for (int t = threadIdx.x; t <= j + 1; t += blockDim.x) {
+            double s = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) s += a.part[(int64_t)b * kPartStride + t];
+            if (t <= j) a.ctl->h1[t] = s;
+            else a.ctl->wnorm_in = sqrt(s);
+        }
+        if (threadIdx.x == 0) a.ctl->counter = 0;
+    }
+}
+
+// w -= V h1; partial dots V_t . w for the second Gram-Schmidt pass
+__global__ void __launch_bounds__(kStreamBlock) k_cgs_pass2(KrylovArgs a, int j) {
+    __shared__ double red[kStreamBlock / 64];
+    __shared__ double h[kRestartMax + 1];
+    if (a.ctl->stop) return;
+    int64_t r0, r1;
+    block_rows(a.n, r0, r1);
+    for (int t = threadIdx.x; t <= j; t += blockDim.x) h[t] = a.ctl->h1[t];
+    __syncthreads();
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        double s = a.w[i];
+        for (int t = 0; t <= j; ++t) {
+            const double prod = a.V[(int64_t)t * a.n + i] * h[t];
+            s = s - prod;
+        }
+        a.w[i] = s;
+    }
+    __syncthreads();
+    for (int t = 0; t <= j; ++t) {
+        const double *v = a.V + (int64_t)t * a.n;
+        double s = 0.0;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) s += v[i] * a.w[i];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * kPartStride + t] = s;
+    }
+    if (last_block(&a.ctl->counter)) {
+        for (int t = threadIdx.x; t <= j; t += blockDim.x) {
+            double s = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) s += a.part[(int64_t)b * kPartStride + t];
+            a.ctl->h2[t] = s;
+        }
+        if (threadIdx.x == 0) a.ctl->counter = 0;
+    }
+}
+
+// w -= V h2; ||w||; then (last block) Hessenberg column, Givens rotations, estimate, stop
+__global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j, int restart) {
+    __shared__ double red[kStreamBlock / 64];
+    __shared__ double h[kRestartMax + 1];
+    if (a.ctl->stop) return;
+    int64_t r0, r1;
+    block_rows(a.n, r0, r1);
+    for (int t = threadIdx.x; t <= j; t += blockDim.x) h[t] = a.ctl->h2[t];
+    __syncthreads();
+    double ss = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        double s = a.w[i];
+        for (int t = 0; t <= j; ++t) {
+            const double prod = a.V[(int64_t)t * a.n + i] * h[t];
+            s = s - prod;
+        }
+        a.w[i] = s;
+        ss += s * s;
+    }
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * kPartStride] = ss;
+    if (last_block(&a.ctl->counter) && threadIdx.x == 0) {
+        Control *c = a.ctl;
+        double s = 0.0;
+        for (unsigned b = 0; b < gridDim.x; ++b) s += a.part[(int64_t)b * kPartStride];
+        const double hn = sqrt(s);
+        double col[kRestartMax + 1];
+        for (int t = 0; t <= j; ++t) col[t] = c->h1[t] + c->h2[t];
+        col[j + 1] = hn;
+        for (int t = 0; t < j; ++t) {
+            const double x0 = col[t], x1 = col[t + 1];
+            col[t] = c->cs[t] * x0 + c->sn[t] * x1;
+            col[t + 1] = -c->sn[t] * x0 + c->cs[t] * x1;
+        }
+        const double rr = hypot(col[j], col[j + 1]);
+        double cs = 1.0, sn = 0.0;
+        if (rr != 0.0) {
+            cs = col[j] / rr;
+            sn = col[j + 1] / rr;
+        }
+        c->cs[j] = cs;
+        c->sn[j] = sn;
+        col[j] = rr;
+        const double gj = c->g[j];
+        c->g[j + 1] = -sn * gj;
+        c->g[j] = cs * gj;
+        for (int t = 0; t <= j; ++t) c->H[j * (kRestartMax + 1) + t] = col[t];
+        c->hn = hn;
+        c->est = fabs(c->g[j + 1]);
+        c->jdone = j + 1;
+        const int brk = !(hn > 1e-14 * c->wnorm_in);
+        c->breakdown = brk;
+        if (c->est <= c->inner_tol || brk || j + 1 >= restart) c->stop = 1;
+        c->counter = 0;
+    }
+}
+
+// v_{j+1} = w / ||w|| (skipped after a breakdown); re-arm the solve sentinels
+template <typename T>
+__global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j, T *s1, T *s2) {
+    const Control *c = a.ctl;
+    if (c->jdone != j + 1) return;  // the cycle ended before step j
+    const bool write_v = !c->breakdown;
+    const bool rearm = !c->stop;
+    if (!write_v && !rearm) return;
+    const double hn = c->hn;
+    double *v = a.V + (int64_t)(j + 1) * a.n;
+    if (rearm && blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctl->work_lower = 0;
+        a.ctl->work_upper = 0;
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        if (write_v) v[i] = a.w[i] / hn;
+        if (rearm) {
+            s1[i] = sentinel<T>();
+            s2[i] = sentinel<T>();
+        }
+    }
+}
+
+// rho = b - K x; partial ||rho||^2, ||x||^2, ||b||^2
+__global__ void __launch_bounds__(kStreamBlock) k_resid(KrylovArgs a, const double *b, const double *x, double *r) {
+    __shared__ double red[kStreamBlock / 64];
+    int64_t r0, r1;
+    block_rows(a.n, r0, r1);
+    double sr = 0.0, sx = 0.0, sb = 0.0;
+    int badb = 0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        double s = 0.0;
+        for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+            const double prod = a.kval[p] * x[a.ci[p]];
+            s = s + prod;
+        }
+        const double bi = b[i];
+        const double ri = bi - s;
+        r[i] = ri;
+        sr += ri * ri;
+        sx += x[i] * x[i];
+        sb += bi * bi;
+        badb |= !isfinite(bi);
+    }
+    sr = block_sum(sr, red);
+    sx = block_sum(sx, red);
+    sb = block_sum(sb, red);
+    if (threadIdx.x == 0) {
+        double *p = a.part + (int64_t)blockIdx.x * kPartStride;
+        p[0] = sr;
+        p[1] = sx;
+        p[2] = sb;
+    }
+    if (badb) a.ctl->nonfinite_b = 1;
+    if (last_block(&a.ctl->counter) && threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (unsigned bb = 0; bb < gridDim.x; ++bb) {
+            const double *p = a.part + (int64_t)bb * kPartStride;
+            s0 += p[0];
+            s1 += p[1];
+            s2 += p[2];
+        }
+        a.ctl->rnorm2 = s0;
+        a.ctl->xnorm2 = s1;
+        a.ctl->bnorm2 = s2;
+        a.ctl->counter = 0;
+    }
+}
+
+// Start of a cycle: v_0 = rho / ||rho||, g = (beta, 0, ...), re-arm sentinels
+template <typename T>
+__global__ void __launch_bounds__(kStreamBlock) k_cycle_start(KrylovArgs a, const double *r, double inner_tol,
+                                                              T *s1, T *s2) {
+    const double beta = sqrt(a.ctl->rnorm2);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        a.V[i] = r[i] / beta;
+        s1[i] = sentinel<T>();
+        s2[i] = sentinel<T>();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Control *c = a.ctl;
+        c->work_lower = 0;
+        c->work_upper = 0;
+        c->beta = beta;
+        c->inner_tol = inner_tol;
+        c->stop = 0;
+        c->jdone = 0;
+        c->breakdown = 0;
+        c->est = beta;
+        for (int t = 0; t <= kRestartMax; ++t) c->g[t] = 0.0;
+        c->g[0] = beta;
+    }
+}
+
+// y = H^-1 g (jdone x jdone upper triangular), one thread
+__global__ void k_lsq(Control *c) {
+    if (threadIdx.x != 0) return;
+    const int m = c->jdone;
+    for (int t = m - 1; t >= 0; --t) {
+        double s = c->g[t];
+        for (int u = t + 1; u < m; ++u) {
+            const double prod = c->H[u * (kRestartMax + 1) + t] * c->y[u];
+            s = s - prod;
+        }
+        const double dgn = c->H[t * (kRestartMax + 1) + t];
+        c->y[t] = dgn != 0.0 ? s / dgn : 0.0;
+    }
+}
+
+// x += Z y
+__global__ void __launch_bounds__(kStreamBlock) k_xupdate(KrylovArgs a, double *x) {
+    __shared__ double y[kRestartMax];
+    const int m = a.ctl->jdone;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) y[t] = a.ctl->y[t];
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        double s = x[i];
+        for (int t = 0; t < m; ++t) {
+            const double prod = a.Z[(int64_t)t * a.n + i] * y[t];
+            s = s + prod;
+        }
+        x[i] = s;
+    }
+}
+
+__global__ void k_copy(int64_t n, const double *src, double *dst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ void k_widen(int64_t n, const float *src, double *dst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (double)src[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct DevLayout {
+    // structure
+    int64_t *fp;
+    int32_t *fi, *fdiag, *order, *f2t;
+    int64_t *relptr, *fsrc;
+    int32_t *relpos;
+    int64_t *lrp, *urp, *krp;
+    int32_t *lci, *uci, *kci;
+    int32_t *l_rows, *l_task, *u_rows, *u_task, *prow, *q;
+    int8_t *l_tlog, *u_tlog;
+    // values
+    double *kval, *F64, *T64;
+    float *F32, *T32;
+    unsigned int *flag;
+    // vectors
+    double *V, *Z, *w, *r, *y64, *z64;
+    float *y32, *z32;
+    double *part;
+    Control *ctl;
+};
+
+}  // namespace
+
+}  // namespace kkt
+
+struct kkt_handle_s {
+    kkt_opts_t opts{};
+    kkt::Analysis an;
+    std::string err;
+    // schedule extras
+    std::vector<int8_t> l_tlog, u_tlog;
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int device = -1;
+    kkt::DevLayout d{};
+    bool bound = false;
+    bool device_failed = false;
+    bool have_factors = false;
+    int factor_precision = 0;
+    unsigned int epoch = 0;
+    int grid_refactor64 = 0, grid_refactor32 = 0, grid_trsv64 = 0, grid_trsv32 = 0, grid_stream = 0;
+    kkt::ControlSummary *host_ctl = nullptr;  // pinned
+    int restart_alloc = 0;
+};
+
+using kkt::Analysis;
+
+namespace kkt {
+namespace {
+
+kkt_status_t fail(kkt_handle_t h, kkt_status_t s, const std::string &m) {
+    if (h) h->err = m;
+    g_last_error = m;
+    return s;
+}
+
+#define KKT_HIP(h, call)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            (h)->device_failed = true;                                                          \
+            return fail((h), KKT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+        }                                                                                       \
+    } while (0)
+
+// Lanes per row for the rows of one task: enough lanes that a lane handles about four
+// entries of the longest row, at most 64.
+void task_lanes(const std::vector<int64_t> &rp, const std::vector<int32_t> &rows,
+                const std::vector<int32_t> &task, std::vector<int8_t> &tlog) {
+    // retile: tasks are cut so that (rows in task) * lanes <= 64
+    tlog.assign(task.size() - 1, 0);
+    for (size_t t = 0; t + 1 < task.size(); ++t) {
+        int64_t mx = 0;
+        for (int32_t k = task[t]; k < task[t + 1]; ++k) mx = std::max(mx, rp[rows[k] + 1] - rp[rows[k]]);
+        int lg = 0;
+        while ((1 << lg) < 64 && (int64_t)(1 << lg) * 4 < mx) ++lg;
+        tlog[t] = (int8_t)lg;
+    }
+}
+
+// Split tasks so that rows * lanes <= 64 in every task.
+void retile(const std::vector<int64_t> &rp, const std::vector<int32_t> &rows, std::vector<int32_t> &task,
+            std::vector<int8_t> &tlog) {
+    std::vector<int8_t> lg0;
+    task_lanes(rp, rows, task, lg0);
+    std::vector<int32_t> nt{0};
+    std::vector<int8_t> nl;
+    for (size_t t = 0; t + 1 < task.size(); ++t) {
+        const int per = 64 >> lg0[t];
+        for (int32_t s = task[t]; s < task[t + 1]; s += per) {
+            nt.push_back(std::min(s + per, task[t + 1]));
+            nl.push_back(lg0[t]);
+        }
+    }
+    task.swap(nt);
+    tlog.swap(nl);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Planner {
+    size_t off = 0;
+    template <typename T> size_t take(size_t count) {
+        const size_t o = off;
+        off = align256(off + std::max<size_t>(count, 1) * sizeof(T));
+        return o;
+    }
+};
+
+// Offsets of every array inside the workspace (also gives the total size).
+struct Offsets {
+    size_t fp, fi, fdiag, order, f2t, relptr, fsrc, relpos, lrp, urp, krp, lci, uci, kci, l_rows, l_task,
+        u_rows, u_task, prow, q, l_tlog, u_tlog, kval, F64, T64, F32, T32, flag, V, Z, w, r, y64, z64, y32,
+        z32, part, ctl, total;
+};
+
+Offsets plan(const kkt_handle_t h) {
+    const Analysis &a = h->an;
+    const int64_t n = a.n, f = a.nnz_f();
+    const int R = h->opts.restart;
+    Planner p;
+    Offsets o{};
+    o.fp = p.take<int64_t>(n + 1);
+    o.fi = p.take<int32_t>(f);
+    o.fdiag = p.take<int32_t>(n);
+    o.order = p.take<int32_t>(n);
+    o.f2t = p.take<int32_t>(f);
+    o.relptr = p.take<int64_t>(n + 1);
+    o.fsrc = p.take<int64_t>(f);
+    o.relpos = p.take<int32_t>(a.relpos.size());
+    o.lrp = p.take<int64_t>(n + 1);
+    o.urp = p.take<int64_t>(n + 1);
+    o.krp = p.take<int64_t>(n + 1);
+    o.lci = p.take<int32_t>(a.lci.size());
+    o.uci = p.take<int32_t>(a.uci.size());
+    o.kci = p.take<int32_t>(a.nnz);
+    o.l_rows = p.take<int32_t>(n);
+    o.l_task = p.take<int32_t>(a.l_task.size());
+    o.u_rows = p.take<int32_t>(n);
+    o.u_task = p.take<int32_t>(a.u_task.size());
+    o.prow = p.take<int32_t>(n);
+    o.q = p.take<int32_t>(n);
+    o.l_tlog = p.take<int8_t>(h->l_tlog.size());
+    o.u_tlog = p.take<int8_t>(h->u_tlog.size());
+    o.kval = p.take<double>(a.nnz);
+    o.F64 = p.take<double>(f);
+    o.T64 = p.take<double>(f);
+    o.F32 = p.take<float>(f);
+    o.T32 = p.take<float>(f);
+    o.flag = p.take<unsigned int>(n);
+    o.V = p.take<double>((size_t)(R + 1) * n);
+    o.Z = p.take<double>((size_t)R * n);
+    o.w = p.take<double>(n);
+    o.r = p.take<double>(n);
+    o.y64 = p.take<double>(n);
+    o.z64 = p.take<double>(n);
+    o.y32 = p.take<float>(n);
+    o.z32 = p.take<float>(n);
+    o.part = p.take<double>((size_t)kStreamGridMax * kPartStride);
+    o.ctl = p.take<Control>(1);
+    o.total = p.off;
+    return o;
+}
+
+template <typename T> hipError_t up(char *base, size_t off, const std::vector<T> &v, hipStream_t s) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+int coop_grid(const void *func, int device) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kCoopBlock, 0) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+template <typename T> KrylovArgs kargs(kkt_handle_t h) {
+    KrylovArgs k;
+    k.n = h->an.n;
+    k.rp = h->d.krp;
+    k.ci = h->d.kci;
+    k.kval = h->d.kval;
+    k.V = h->d.V;
+    k.Z = h->d.Z;
+    k.w = h->d.w;
+    k.part = h->d.part;
+    k.ctl = h->d.ctl;
+    return k;
+}
+
+int stream_blocks(int64_t n) {
+    int64_t b = (n + kStreamBlock - 1) / kStreamBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, kStreamGridMax));
+}
+
+unsigned int work_chunk(int64_t items, int waves) {
+    // about four grabs per wavefront, at most 16 items per grab
+    const int64_t c = items / (4 * (int64_t)std::max(waves, 1));
+    return (unsigned int)std::max<int64_t>(1, std::min<int64_t>(16, c));
+}
+
+template <typename T>
+hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T *rhs_step, T *out, double *xout,
+                       const Control *stopflag, hipStream_t s) {
+    const Analysis &a = h->an;
+    TrsvArgs<T> t{};
+    const bool is64 = sizeof(T) == 8;
+    if (lower) {
+        t.ntasks = (int64_t)a.l_task.size() - 1;
+        t.task = h->d.l_task;
+        t.tlog = h->d.l_tlog;
+        t.rows = h->d.l_rows;
+        t.rp = h->d.lrp;
+        t.ci = h->d.lci;
+        t.val = (const T *)(is64 ? (void *)h->d.T64 : (void *)h->d.T32);
+        t.rhs64 = rhs64;
+        t.prow = h->d.prow;
+    } else {
+        t.ntasks = (int64_t)a.u_task.size() - 1;
+        t.task = h->d.u_task;
+        t.tlog = h->d.u_tlog;
+        t.rows = h->d.u_rows;
+        t.rp = h->d.urp;
+        t.ci = h->d.uci;
+        const T *base = (const T *)(is64 ? (void *)h->d.T64 : (void *)h->d.T32);
+        t.val = base + a.lrp[a.n];
+        t.diag = base + a.lrp[a.n] + a.urp[a.n];
+        t.rhs_step = rhs_step;
+        t.xout = xout;
+        t.q = h->d.q;
+    }
+    t.out = out;
+    t.stopflag = stopflag;
+    t.work = lower ? &h->d.ctl->work_lower : &h->d.ctl->work_upper;
+    t.hang = &h->d.ctl->hang;
+    const int grid = is64 ? h->grid_trsv64 : h->grid_trsv32;
+    t.chunk = work_chunk(t.ntasks, grid * (kCoopBlock / 64));
+    if (lower) k_trsv<T, true><<<grid, kCoopBlock, 0, s>>>(t);
+    else k_trsv<T, false><<<grid, kCoopBlock, 0, s>>>(t);
+    return hipGetLastError();
+}
+
+// x = Q U^-1 L^-1 P b with the current factors of precision T; sentinels re-armed first.
+template <typename T>
+hipError_t precond(kkt_handle_t h, const double *b, double *x, const Control *ctl, hipStream_t s) {
+    T *y = (T *)(sizeof(T) == 8 ? (void *)h->d.y64 : (void *)h->d.y32);
+    T *z = (T *)(sizeof(T) == 8 ? (void *)h->d.z64 : (void *)h->d.z32);
+    hipError_t e = launch_trsv<T>(h, true, b, nullptr, y, nullptr, ctl, s);
+    if (e != hipSuccess) return e;
+    return launch_trsv<T>(h, false, nullptr, y, z, x, ctl, s);
+}
+
+template <typename T> void rearm(kkt_handle_t h, hipStream_t s) {
+    T *y = (T *)(sizeof(T) == 8 ? (void *)h->d.y64 : (void *)h->d.y32);
+    T *z = (T *)(sizeof(T) == 8 ? (void *)h->d.z64 : (void *)h->d.z32);
+    k_fill_sentinel<T><<<h->grid_stream, kStreamBlock, 0, s>>>(h->an.n, y, z, h->d.ctl);
+}
+
+kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precision, hipStream_t s) {
+    const Analysis &a = h->an;
+    const int64_t f = a.nnz_f();
+    DevLayout &d = h->d;
+    k_prep_refactor<<<1, 1, 0, s>>>(d.ctl);
+    k_ingest<<<2048, 256, 0, s>>>(a.nnz, dev_values, d.kval, f, d.fsrc, d.F64, d.F32, precision, d.ctl);
+    k_rownorm<<<std::max<int64_t>(1, std::min<int64_t>((a.n + 255) / 256, 2048)), 256, 0, s>>>(a.n, d.krp, d.kval,
+                                                                                             d.ctl);
+    KKT_HIP(h, hipGetLastError());
+    h->epoch += 1;
+    if (h->epoch == 0) h->epoch = 1;
+    if (precision == KKT_PREC_MIXED) {
+        const unsigned int chunk = work_chunk(a.n, h->grid_refactor32 * (kCoopBlock / 64));
+        RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F32, d.T32,
+                              d.flag, h->epoch, chunk, h->opts.guard_policy, d.ctl};
+        k_refactor<float><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r);
+    } else {
+        const unsigned int chunk = work_chunk(a.n, h->grid_refactor64 * (kCoopBlock / 64));
+        RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F64, d.T64,
+                               d.flag, h->epoch, chunk, h->opts.guard_policy, d.ctl};
+        k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r);
+    }
+    KKT_HIP(h, hipGetLastError());
+    h->have_factors = true;
+    h->factor_precision = precision;
+    return KKT_OK;
+}
+
+kkt_status_t read_ctl(kkt_handle_t h, hipStream_t s) {
+    KKT_HIP(h, hipMemcpyAsync(h->host_ctl, h->d.ctl, sizeof(ControlSummary), hipMemcpyDeviceToHost, s));
+    KKT_HIP(h, hipStreamSynchronize(s));
+    return KKT_OK;
+}
+
+// One FGMRES-IR solve with the factors currently in the workspace.
+template <typename T>
+kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, kkt_solve_info_t *info,
+                        hipStream_t s) {
+    const Analysis &a = h->an;
+    DevLayout &d = h->d;
+    const int R = h->opts.restart;
+    const int G = h->grid_stream;
+    KrylovArgs ka = kargs<T>(h);
+    T *y = (T *)(sizeof(T) == 8 ? (void *)d.y64 : (void *)d.y32);
+    T *z = (T *)(sizeof(T) == 8 ? (void *)d.z64 : (void *)d.z32);
+    // x0 = M^-1 b, residual and norms
+    k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
+    rearm<T>(h, s);
+    KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
+    k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+    KKT_HIP(h, hipGetLastError());
+    kkt_status_t st = read_ctl(h, s);
+    if (st != KKT_OK) return st;
+    const ControlSummary &c = *h->host_ctl;
+    if (c.hang) {
+        h->device_failed = true;
+        return fail(h, KKT_EDEVICE, "a dependency wait exceeded its spin limit");
+    }
+    if (c.nonfinite) return fail(h, KKT_EINVAL, "non-finite value in the matrix of the last refactorization");
+    if (c.nonfinite_b) return fail(h, KKT_EINVAL, "non-finite value in the right-hand side");
+    if (c.guard_fail) return fail(h, KKT_ESINGULAR, "tiny static pivot under the FAIL guard policy");
+    double knorm;
+    {
+        unsigned long long bits = c.knorm_bits;
+        std::memcpy(&knorm, &bits, sizeof(knorm));
+    }
+    const double bn = std::sqrt(c.bnorm2);
+    const double rho0 = std::sqrt(c.rnorm2);
+    double rn = rho0;
+    double nrbe = rn / (knorm * std::sqrt(c.xnorm2) + bn);
+    kkt_solve_info_t inf{};
+    inf.precision = sizeof(T) == 8 ? KKT_PREC_FP64 : KKT_PREC_MIXED;
+    inf.pivots_perturbed = (int64_t)c.nguard;
+    inf.knorm_inf = knorm;
+    inf.nrbe0 = nrbe;
+    const bool paper = h->opts.stop_mode == KKT_STOP_PAPER;
+    const double target = h->opts.nrbe_target;
+    auto accept = [&](double est_pass) { return (paper ? est_pass : true) && nrbe <= target; };
+    bool converged;
+    if (bn == 0.0) converged = true;
+    else converged = paper ? (rn / bn < tol && nrbe <= target) : nrbe <= target;
+    inf.refined = !converged;
+    int iters = 0, cycles = 0;
+    double est = rn;
+    while (!converged && cycles <= h->opts.max_restarts) {
+        ++cycles;
+        if (!(rn > 0.0)) {
+            converged = true;
+            break;
+        }
+        const double xn = std::sqrt(h->host_ctl->xnorm2);
+        const double inner = paper ? tol * rho0 : target * (knorm * xn + bn);
+        k_cycle_start<T><<<G, kStreamBlock, 0, s>>>(ka, d.r, inner, y, z);
+        for (int j = 0; j < R; ++j) {
+            KKT_HIP(h, precond<T>(h, d.V + (int64_t)j * a.n, d.Z + (int64_t)j * a.n, d.ctl, s));
+            k_spmv_dots<<<G, kStreamBlock, 0, s>>>(ka, j);
+            k_cgs_pass2<<<G, kStreamBlock, 0, s>>>(ka, j);
+            k_cgs_finish<<<G, kStreamBlock, 0, s>>>(ka, j, R);
+            k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, y, z);
+        }
+        k_lsq<<<1, 64, 0, s>>>(d.ctl);
+        k_xupdate<<<G, kStreamBlock, 0, s>>>(ka, x);
+        k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+        KKT_HIP(h, hipGetLastError());
+        st = read_ctl(h, s);
+        if (st != KKT_OK) return st;
+        if (h->host_ctl->hang) {
+            h->device_failed = true;
+            return fail(h, KKT_EDEVICE, "a dependency wait exceeded its spin limit");
+        }
+        iters += h->host_ctl->jdone;
+        est = h->host_ctl->est;
+        rn = std::sqrt(h->host_ctl->rnorm2);
+        nrbe = rn / (knorm * std::sqrt(h->host_ctl->xnorm2) + bn);
+        converged = accept(est < tol * rho0);
+    }
+    inf.converged = converged;
+    inf.iterations = iters;
+    inf.cycles = cycles;
+    inf.nrbe = nrbe;
+    inf.rel_resid = bn > 0.0 ? rn / bn : 0.0;
+    inf.rr = rho0 > 0.0 ? rn / rho0 : 0.0;
+    inf.est_resid = est;
+    inf.true_resid = rn;
+    if (info) *info = inf;
+    return converged ? KKT_OK : KKT_ENOCONV;
+}
+
+}  // namespace
+}  // namespace kkt
+
+// ---------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------
+
+using namespace kkt;
+
+extern "C" {
+
+void kkt_opts_default(kkt_opts_t *o) {
+    if (!o) return;
+    o->nd_leaf = 64;
+    o->pivot_tau = 0.1;
+    o->restart = 10;
+    o->max_restarts = 20;
+    o->delta_tol = 1e-14;
+    o->nrbe_target = 1e-12;
+    o->precision = KKT_PREC_FP64;
+    o->guard_policy = KKT_GUARD_PERTURB;
+    o->stop_mode = KKT_STOP_PAPER;
+    o->mixed_fallback = 1;
+}
+
+kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowptr, const int32_t *colidx,
+                         const double *values_first, kkt_handle_t *out) {
+    if (!out) return fail(nullptr, KKT_EINVAL, "null output handle");
+    *out = nullptr;
+    kkt_handle_t h = new (std::nothrow) kkt_handle_s();
+    if (!h) return fail(nullptr, KKT_ENOMEM, "out of host memory");
+    if (opts) h->opts = *opts;
+    else kkt_opts_default(&h->opts);
+    if (h->opts.restart < 1 || h->opts.restart > kRestartMax) {
+        delete h;
+        return fail(nullptr, KKT_EINVAL, "restart must be in 1..64");
+    }
+    AnalysisOptions ao;
+    ao.nd_leaf = h->opts.nd_leaf;
+    ao.pivot_tau = h->opts.pivot_tau;
+    std::string msg;
+    int rc = analyze(ao, n, rowptr, colidx, values_first, h->an, &msg);
+    if (rc != AN_OK) {
+        delete h;
+        const kkt_status_t s = rc == AN_EINVAL ? KKT_EINVAL : rc == AN_ESINGULAR ? KKT_ESINGULAR : KKT_ENOMEM;
+        return fail(nullptr, s, msg);
+    }
+    try {
+        retile(h->an.lrp, h->an.l_rows, h->an.l_task, h->l_tlog);
+        retile(h->an.urp, h->an.u_rows, h->an.u_task, h->u_tlog);
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return fail(nullptr, KKT_ENOMEM, "out of host memory");
+    }
+    *out = h;
+    return KKT_OK;
+}
+
+kkt_status_t kkt_get_analysis_info(kkt_handle_t h, kkt_analysis_info_t *info) {
+    if (!h || !info) return fail(h, KKT_EINVAL, "null argument");
+    const Analysis &a = h->an;
+    info->n = a.n;
+    info->nnz = a.nnz;
+    info->nnz_l = a.nnz_l();
+    info->nnz_u = a.nnz_u();
+    info->offdiag_pivots = a.offdiag_pivots;
+    info->levels_refactor = a.levels_refactor;
+    info->levels_l = a.levels_l;
+    info->levels_u = a.levels_u;
+    info->updates = a.updates();
+    info->analysis_seconds = a.seconds;
+    return KKT_OK;
+}
+
+kkt_status_t kkt_get_permutations(kkt_handle_t h, int32_t *prow, int32_t *q) {
+    if (!h) return fail(h, KKT_EINVAL, "null handle");
+    if (prow) std::memcpy(prow, h->an.prow.data(), h->an.n * sizeof(int32_t));
+    if (q) std::memcpy(q, h->an.q.data(), h->an.n * sizeof(int32_t));
+    return KKT_OK;
+}
+
+kkt_status_t kkt_get_factor_pattern(kkt_handle_t h, int64_t *lp, int32_t *li, int64_t *up, int32_t *ui) {
+    if (!h) return fail(h, KKT_EINVAL, "null handle");
+    const Analysis &a = h->an;
+    if (lp) std::memcpy(lp, a.lp.data(), a.lp.size() * sizeof(int64_t));
+    if (li) std::memcpy(li, a.li.data(), a.li.size() * sizeof(int32_t));
+    if (up) std::memcpy(up, a.up.data(), a.up.size() * sizeof(int64_t));
+    if (ui) std::memcpy(ui, a.ui.data(), a.ui.size() * sizeof(int32_t));
+    return KKT_OK;
+}
+
+kkt_status_t kkt_get_analysis_values(kkt_handle_t h, double *lx, double *ux) {
+    if (!h) return fail(h, KKT_EINVAL, "null handle");
+    if (lx) std::memcpy(lx, h->an.lx.data(), h->an.lx.size() * sizeof(double));
+    if (ux) std::memcpy(ux, h->an.ux.data(), h->an.ux.size() * sizeof(double));
+    return KKT_OK;
+}
+
+kkt_status_t kkt_workspace_size(kkt_handle_t h, size_t *bytes) {
+    if (!h || !bytes) return fail(h, KKT_EINVAL, "null argument");
+    *bytes = plan(h).total;
+    return KKT_OK;
+}
+
+kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, void *stream) {
+    if (!h) return fail(h, KKT_EINVAL, "null handle");
+    if (h->device_failed) return fail(h, KKT_EDEVICE, "handle unusable after a device error");
+    const Offsets o = plan(h);
+    if (!dev_ptr || bytes < o.total) return fail(h, KKT_ENOMEM, "workspace too small");
+    if (((uintptr_t)dev_ptr & 255) != 0) return fail(h, KKT_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    KKT_HIP(h, hipGetDevice(&h->device));
+    if (!h->host_ctl) KKT_HIP(h, hipHostMalloc((void **)&h->host_ctl, sizeof(ControlSummary), hipHostMallocDefault));
+    char *b = (char *)dev_ptr;
+    DevLayout &d = h->d;
+    const Analysis &a = h->an;
+    d.fp = (int64_t *)(b + o.fp);
+    d.fi = (int32_t *)(b + o.fi);
+    d.fdiag = (int32_t *)(b + o.fdiag);
+    d.order = (int32_t *)(b + o.order);
+    d.f2t = (int32_t *)(b + o.f2t);
+    d.relptr = (int64_t *)(b + o.relptr);
+    d.fsrc = (int64_t *)(b + o.fsrc);
+    d.relpos = (int32_t *)(b + o.relpos);
+    d.lrp = (int64_t *)(b + o.lrp);
+    d.urp = (int64_t *)(b + o.urp);
+    d.krp = (int64_t *)(b + o.krp);
+    d.lci = (int32_t *)(b + o.lci);
+    d.uci = (int32_t *)(b + o.uci);
+    d.kci = (int32_t *)(b + o.kci);
+    d.l_rows = (int32_t *)(b + o.l_rows);
+    d.l_task = (int32_t *)(b + o.l_task);
+    d.u_rows = (int32_t *)(b + o.u_rows);
+    d.u_task = (int32_t *)(b + o.u_task);
+    d.prow = (int32_t *)(b + o.prow);
+    d.q = (int32_t *)(b + o.q);
+    d.l_tlog = (int8_t *)(b + o.l_tlog);
+    d.u_tlog = (int8_t *)(b + o.u_tlog);
+    d.kval = (double *)(b + o.kval);
+    d.F64 = (double *)(b + o.F64);
+    d.T64 = (double *)(b + o.T64);
+    d.F32 = (float *)(b + o.F32);
+    d.T32 = (float *)(b + o.T32);
+    d.flag = (unsigned int *)(b + o.flag);
+    d.V = (double *)(b + o.V);
+    d.Z = (double *)(b + o.Z);
+    d.w = (double *)(b + o.w);
+    d.r = (double *)(b + o.r);
+    d.y64 = (double *)(b + o.y64);
+    d.z64 = (double *)(b + o.z64);
+    d.y32 = (float *)(b + o.y32);
+    d.z32 = (float *)(b + o.z32);
+    d.part = (double *)(b + o.part);
+    d.ctl = (Control *)(b + o.ctl);
+    KKT_HIP(h, up(b, o.fp, a.fp, s));
+    KKT_HIP(h, up(b, o.fi, a.fi, s));
+    KKT_HIP(h, up(b, o.fdiag, a.fdiag, s));
+    KKT_HIP(h, up(b, o.order, a.col_order, s));
+    KKT_HIP(h, up(b, o.f2t, a.f2t, s));
+    KKT_HIP(h, up(b, o.relptr, a.relptr, s));
+    KKT_HIP(h, up(b, o.fsrc, a.fsrc, s));
+    KKT_HIP(h, up(b, o.relpos, a.relpos, s));
+    KKT_HIP(h, up(b, o.lrp, a.lrp, s));
+    KKT_HIP(h, up(b, o.urp, a.urp, s));
+    KKT_HIP(h, up(b, o.krp, a.rowptr, s));
+    KKT_HIP(h, up(b, o.lci, a.lci, s));
+    KKT_HIP(h, up(b, o.uci, a.uci, s));
+    KKT_HIP(h, up(b, o.kci, a.colidx, s));
+    KKT_HIP(h, up(b, o.l_rows, a.l_rows, s));
+    KKT_HIP(h, up(b, o.l_task, a.l_task, s));
+    KKT_HIP(h, up(b, o.u_rows, a.u_rows, s));
+    KKT_HIP(h, up(b, o.u_task, a.u_task, s));
+    KKT_HIP(h, up(b, o.prow, a.prow, s));
+    KKT_HIP(h, up(b, o.q, a.q, s));
+    KKT_HIP(h, up(b, o.l_tlog, h->l_tlog, s));
+    KKT_HIP(h, up(b, o.u_tlog, h->u_tlog, s));
+    KKT_HIP(h, hipMemsetAsync(d.flag, 0, a.n * sizeof(unsigned int), s));
+    KKT_HIP(h, hipMemsetAsync(d.ctl, 0, sizeof(Control), s));
+    KKT_HIP(h, hipMemsetAsync(d.part, 0, (size_t)kStreamGridMax * kPartStride * sizeof(double), s));
+    KKT_HIP(h, hipStreamSynchronize(s));
+    h->epoch = 0;
+    h->grid_refactor64 = coop_grid((const void *)k_refactor<double>, h->device);
+    h->grid_refactor32 = coop_grid((const void *)k_refactor<float>, h->device);
+    h->grid_trsv64 = std::min(coop_grid((const void *)k_trsv<double, true>, h->device),
+                              coop_grid((const void *)k_trsv<double, false>, h->device));
+    h->grid_trsv32 = std::min(coop_grid((const void *)k_trsv<float, true>, h->device),
+                              coop_grid((const void *)k_trsv<float, false>, h->device));
+    if (h->grid_refactor64 <= 0 || h->grid_refactor32 <= 0 || h->grid_trsv64 <= 0 || h->grid_trsv32 <= 0)
+        return fail(h, KKT_EDEVICE, "occupancy query failed");
+    h->grid_stream = stream_blocks(a.n);
+    h->ws = b;
+    h->ws_bytes = bytes;
+    h->bound = true;
+    h->have_factors = false;
+    return KKT_OK;
+}
+
+kkt_status_t kkt_refactor(kkt_handle_t h, const double *dev_values, void *stream) {
+    if (!h || !dev_values) return fail(h, KKT_EINVAL, "null argument");
+    if (h->device_failed) return fail(h, KKT_EDEVICE, "handle unusable after a device error");
+    if (!h->bound) return fail(h, KKT_ESTATE, "no workspace bound");
+    return refactor_impl(h, dev_values, h->opts.precision, (hipStream_t)stream);
+}
+
+kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, double tol, kkt_solve_info_t *info,
+                       void *stream) {
+    if (!h || !dev_b || !dev_x) return fail(h, KKT_EINVAL, "null argument");
+    if (dev_b == dev_x) return fail(h, KKT_EINVAL, "b and x must be distinct");
+    if (h->device_failed) return fail(h, KKT_EDEVICE, "handle unusable after a device error");
+    if (!h->bound || !h->have_factors) return fail(h, KKT_ESTATE, "refactor before solve");
+    if (tol <= 0.0) tol = h->opts.delta_tol;
+    hipStream_t s = (hipStream_t)stream;
+    if (h->factor_precision == KKT_PREC_MIXED) {
+        kkt_status_t st = solve_impl<float>(h, dev_b, dev_x, tol, info, s);
+        if (st != KKT_ENOCONV || !h->opts.mixed_fallback) return st;
+        // FP64 fallback: refactor the same values (already in the workspace) in FP64
+        const int64_t f = h->an.nnz_f();
+        k_prep_refactor<<<1, 1, 0, s>>>(h->d.ctl);
+        k_ingest<<<2048, 256, 0, s>>>(h->an.nnz, h->d.kval, nullptr, f, h->d.fsrc, h->d.F64, h->d.F32, 0,
+                                      h->d.ctl);
+        k_rownorm<<<std::max<int64_t>(1, std::min<int64_t>((h->an.n + 255) / 256, 2048)), 256, 0, s>>>(
+            h->an.n, h->d.krp, h->d.kval, h->d.ctl);
+        h->epoch += 1;
+        if (h->epoch == 0) h->epoch = 1;
+        const unsigned int chunk = work_chunk(h->an.n, h->grid_refactor64 * (kCoopBlock / 64));
+        RefactorArgs<double> r{h->an.n, h->d.fp, h->d.fi, h->d.fdiag, h->d.relptr, h->d.relpos, h->d.order,
+                               h->d.f2t, h->d.F64, h->d.T64, h->d.flag, h->epoch, chunk, h->opts.guard_policy,
+                               h->d.ctl};
+        k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r);
+        KKT_HIP(h, hipGetLastError());
+        h->factor_precision = KKT_PREC_FP64;
+        st = solve_impl<double>(h, dev_b, dev_x, tol, info, s);
+        if (info) info->fallback = 1;
+        h->factor_precision = KKT_PREC_MIXED;  // the next refactor starts in mixed again
+        return st;
+    }
+    return solve_impl<double>(h, dev_b, dev_x, tol, info, s);
+}
+
+kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x, void *stream) {
+    if (!h || !dev_b || !dev_x) return fail(h, KKT_EINVAL, "null argument");
+    if (h->device_failed) return fail(h, KKT_EDEVICE, "handle unusable after a device error");
+    if (!h->bound || !h->have_factors) return fail(h, KKT_ESTATE, "refactor before solve");
+    hipStream_t s = (hipStream_t)stream;
+    if (h->factor_precision == KKT_PREC_MIXED) {
+        rearm<float>(h, s);
+        KKT_HIP(h, precond<float>(h, dev_b, dev_x, nullptr, s));
+    } else {
+        rearm<double>(h, s);
+        KKT_HIP(h, precond<double>(h, dev_b, dev_x, nullptr, s));
+    }
+    return KKT_OK;
+}
+
+kkt_status_t kkt_get_factor_values(kkt_handle_t h, int32_t precision, double *lx, double *ux, void *stream) {
+    if (!h) return fail(h, KKT_EINVAL, "null handle");
+    if (!h->bound || !h->have_factors) return fail(h, KKT_ESTATE, "no factors");
+    hipStream_t s = (hipStream_t)stream;
+    const Analysis &a = h->an;
+    const int64_t f = a.nnz_f();
+    std::vector<double> F(f);
+    if (precision == 1) {
+        std::vector<float> F32(f);
+        KKT_HIP(h, hipMemcpyAsync(F32.data(), h->d.F32, f * sizeof(float), hipMemcpyDeviceToHost, s));
+        KKT_HIP(h, hipStreamSynchronize(s));
+        for (int64_t t = 0; t < f; ++t) F[t] = (double)F32[t];
+    } else {
+        KKT_HIP(h, hipMemcpyAsync(F.data(), h->d.F64, f * sizeof(double), hipMemcpyDeviceToHost, s));
+        KKT_HIP(h, hipStreamSynchronize(s));
+    }
+    if (lx)
+        for (int64_t p = 0; p < a.nnz_l(); ++p) lx[p] = F[a.l2f[p]];
+    if (ux)
+        for (int64_t p = 0; p < a.nnz_u(); ++p) ux[p] = F[a.u2f[p]];
+    return KKT_OK;
+}
+
+kkt_status_t kkt_release(kkt_handle_t h) {
+    if (!h) return KKT_OK;
+    if (h->host_ctl) (void)hipHostFree(h->host_ctl);
+    delete h;
+    return KKT_OK;
+}
+
+const char *kkt_last_error(kkt_handle_t h) {
+    if (h) return h->err.c_str();
+    return g_last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+"""Python binding of libkkt.so (include/kkt.h): argument marshalling only.
+
+Every step of the solver runs in the library (host analysis in C++, refactorization,
+triangular solves and FGMRES-IR in HIP kernels).  PyTorch supplies device memory and the
+stream; arrays cross the boundary as raw pointers.  If the library is missing this module
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import pathlib
+
+import numpy as np
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "libkkt.so"
+_lib = None
+
+KKT_OK, KKT_EINVAL, KKT_ENOMEM, KKT_ESINGULAR, KKT_ENOCONV, KKT_EDEVICE, KKT_ESTATE = range(7)
+PREC_FP64, PREC_MIXED = 0, 1
+GUARD_PERTURB, GUARD_FAIL = 0, 1
+STOP_PAPER, STOP_NRBE = 0, 1
+
+#: every entry point declared in include/kkt.h
+EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
+           "kkt_get_factor_pattern", "kkt_get_analysis_values", "kkt_workspace_size",
+           "kkt_bind_workspace", "kkt_refactor", "kkt_solve", "kkt_direct_solve",
+           "kkt_get_factor_values", "kkt_release", "kkt_last_error"]
+
+
+class Opts(C.Structure):
+    _fields_ = [("nd_leaf", C.c_int32), ("pivot_tau", C.c_double), ("restart", C.c_int32),
+                ("max_restarts", C.c_int32), ("delta_tol", C.c_double), ("nrbe_target", C.c_double),
+                ("precision", C.c_int32), ("guard_policy", C.c_int32), ("stop_mode", C.c_int32),
+                ("mixed_fallback", C.c_int32)]
+
+
+class AnalysisInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64),
+                ("offdiag_pivots", C.c_int64), ("levels_refactor", C.c_int64),
+                ("levels_l", C.c_int64), ("levels_u", C.c_int64), ("updates", C.c_int64),
+                ("analysis_seconds", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("converged", C.c_int32), ("iterations", C.c_int32), ("cycles", C.c_int32),
+                ("refined", C.c_int32), ("precision", C.c_int32), ("fallback", C.c_int32),
+                ("pivots_perturbed", C.c_int64), ("nrbe", C.c_double), ("nrbe0", C.c_double),
+                ("rel_resid", C.c_double), ("rr", C.c_double), ("est_resid", C.c_double),
+                ("true_resid", C.c_double), ("knorm_inf", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KKTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("kkt status %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libkkt.so (built by paper_2401_13926_amd.build); raises if it is absent."""
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            raise ImportError("libkkt.so is not built: run __graft_entry__.build() or "
+                              "python -m paper_2401_13926_amd.build")
+        L = C.CDLL(str(_LIB_PATH))
+        vp, i64, i64p, i32p, f64p = C.c_void_p, C.c_int64, C.POINTER(C.c_int64), \
+            C.POINTER(C.c_int32), C.POINTER(C.c_double)
+        L.kkt_opts_default.argtypes = [C.POINTER(Opts)]
+        L.kkt_opts_default.restype = None
+        L.kkt_analyze.argtypes = [C.POINTER(Opts), i64, i64p, i32p, f64p, C.POINTER(vp)]
+        L.kkt_get_analysis_info.argtypes = [vp, C.POINTER(AnalysisInfo)]
+        L.kkt_get_permutations.argtypes = [vp, i32p, i32p]
+        L.kkt_get_factor_pattern.argtypes = [vp, i64p, i32p, i64p, i32p]
+        L.kkt_get_analysis_values.argtypes = [vp, f64p, f64p]
+        L.kkt_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.kkt_bind_workspace.argtypes = [vp, vp, C.c_size_t, vp]
+        L.kkt_refactor.argtypes = [vp, vp, vp]
+        L.kkt_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(SolveInfo), vp]
+        L.kkt_direct_solve.argtypes = [vp, vp, vp, vp]
+        L.kkt_get_factor_values.argtypes = [vp, C.c_int32, f64p, f64p, vp]
+        L.kkt_release.argtypes = [vp]
+        L.kkt_last_error.argtypes = [vp]
+        L.kkt_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("kkt_opts_default", "kkt_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().kkt_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Solver:
+    """A handle: analysis of one pattern plus (after bind) its device workspace."""
+
+    def __init__(self, rowptr, colidx, values_first, **opts):
+        self._h = None
+        rp = np.ascontiguousarray(rowptr, np.int64)
+        ci = np.ascontiguousarray(colidx, np.int32)
+        v = np.ascontiguousarray(values_first, np.float64)
+        self.n = rp.size - 1
+        self.opts = default_opts(**opts)
+        h = C.c_void_p()
+        rc = lib().kkt_analyze(C.byref(self.opts), self.n, _p(rp, C.c_int64), _p(ci, C.c_int32),
+                               _p(v, C.c_double), C.byref(h))
+        if rc != KKT_OK:
+            raise KKTError(rc, lib().kkt_last_error(None).decode())
+        self._h = h
+        self.workspace = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.kkt_release(self._h)
+            self._h = None
+
+    def _check(self, rc, allow=()):
+        if rc != KKT_OK and rc not in allow:
+            raise KKTError(rc, lib().kkt_last_error(self._h).decode())
+        return rc
+
+    # --- host-side queries -------------------------------------------------------------
+    def info(self) -> dict:
+        ai = AnalysisInfo()
+        self._check(lib().kkt_get_analysis_info(self._h, C.byref(ai)))
+        return {k: getattr(ai, k) for k, _ in ai._fields_}
+
+    def permutations(self):
+        prow = np.empty(self.n, np.int32)
+        q = np.empty(self.n, np.int32)
+        self._check(lib().kkt_get_permutations(self._h, _p(prow, C.c_int32), _p(q, C.c_int32)))
+        return prow, q
+
+    def pattern(self):
+        inf = self.info()
+        lp = np.empty(self.n + 1, np.int64)
+        up = np.empty(self.n + 1, np.int64)
+        li = np.empty(inf["nnz_l"], np.int32)
+        ui = np.empty(inf["nnz_u"], np.int32)
+        self._check(lib().kkt_get_factor_pattern(self._h, _p(lp, C.c_int64), _p(li, C.c_int32),
+                                                 _p(up, C.c_int64), _p(ui, C.c_int32)))
+        return lp, li, up, ui
+
+    def analysis_values(self):
+        inf = self.info()
+        lx = np.empty(inf["nnz_l"])
+        ux = np.empty(inf["nnz_u"])
+        self._check(lib().kkt_get_analysis_values(self._h, _p(lx, C.c_double), _p(ux, C.c_double)))
+        return lx, ux
+
+    def workspace_size(self) -> int:
+        s = C.c_size_t()
+        self._check(lib().kkt_workspace_size(self._h, C.byref(s)))
+        return s.value
+
+    # --- device -------------------------------------------------------------------------
+    def bind(self, device=None, stream=None):
+        """Allocate the workspace as a torch uint8 tensor and bind it."""
+        import torch
+        dev = torch.device("cuda" if device is None else device)
+        nbytes = self.workspace_size()
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = ws.data_ptr()
+        off = (-base) % 256
+        self._check(lib().kkt_bind_workspace(self._h, C.c_void_p(base + off), nbytes, _stream_ptr(stream)))
+        self.workspace = ws
+        return self
+
+    def refactor(self, values, stream=None):
+        """values: float64 CUDA tensor (nnz) in the CSR order of the analysed pattern."""
+        assert values.is_cuda and values.dtype.is_floating_point and values.element_size() == 8
+        assert values.is_contiguous()
+        self._check(lib().kkt_refactor(self._h, C.c_void_p(values.data_ptr()), _stream_ptr(stream)))
+        self._values_ref = values
+        return self
+
+    def solve(self, b, x=None, tol: float = 0.0, stream=None, allow_noconv=False):
+        """Solve with FGMRES-IR; returns (x, info dict).  b: float64 CUDA tensor (n)."""
+        import torch
+        assert b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == self.n
+        if x is None:
+            x = torch.empty_like(b)
+        info = SolveInfo()
+        rc = lib().kkt_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol),
+                             C.byref(info), _stream_ptr(stream))
+        self._check(rc, allow=(KKT_ENOCONV,) if allow_noconv else ())
+        d = info.as_dict()
+        d["status"] = rc
+        return x, d
+
+    def direct_solve(self, b, x=None, stream=None):
+        import torch
+        assert b.is_cuda and b.dtype == torch.float64 and b.numel() == self.n
+        if x is None:
+            x = torch.empty_like(b)
+        self._check(lib().kkt_direct_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                           _stream_ptr(stream)))
+        return x
+
+    def factor_values(self, precision=0, stream=None):
+        inf = self.info()
+        lx = np.empty(inf["nnz_l"])
+        ux = np.empty(inf["nnz_u"])
+        self._check(lib().kkt_get_factor_values(self._h, int(precision), _p(lx, C.c_double),
+                                                _p(ux, C.c_double), _stream_ptr(stream)))
+        return lx, ux

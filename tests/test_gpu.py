@@ -1,0 +1,242 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the CPU oracle.
+
+* refactorization: FP64 factors bit-identical to the oracle's static-pivot refactorization
+  (same operation order, no contraction); FP32 factors bit-identical to the oracle's FP32
+  refactorization; guard counts equal.
+* direct solve: agrees with the oracle's triangular solves with the same factors.
+* FGMRES-IR: every solve meets NRBE <= 1e-12 and the paper's relative-residual test, and
+  is close to the oracle's solution; repeated solves are bitwise identical.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import kkt_synth as ks
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2401_13926_amd as P  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def cuda(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev)
+
+
+def make(cfg_or_pattern, dev, **opts):
+    p = cfg_or_pattern if isinstance(cfg_or_pattern, ks.KKTPattern) else ks.make_pattern(cfg_or_pattern)
+    v1, _ = p.system(1)
+    s = P.Solver(p.rowptr, p.colidx, v1, **opts).bind(dev)
+    f = oracle.LU(p.rowptr, p.colidx, v1, tau=opts.get("pivot_tau", 0.1))
+    return p, s, f
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_refactor_fp64_bit_exact(dev, cfg):
+    say("refactor fp64 config", cfg)
+    p, s, f = make(cfg, dev)
+    for step in (1, 2, 3):
+        v, _ = p.system(step)
+        s.refactor(cuda(v, dev))
+        torch.cuda.synchronize()
+        lx, ux = s.factor_values(0)
+        olx, oux, ng = f.refactor64(p.rowptr, p.colidx, v)
+        assert np.array_equal(lx, olx), "L differs at step %d" % step
+        assert np.array_equal(ux, oux), "U differs at step %d" % step
+        if step == 1:
+            assert np.array_equal(lx, f.Lx) and np.array_equal(ux, f.Ux)
+
+
+def test_refactor_fp32_bit_exact(dev):
+    say("refactor fp32 config 1")
+    p, s, f = make(1, dev, precision=P.PREC_MIXED)
+    for step in (1, 2):
+        v, _ = p.system(step)
+        s.refactor(cuda(v, dev))
+        torch.cuda.synchronize()
+        lx, ux = s.factor_values(1)
+        olx, oux, ng = f.refactor32(p.rowptr, p.colidx, v)
+        assert np.array_equal(lx, olx.astype(np.float64))
+        assert np.array_equal(ux, oux.astype(np.float64))
+
+
+def test_guard_count_matches_oracle(dev):
+    say("guard count config 2")
+    p, s, f = make(2, dev)
+    v, b = p.system(4)
+    s.refactor(cuda(v, dev))
+    _, info = s.solve(cuda(b, dev))
+    _, _, ng = f.refactor64(p.rowptr, p.colidx, v)
+    assert info["pivots_perturbed"] == ng
+
+
+def step_factors(f, lx, ux):
+    """Unit-lower L and upper U of P K Q in pivot-step indexing (scipy CSC)."""
+    import scipy.sparse as sp
+    n = f.n
+    L = sp.csc_matrix((lx, f.pinv[f.Li], f.Lp), shape=(n, n)) + sp.eye(n, format="csc")
+    U = sp.csc_matrix((ux, f.Ui, f.Up), shape=(n, n))
+    return L, U
+
+
+def check_solve_backward_error(f, lx, ux, b, x, unit):
+    """Componentwise backward error of x = Q U^-1 L^-1 P b for the given factors:
+    |P b - L U z| <= c w u |L| |U| |z| (z = Q^T x, w = longest row), the bound of a
+    forward/backward substitution pair in floating point."""
+    L, U = step_factors(f, lx, ux)
+    z = x[f.Q]
+    pb = b[f.prow]
+    r = np.abs(pb - L @ (U @ z))
+    bound = (abs(L) @ (abs(U) @ np.abs(z)))
+    w = max(np.diff(L.tocsr().indptr).max(), np.diff(U.tocsr().indptr).max())
+    assert np.all(r <= 4 * w * unit * bound + 1e-300), float(np.max(r / np.maximum(bound, 1e-300)))
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("step", [1, 2])
+def test_direct_solve_backward_error(dev, cfg, step):
+    say("direct solve config", cfg, "step", step)
+    p, s, f = make(cfg, dev)
+    v, b = p.system(step)
+    s.refactor(cuda(v, dev))
+    x = s.direct_solve(cuda(b, dev)).cpu().numpy()
+    olx, oux, _ = f.refactor64(p.rowptr, p.colidx, v)
+    check_solve_backward_error(f, olx, oux, b, x, 2.0 ** -53)
+    if step == 1:
+        # pivoted factors: well-conditioned triangles, the solutions agree closely
+        xo = f.solve(b, olx, oux)
+        assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("prec", [P.PREC_FP64, P.PREC_MIXED])
+def test_direct_solve_well_conditioned(dev, prec):
+    say("direct solve well conditioned, precision", prec)
+    p = ks.small_kkt(3000, 2000, 17, dlog=(-1.0, 1.0))
+    p, s, f = make(p, dev, precision=prec)
+    v, b = p.system(2)
+    s.refactor(cuda(v, dev))
+    x = s.direct_solve(cuda(b, dev)).cpu().numpy()
+    if prec == P.PREC_FP64:
+        olx, oux, _ = f.refactor64(p.rowptr, p.colidx, v)
+        xo = f.solve(b, olx, oux)
+        tol = 1e-11
+        check_solve_backward_error(f, olx, oux, b, x, 2.0 ** -53)
+    else:
+        olx, oux, _ = f.refactor32(p.rowptr, p.colidx, v)
+        xo = f.solve32(b, olx, oux)
+        tol = 1e-3
+        # the FP32 solve rounds b to binary32 first, then substitutes in binary32
+        check_solve_backward_error(f, olx.astype(np.float64), oux.astype(np.float64),
+                                   b.astype(np.float32).astype(np.float64), x, 2.0 ** -24)
+    assert np.linalg.norm(x - xo) <= tol * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fgmres_ir_sequence(dev, cfg):
+    p, s, f = make(cfg, dev)
+    nsteps = 1 if cfg == 1 else 6
+    for step in range(1, nsteps + 1):
+        say("fgmres config", cfg, "step", step)
+        v, b = p.system(step)
+        s.refactor(cuda(v, dev))
+        xg, info = s.solve(cuda(b, dev))
+        x = xg.cpu().numpy()
+        m = oracle.metrics(p.rowptr, p.colidx, v, x, b)
+        assert info["converged"] == 1
+        assert m["nrbe"] <= 1e-12
+        assert info["nrbe"] == pytest.approx(m["nrbe"], rel=1e-6, abs=1e-30)
+        # the oracle's FGMRES-IR on the same static-pivot factors (paper control)
+        olx, oux, _ = f.refactor64(p.rowptr, p.colidx, v)
+        xo, oinfo = f.fgmres_ir(p.rowptr, p.colidx, v, b, Lx=olx, Ux=oux, restart=10, mode=1, eta=1e-14)
+        assert oinfo["converged"]
+        assert abs(info["iterations"] - oinfo["iters"]) <= 3
+        # both are refinements of the same system: compare with a fresh pivoted solve
+        xd, _ = oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=f.Q)
+        rel = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+        reld = np.linalg.norm(xo - xd) / np.linalg.norm(xd)
+        say("   iters", info["iterations"], "oracle iters", oinfo["iters"], "nrbe %.2e" % m["nrbe"],
+            "rel diff vs direct %.2e (oracle IR %.2e)" % (rel, reld))
+        assert rel <= max(1e3 * reld, 1e-10)
+
+
+def test_solve_repeatable_bitwise(dev):
+    say("repeatability config 2")
+    p, s, f = make(2, dev)
+    v, b = p.system(3)
+    s.refactor(cuda(v, dev))
+    x1, i1 = s.solve(cuda(b, dev))
+    x1 = x1.cpu().numpy()
+    s.refactor(cuda(v, dev))
+    x2, i2 = s.solve(cuda(b, dev))
+    assert np.array_equal(x1, x2.cpu().numpy())
+    assert i1["iterations"] == i2["iterations"]
+
+
+def test_edge_cases(dev):
+    say("edge cases")
+    p = ks.small_kkt(12, 7, 5)
+    v, b = p.system(1)
+    s = P.Solver(p.rowptr, p.colidx, v)
+    s.bind(dev)
+    with pytest.raises(P.KKTError) as e:
+        s.solve(cuda(b, dev))
+    assert e.value.code == P.KKT_ESTATE
+    s.refactor(cuda(v, dev))
+    x, info = s.solve(cuda(b, dev))
+    A = ks.to_dense(p.rowptr, p.colidx, v, p.N)
+    assert np.linalg.norm(A @ x.cpu().numpy() - b) <= 1e-8 * np.linalg.norm(b) * np.abs(A).max()
+    # zero right-hand side: x = 0 without refinement
+    x0, info0 = s.solve(torch.zeros(p.N, dtype=torch.float64, device=dev))
+    assert info0["converged"] == 1 and info0["iterations"] == 0
+    assert torch.count_nonzero(x0).item() == 0
+    # non-finite right-hand side is rejected
+    bb = b.copy()
+    bb[3] = np.nan
+    with pytest.raises(P.KKTError) as e:
+        s.solve(cuda(bb, dev))
+    assert e.value.code == P.KKT_EINVAL
+    # non-finite matrix value is rejected at the next solve
+    vv = v.copy()
+    vv[0] = np.inf
+    s.refactor(cuda(vv, dev))
+    with pytest.raises(P.KKTError) as e:
+        s.solve(cuda(b, dev))
+    assert e.value.code == P.KKT_EINVAL
+    # the handle still works afterwards
+    s.refactor(cuda(v, dev))
+    _, info = s.solve(cuda(b, dev))
+    assert info["converged"] == 1
+
+
+def test_guard_fail_policy(dev):
+    say("guard fail policy")
+    # K_1 = [[4, 2], [2, 3]]; K_2 = [[4, 2], [2, 1]] cancels the second static pivot exactly
+    rp = np.array([0, 2, 4], np.int64)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    v1 = np.array([4.0, 2.0, 2.0, 3.0])
+    v2 = np.array([4.0, 2.0, 2.0, 1.0])
+    b = np.array([1.0, 2.0])
+    s = P.Solver(rp, ci, v1, guard_policy=P.GUARD_FAIL).bind(dev)
+    s.refactor(cuda(v2, dev))
+    with pytest.raises(P.KKTError) as e:
+        s.solve(cuda(b, dev))
+    assert e.value.code == P.KKT_ESINGULAR
+    s2 = P.Solver(rp, ci, v1).bind(dev)
+    s2.refactor(cuda(v2, dev))
+    torch.cuda.synchronize()
+    _, ux = s2.factor_values(0)
+    assert ux[-1] == 2.0 * 2.0 ** -53

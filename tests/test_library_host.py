@@ -1,0 +1,91 @@
+"""Host-side checks of the GPU library: the C ABI loads and exports every declared symbol,
+and its host analysis (an independent implementation of the ordering and pivot rules)
+reproduces the oracle's permutations, patterns and FP64 factor values bit for bit.
+No GPU needed: kkt_analyze and the getters make no device calls."""
+import pathlib
+import re
+
+import numpy as np
+import pytest
+
+import kkt_synth as ks
+import oracle
+import paper_2401_13926_amd as P
+from paper_2401_13926_amd import kkt as K
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+
+
+def test_exports_every_declared_symbol():
+    header = (ROOT / "include" / "kkt.h").read_text()
+    declared = sorted(set(re.findall(r"\b(kkt_[a-z_]+)\s*\(", header)))
+    assert declared, "no declarations found"
+    assert sorted(K.EXPORTS) == declared
+    lib = P.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def check_parity(rowptr, colidx, values, leaf=64, tau=0.1):
+    s = P.Solver(rowptr, colidx, values, nd_leaf=leaf, pivot_tau=tau)
+    Q = oracle.order(rowptr, colidx, leaf=leaf)
+    f = oracle.LU(rowptr, colidx, values, Q=Q, tau=tau)
+    prow, q = s.permutations()
+    assert np.array_equal(q, f.Q)
+    assert np.array_equal(prow, f.prow)
+    lp, li, up, ui = s.pattern()
+    assert np.array_equal(lp, f.Lp) and np.array_equal(li, f.Li)
+    assert np.array_equal(up, f.Up) and np.array_equal(ui, f.Ui)
+    lx, ux = s.analysis_values()
+    assert np.array_equal(lx, f.Lx) and np.array_equal(ux, f.Ux)
+    inf = s.info()
+    assert inf["nnz_l"] == f.lnz and inf["nnz_u"] == f.unz
+    assert inf["offdiag_pivots"] == int(np.sum(f.prow != f.Q))
+    return s, f
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_analysis_bit_exact_configs(cfg):
+    p = ks.make_pattern(cfg)
+    v, _ = p.system(1)
+    check_parity(p.rowptr, p.colidx, v)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_analysis_bit_exact_small(seed):
+    p = ks.small_kkt(40 + 7 * seed, 25 + 4 * seed, 300 + seed, dlog=(-8.0, 8.0))
+    v, _ = p.system(1 + seed % 4)
+    check_parity(p.rowptr, p.colidx, v, leaf=[1, 4, 16, 64][seed % 4], tau=[0.1, 0.5, 1.0][seed % 3])
+
+
+def test_analysis_general_unsymmetric():
+    rng = np.random.default_rng(11)
+    n = 300
+    import scipy.sparse as sp
+    A = sp.random(n, n, density=0.01, random_state=12, format="csr") + sp.diags(rng.standard_normal(n))
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    check_parity(A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, leaf=8, tau=0.3)
+
+
+def test_errors():
+    rp = np.array([0, 2, 3], np.int64)
+    ci = np.array([1, 0, 1], np.int32)
+    with pytest.raises(P.KKTError) as e:
+        P.Solver(rp, ci, np.ones(3))
+    assert e.value.code == P.KKT_EINVAL
+    rp = np.array([0, 2, 4, 5], np.int64)
+    ci = np.array([0, 1, 0, 1, 2], np.int32)
+    with pytest.raises(P.KKTError) as e:
+        P.Solver(rp, ci, np.array([1.0, 1.0, 1.0, 1.0, 1.0]))
+    assert e.value.code == P.KKT_ESINGULAR
+    with pytest.raises(P.KKTError) as e:
+        P.Solver(rp, ci, np.array([1.0, np.nan, 1.0, 1.0, 1.0]))
+    assert e.value.code == P.KKT_EINVAL
+    p = ks.small_kkt(20, 10, 1)
+    v, _ = p.system(1)
+    with pytest.raises(P.KKTError) as e:
+        P.Solver(p.rowptr, p.colidx, v, restart=0)
+    assert e.value.code == P.KKT_EINVAL
+    s = P.Solver(p.rowptr, p.colidx, v)
+    assert s.workspace_size() > 0
