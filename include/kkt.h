@@ -72,7 +72,27 @@ typedef struct {
                                inner test |g| <= nrbe_target (||K||inf ||x|| + ||r||) */
     int32_t mixed_fallback; /* mixed precision: on non-convergence refactor in FP64 and
                                solve again (1) or return KKT_ENOCONV (0) */
+    int32_t mixed_max_cycles; /* mixed precision: restart cycles tried with the FP32
+                               preconditioner before the fallback (3) */
 } kkt_opts_t;
+
+/* Kernel classes reported by kkt_get_kernel_times. */
+enum {
+    KKT_K_INGEST = 0,   /* values into factor storage, ||K||_inf, finiteness checks */
+    KKT_K_REFACTOR = 1, /* numeric refactorization */
+    KKT_K_TRSV_L = 2,   /* forward substitution with L (one launch per preconditioner use) */
+    KKT_K_TRSV_U = 3,   /* backward substitution with U */
+    KKT_K_SPMV = 4,     /* w = K z_j with the first Gram-Schmidt projections */
+    KKT_K_CGS = 5,      /* second Gram-Schmidt pass, norm, rotation, normalization */
+    KKT_K_RESID = 6,    /* true residual rho = b - K x with norms */
+    KKT_K_OTHER = 7,    /* cycle start, least squares, solution update, sentinel reset */
+    KKT_K_CLASSES = 8
+};
+
+typedef struct {
+    int64_t launches[KKT_K_CLASSES]; /* timed launches per class */
+    double ms[KKT_K_CLASSES];        /* summed device time per class (HIP events) */
+} kkt_kernel_times_t;
 
 typedef struct {
     int64_t n;              /* N */
@@ -152,7 +172,8 @@ kkt_status_t kkt_refactor(kkt_handle_t h, const double *dev_values, void *stream
 
 /* Solve K x = b for the last refactored K: direct solve, refine decision, FGMRES-IR
  * (Section 2).  dev_b, dev_x: DEVICE arrays of n float64 (distinct).  tol <= 0 uses
- * opts.delta_tol.  Synchronizes `stream` once per restart cycle and before returning; *info
+ * opts.delta_tol.  Synchronizes `stream` after each Arnoldi step (to read the stop flag)
+ * and before returning; *info
  * (may be NULL) is filled on return.  Errors: KKT_ESTATE (no refactor yet), KKT_EINVAL
  * (non-finite K values or b), KKT_ESINGULAR (guard_policy = FAIL and a guarded pivot),
  * KKT_ENOCONV (tolerance not met; x holds the last iterate, info is filled). */
@@ -169,6 +190,14 @@ kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x
  * float64.  Synchronizes `stream`. */
 kkt_status_t kkt_get_factor_values(kkt_handle_t h, int32_t precision, double *lx, double *ux,
                                    void *stream);
+
+/* Enable (1) or disable (0) per-launch timing with HIP events on the work stream; enabling
+ * clears the totals.  Timing adds two event records per kernel launch. */
+kkt_status_t kkt_set_profiling(kkt_handle_t h, int32_t on);
+
+/* Totals since profiling was enabled: launches and device milliseconds per kernel class.
+ * Synchronizes `stream` (the stream the work was issued on). */
+kkt_status_t kkt_get_kernel_times(kkt_handle_t h, kkt_kernel_times_t *times, void *stream);
 
 /* Free the handle and its host memory (the workspace stays owned by the caller). */
 kkt_status_t kkt_release(kkt_handle_t h);

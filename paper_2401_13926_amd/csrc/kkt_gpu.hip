@@ -732,6 +732,16 @@ struct kkt_handle_s {
     int grid_refactor64 = 0, grid_refactor32 = 0, grid_trsv64 = 0, grid_trsv32 = 0, grid_stream = 0;
     kkt::ControlSummary *host_ctl = nullptr;  // pinned
     int restart_alloc = 0;
+    bool fp64_current = false;  // mixed mode: FP64 factors of the current system exist
+    // per-launch timing (kkt_set_profiling)
+    struct ProfRec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<ProfRec> ev_pending;
+    kkt_kernel_times_t times{};
 };
 
 using kkt::Analysis;
@@ -753,6 +763,55 @@ kkt_status_t fail(kkt_handle_t h, kkt_status_t s, const std::string &m) {
             return fail((h), KKT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
         }                                                                                       \
     } while (0)
+
+// --- per-launch timing with HIP events --------------------------------------------------
+hipEvent_t prof_begin(kkt_handle_t h, hipStream_t s) {
+    if (!h->prof) return nullptr;
+    hipEvent_t e = nullptr;
+    if (!h->ev_pool.empty()) {
+        e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return nullptr;
+    }
+    if (hipEventRecord(e, s) != hipSuccess) {
+        h->ev_pool.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+void prof_end(kkt_handle_t h, int cls, hipEvent_t a, hipStream_t s) {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (!h->ev_pool.empty()) {
+        b = h->ev_pool.back();
+        h->ev_pool.pop_back();
+    } else if (hipEventCreate(&b) != hipSuccess) {
+        h->ev_pool.push_back(a);
+        return;
+    }
+    if (hipEventRecord(b, s) != hipSuccess) {
+        h->ev_pool.push_back(a);
+        h->ev_pool.push_back(b);
+        return;
+    }
+    h->ev_pending.push_back({cls, a, b});
+}
+
+// Accumulates completed records; call after the stream has been synchronized.
+void prof_collect(kkt_handle_t h) {
+    for (auto &r : h->ev_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            h->times.launches[r.cls] += 1;
+            h->times.ms[r.cls] += ms;
+        }
+        h->ev_pool.push_back(r.a);
+        h->ev_pool.push_back(r.b);
+    }
+    h->ev_pending.clear();
+}
 
 // Lanes per row for the rows of one task: enough lanes that a lane handles about four
 // entries of the longest row, at most 64.
@@ -931,33 +990,48 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     return hipGetLastError();
 }
 
-// x = Q U^-1 L^-1 P b with the current factors of precision T; sentinels re-armed first.
+// x = Q U^-1 L^-1 P b with the current factors of precision T (sentinels armed before).
 template <typename T>
 hipError_t precond(kkt_handle_t h, const double *b, double *x, const Control *ctl, hipStream_t s) {
     T *y = (T *)(sizeof(T) == 8 ? (void *)h->d.y64 : (void *)h->d.y32);
     T *z = (T *)(sizeof(T) == 8 ? (void *)h->d.z64 : (void *)h->d.z32);
+    hipEvent_t e0 = prof_begin(h, s);
     hipError_t e = launch_trsv<T>(h, true, b, nullptr, y, nullptr, ctl, s);
+    prof_end(h, KKT_K_TRSV_L, e0, s);
     if (e != hipSuccess) return e;
-    return launch_trsv<T>(h, false, nullptr, y, z, x, ctl, s);
+    e0 = prof_begin(h, s);
+    e = launch_trsv<T>(h, false, nullptr, y, z, x, ctl, s);
+    prof_end(h, KKT_K_TRSV_U, e0, s);
+    return e;
 }
 
 template <typename T> void rearm(kkt_handle_t h, hipStream_t s) {
     T *y = (T *)(sizeof(T) == 8 ? (void *)h->d.y64 : (void *)h->d.y32);
     T *z = (T *)(sizeof(T) == 8 ? (void *)h->d.z64 : (void *)h->d.z32);
+    hipEvent_t e0 = prof_begin(h, s);
     k_fill_sentinel<T><<<h->grid_stream, kStreamBlock, 0, s>>>(h->an.n, y, z, h->d.ctl);
+    prof_end(h, KKT_K_OTHER, e0, s);
 }
 
+// Enqueues ingest + numeric refactorization of the values at `vals` (device; when null, the
+// values already in the workspace are re-ingested).
 kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precision, hipStream_t s) {
     const Analysis &a = h->an;
     const int64_t f = a.nnz_f();
     DevLayout &d = h->d;
+    const int rows_grid = (int)std::max<int64_t>(1, std::min<int64_t>((a.n + 255) / 256, 2048));
+    hipEvent_t e0 = prof_begin(h, s);
     k_prep_refactor<<<1, 1, 0, s>>>(d.ctl);
-    k_ingest<<<2048, 256, 0, s>>>(a.nnz, dev_values, d.kval, f, d.fsrc, d.F64, d.F32, precision, d.ctl);
-    k_rownorm<<<std::max<int64_t>(1, std::min<int64_t>((a.n + 255) / 256, 2048)), 256, 0, s>>>(a.n, d.krp, d.kval,
-                                                                                             d.ctl);
+    if (dev_values)
+        k_ingest<<<2048, 256, 0, s>>>(a.nnz, dev_values, d.kval, f, d.fsrc, d.F64, d.F32, precision, d.ctl);
+    else
+        k_ingest<<<2048, 256, 0, s>>>(a.nnz, d.kval, nullptr, f, d.fsrc, d.F64, d.F32, precision, d.ctl);
+    k_rownorm<<<rows_grid, 256, 0, s>>>(a.n, d.krp, d.kval, d.ctl);
+    prof_end(h, KKT_K_INGEST, e0, s);
     KKT_HIP(h, hipGetLastError());
     h->epoch += 1;
     if (h->epoch == 0) h->epoch = 1;
+    e0 = prof_begin(h, s);
     if (precision == KKT_PREC_MIXED) {
         const unsigned int chunk = work_chunk(a.n, h->grid_refactor32 * (kCoopBlock / 64));
         RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F32, d.T32,
@@ -969,6 +1043,7 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
                                d.flag, h->epoch, chunk, h->opts.guard_policy, d.ctl};
         k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r);
     }
+    prof_end(h, KKT_K_REFACTOR, e0, s);
     KKT_HIP(h, hipGetLastError());
     h->have_factors = true;
     h->factor_precision = precision;
@@ -978,13 +1053,21 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
 kkt_status_t read_ctl(kkt_handle_t h, hipStream_t s) {
     KKT_HIP(h, hipMemcpyAsync(h->host_ctl, h->d.ctl, sizeof(ControlSummary), hipMemcpyDeviceToHost, s));
     KKT_HIP(h, hipStreamSynchronize(s));
+    prof_collect(h);
+    if (h->host_ctl->hang) {
+        h->device_failed = true;
+        return fail(h, KKT_EDEVICE, "a dependency wait exceeded its spin limit");
+    }
     return KKT_OK;
 }
 
-// One FGMRES-IR solve with the factors currently in the workspace.
+// One FGMRES-IR solve with the factors currently in the workspace (Section 2.1): x0 from
+// the direct solve, the refine test of Section 2.3, then restart cycles whose solution is
+// formed only at the end of the cycle.  The host reads the stop flag after every Arnoldi
+// step, so no kernel is launched past the end of a cycle.
 template <typename T>
 kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, kkt_solve_info_t *info,
-                        hipStream_t s) {
+                        hipStream_t s, int max_cycles) {
     const Analysis &a = h->an;
     DevLayout &d = h->d;
     const int R = h->opts.restart;
@@ -992,19 +1075,18 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     KrylovArgs ka = kargs<T>(h);
     T *y = (T *)(sizeof(T) == 8 ? (void *)d.y64 : (void *)d.y32);
     T *z = (T *)(sizeof(T) == 8 ? (void *)d.z64 : (void *)d.z32);
-    // x0 = M^-1 b, residual and norms
+    hipEvent_t e0 = prof_begin(h, s);
     k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
+    prof_end(h, KKT_K_OTHER, e0, s);
     rearm<T>(h, s);
     KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
+    e0 = prof_begin(h, s);
     k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+    prof_end(h, KKT_K_RESID, e0, s);
     KKT_HIP(h, hipGetLastError());
     kkt_status_t st = read_ctl(h, s);
     if (st != KKT_OK) return st;
     const ControlSummary &c = *h->host_ctl;
-    if (c.hang) {
-        h->device_failed = true;
-        return fail(h, KKT_EDEVICE, "a dependency wait exceeded its spin limit");
-    }
     if (c.nonfinite) return fail(h, KKT_EINVAL, "non-finite value in the matrix of the last refactorization");
     if (c.nonfinite_b) return fail(h, KKT_EINVAL, "non-finite value in the right-hand side");
     if (c.guard_fail) return fail(h, KKT_ESINGULAR, "tiny static pivot under the FAIL guard policy");
@@ -1024,14 +1106,13 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     inf.nrbe0 = nrbe;
     const bool paper = h->opts.stop_mode == KKT_STOP_PAPER;
     const double target = h->opts.nrbe_target;
-    auto accept = [&](double est_pass) { return (paper ? est_pass : true) && nrbe <= target; };
     bool converged;
     if (bn == 0.0) converged = true;
     else converged = paper ? (rn / bn < tol && nrbe <= target) : nrbe <= target;
     inf.refined = !converged;
     int iters = 0, cycles = 0;
     double est = rn;
-    while (!converged && cycles <= h->opts.max_restarts) {
+    while (!converged && cycles < max_cycles) {
         ++cycles;
         if (!(rn > 0.0)) {
             converged = true;
@@ -1039,29 +1120,39 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         }
         const double xn = std::sqrt(h->host_ctl->xnorm2);
         const double inner = paper ? tol * rho0 : target * (knorm * xn + bn);
+        e0 = prof_begin(h, s);
         k_cycle_start<T><<<G, kStreamBlock, 0, s>>>(ka, d.r, inner, y, z);
+        prof_end(h, KKT_K_OTHER, e0, s);
         for (int j = 0; j < R; ++j) {
             KKT_HIP(h, precond<T>(h, d.V + (int64_t)j * a.n, d.Z + (int64_t)j * a.n, d.ctl, s));
+            e0 = prof_begin(h, s);
             k_spmv_dots<<<G, kStreamBlock, 0, s>>>(ka, j);
+            prof_end(h, KKT_K_SPMV, e0, s);
+            e0 = prof_begin(h, s);
             k_cgs_pass2<<<G, kStreamBlock, 0, s>>>(ka, j);
             k_cgs_finish<<<G, kStreamBlock, 0, s>>>(ka, j, R);
             k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, y, z);
+            prof_end(h, KKT_K_CGS, e0, s);
+            KKT_HIP(h, hipGetLastError());
+            st = read_ctl(h, s);
+            if (st != KKT_OK) return st;
+            if (h->host_ctl->stop) break;
         }
+        e0 = prof_begin(h, s);
         k_lsq<<<1, 64, 0, s>>>(d.ctl);
         k_xupdate<<<G, kStreamBlock, 0, s>>>(ka, x);
+        prof_end(h, KKT_K_OTHER, e0, s);
+        e0 = prof_begin(h, s);
         k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+        prof_end(h, KKT_K_RESID, e0, s);
         KKT_HIP(h, hipGetLastError());
         st = read_ctl(h, s);
         if (st != KKT_OK) return st;
-        if (h->host_ctl->hang) {
-            h->device_failed = true;
-            return fail(h, KKT_EDEVICE, "a dependency wait exceeded its spin limit");
-        }
         iters += h->host_ctl->jdone;
         est = h->host_ctl->est;
         rn = std::sqrt(h->host_ctl->rnorm2);
         nrbe = rn / (knorm * std::sqrt(h->host_ctl->xnorm2) + bn);
-        converged = accept(est < tol * rho0);
+        converged = paper ? (est < tol * rho0 && nrbe <= target) : nrbe <= target;
     }
     inf.converged = converged;
     inf.iterations = iters;
@@ -1098,6 +1189,7 @@ void kkt_opts_default(kkt_opts_t *o) {
     o->guard_policy = KKT_GUARD_PERTURB;
     o->stop_mode = KKT_STOP_PAPER;
     o->mixed_fallback = 1;
+    o->mixed_max_cycles = 3;
 }
 
 kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowptr, const int32_t *colidx,
@@ -1276,6 +1368,7 @@ kkt_status_t kkt_refactor(kkt_handle_t h, const double *dev_values, void *stream
     if (!h || !dev_values) return fail(h, KKT_EINVAL, "null argument");
     if (h->device_failed) return fail(h, KKT_EDEVICE, "handle unusable after a device error");
     if (!h->bound) return fail(h, KKT_ESTATE, "no workspace bound");
+    h->fp64_current = false;
     return refactor_impl(h, dev_values, h->opts.precision, (hipStream_t)stream);
 }
 
@@ -1287,31 +1380,22 @@ kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, doubl
     if (!h->bound || !h->have_factors) return fail(h, KKT_ESTATE, "refactor before solve");
     if (tol <= 0.0) tol = h->opts.delta_tol;
     hipStream_t s = (hipStream_t)stream;
-    if (h->factor_precision == KKT_PREC_MIXED) {
-        kkt_status_t st = solve_impl<float>(h, dev_b, dev_x, tol, info, s);
+    const int cycles = h->opts.max_restarts + 1;
+    if (h->factor_precision == KKT_PREC_MIXED && !h->fp64_current) {
+        const int mixed_cycles = h->opts.mixed_fallback ? std::min(cycles, std::max(1, h->opts.mixed_max_cycles))
+                                                        : cycles;
+        kkt_status_t st = solve_impl<float>(h, dev_b, dev_x, tol, info, s, mixed_cycles);
         if (st != KKT_ENOCONV || !h->opts.mixed_fallback) return st;
-        // FP64 fallback: refactor the same values (already in the workspace) in FP64
-        const int64_t f = h->an.nnz_f();
-        k_prep_refactor<<<1, 1, 0, s>>>(h->d.ctl);
-        k_ingest<<<2048, 256, 0, s>>>(h->an.nnz, h->d.kval, nullptr, f, h->d.fsrc, h->d.F64, h->d.F32, 0,
-                                      h->d.ctl);
-        k_rownorm<<<std::max<int64_t>(1, std::min<int64_t>((h->an.n + 255) / 256, 2048)), 256, 0, s>>>(
-            h->an.n, h->d.krp, h->d.kval, h->d.ctl);
-        h->epoch += 1;
-        if (h->epoch == 0) h->epoch = 1;
-        const unsigned int chunk = work_chunk(h->an.n, h->grid_refactor64 * (kCoopBlock / 64));
-        RefactorArgs<double> r{h->an.n, h->d.fp, h->d.fi, h->d.fdiag, h->d.relptr, h->d.relpos, h->d.order,
-                               h->d.f2t, h->d.F64, h->d.T64, h->d.flag, h->epoch, chunk, h->opts.guard_policy,
-                               h->d.ctl};
-        k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r);
-        KKT_HIP(h, hipGetLastError());
-        h->factor_precision = KKT_PREC_FP64;
-        st = solve_impl<double>(h, dev_b, dev_x, tol, info, s);
-        if (info) info->fallback = 1;
-        h->factor_precision = KKT_PREC_MIXED;  // the next refactor starts in mixed again
-        return st;
+        // FP64 fallback: refactor the values already in the workspace in FP64 (the FP32
+        // factors stay valid); later solves of this system go straight to FP64
+        st = refactor_impl(h, nullptr, KKT_PREC_FP64, s);
+        if (st != KKT_OK) return st;
+        h->factor_precision = KKT_PREC_MIXED;
+        h->fp64_current = true;
     }
-    return solve_impl<double>(h, dev_b, dev_x, tol, info, s);
+    kkt_status_t st = solve_impl<double>(h, dev_b, dev_x, tol, info, s, cycles);
+    if (info && h->fp64_current) info->fallback = 1;
+    return st;
 }
 
 kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x, void *stream) {
@@ -1352,8 +1436,30 @@ kkt_status_t kkt_get_factor_values(kkt_handle_t h, int32_t precision, double *lx
     return KKT_OK;
 }
 
+kkt_status_t kkt_set_profiling(kkt_handle_t h, int32_t on) {
+    if (!h) return fail(h, KKT_EINVAL, "null handle");
+    h->prof = on != 0;
+    h->times = kkt_kernel_times_t{};
+    return KKT_OK;
+}
+
+kkt_status_t kkt_get_kernel_times(kkt_handle_t h, kkt_kernel_times_t *t, void *stream) {
+    if (!h || !t) return fail(h, KKT_EINVAL, "null argument");
+    if (!h->ev_pending.empty()) {
+        KKT_HIP(h, hipStreamSynchronize((hipStream_t)stream));
+        prof_collect(h);
+    }
+    *t = h->times;
+    return KKT_OK;
+}
+
 kkt_status_t kkt_release(kkt_handle_t h) {
     if (!h) return KKT_OK;
+    for (auto &r : h->ev_pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->host_ctl) (void)hipHostFree(h->host_ctl);
     delete h;
     return KKT_OK;

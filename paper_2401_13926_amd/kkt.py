@@ -25,14 +25,17 @@ STOP_PAPER, STOP_NRBE = 0, 1
 EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
            "kkt_get_factor_pattern", "kkt_get_analysis_values", "kkt_workspace_size",
            "kkt_bind_workspace", "kkt_refactor", "kkt_solve", "kkt_direct_solve",
-           "kkt_get_factor_values", "kkt_release", "kkt_last_error"]
+           "kkt_get_factor_values", "kkt_set_profiling", "kkt_get_kernel_times", "kkt_release",
+           "kkt_last_error"]
+
+KERNEL_CLASSES = ["ingest", "refactor", "trsv_l", "trsv_u", "spmv", "cgs", "resid", "other"]
 
 
 class Opts(C.Structure):
     _fields_ = [("nd_leaf", C.c_int32), ("pivot_tau", C.c_double), ("restart", C.c_int32),
                 ("max_restarts", C.c_int32), ("delta_tol", C.c_double), ("nrbe_target", C.c_double),
                 ("precision", C.c_int32), ("guard_policy", C.c_int32), ("stop_mode", C.c_int32),
-                ("mixed_fallback", C.c_int32)]
+                ("mixed_fallback", C.c_int32), ("mixed_max_cycles", C.c_int32)]
 
 
 class AnalysisInfo(C.Structure):
@@ -51,6 +54,10 @@ class SolveInfo(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8)]
 
 
 class KKTError(RuntimeError):
@@ -82,6 +89,8 @@ def lib():
         L.kkt_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(SolveInfo), vp]
         L.kkt_direct_solve.argtypes = [vp, vp, vp, vp]
         L.kkt_get_factor_values.argtypes = [vp, C.c_int32, f64p, f64p, vp]
+        L.kkt_set_profiling.argtypes = [vp, C.c_int32]
+        L.kkt_get_kernel_times.argtypes = [vp, C.POINTER(KernelTimes), vp]
         L.kkt_release.argtypes = [vp]
         L.kkt_last_error.argtypes = [vp]
         L.kkt_last_error.restype = C.c_char_p
@@ -226,3 +235,13 @@ class Solver:
         self._check(lib().kkt_get_factor_values(self._h, int(precision), _p(lx, C.c_double),
                                                 _p(ux, C.c_double), _stream_ptr(stream)))
         return lx, ux
+
+    # --- per-kernel timing ------------------------------------------------------------
+    def set_profiling(self, on=True):
+        self._check(lib().kkt_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_times(self, stream=None) -> dict:
+        """{class: (launches, total ms)} since profiling was enabled (syncs the stream)."""
+        t = KernelTimes()
+        self._check(lib().kkt_get_kernel_times(self._h, C.byref(t), _stream_ptr(stream)))
+        return {name: (int(t.launches[i]), float(t.ms[i])) for i, name in enumerate(KERNEL_CLASSES)}
