@@ -510,38 +510,89 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
         }
     }
     // --- triangular-solve schedules
-    auto schedule = [&](bool lower, std::vector<int32_t> &rows, std::vector<int32_t> &task,
-                        int64_t &nlev) {
-        std::vector<int64_t> level(n, 0);
+    auto schedule = [&](bool lower, TriSchedule &sc) {
+        const std::vector<int64_t> &rp = lower ? a.lrp : a.urp;
+        const std::vector<int32_t> &ci = lower ? a.lci : a.uci;
+        std::vector<int32_t> level(n, 0);
         if (lower) {
             for (int64_t i = 0; i < n; ++i) {
-                int64_t l = 0;
-                for (int64_t p = a.lrp[i]; p < a.lrp[i + 1]; ++p) l = std::max(l, level[a.lci[p]] + 1);
+                int32_t l = 0;
+                for (int64_t p = rp[i]; p < rp[i + 1]; ++p) l = std::max(l, level[ci[p]] + 1);
                 level[i] = l;
             }
         } else {
             for (int64_t i = n - 1; i >= 0; --i) {
-                int64_t l = 0;
-                for (int64_t p = a.urp[i]; p < a.urp[i + 1]; ++p) l = std::max(l, level[a.uci[p]] + 1);
+                int32_t l = 0;
+                for (int64_t p = rp[i]; p < rp[i + 1]; ++p) l = std::max(l, level[ci[p]] + 1);
                 level[i] = l;
             }
         }
-        rows.resize(n);
-        for (int64_t i = 0; i < n; ++i) rows[i] = (int32_t)(lower ? i : n - 1 - i);
-        std::stable_sort(rows.begin(), rows.end(), [&](int32_t x, int32_t y) { return level[x] < level[y]; });
-        task.clear();
-        task.push_back(0);
-        int64_t cur = 0;
-        while (cur < n) {
-            int64_t end = cur + 1;
-            while (end < n && end - cur < opt.trsv_rows_per_task && level[rows[end]] == level[rows[cur]]) ++end;
-            task.push_back((int32_t)end);
-            cur = end;
+        const int32_t nlev = n ? 1 + *std::max_element(level.begin(), level.end()) : 0;
+        sc.levels = nlev;
+        sc.rows.resize(n);
+        for (int64_t i = 0; i < n; ++i) sc.rows[i] = (int32_t)(lower ? i : n - 1 - i);
+        std::stable_sort(sc.rows.begin(), sc.rows.end(), [&](int32_t x, int32_t y) { return level[x] < level[y]; });
+        sc.lev_ptr.assign(nlev + 1, 0);
+        for (int64_t i = 0; i < n; ++i) ++sc.lev_ptr[level[i] + 1];
+        for (int32_t l = 0; l < nlev; ++l) sc.lev_ptr[l + 1] += sc.lev_ptr[l];
+        sc.lev_lg.assign(nlev, 0);
+        for (int32_t l = 0; l < nlev; ++l) {
+            int64_t mx = 0;
+            for (int32_t r = sc.lev_ptr[l]; r < sc.lev_ptr[l + 1]; ++r)
+                mx = std::max(mx, rp[sc.rows[r] + 1] - rp[sc.rows[r]]);
+            int lg = 0;  // lanes such that each lane handles about four entries, at most 64
+            while (lg < 6 && ((int64_t)1 << lg) * 4 < mx) ++lg;
+            sc.lev_lg[l] = (int8_t)lg;
         }
-        nlev = n ? 1 + *std::max_element(level.begin(), level.end()) : 0;
+        // tiles
+        sc.tile_row.assign(1, 0);
+        sc.tile_lev.clear();
+        int32_t open_rows = 0;  // rows in the current multi-level tile
+        auto close = [&](int32_t end) {
+            if (end > sc.tile_row.back()) sc.tile_row.push_back(end);
+        };
+        for (int32_t l = 0; l < nlev; ++l) {
+            const int32_t r0 = sc.lev_ptr[l], r1 = sc.lev_ptr[l + 1];
+            const int32_t cnt = r1 - r0;
+            if (cnt > opt.narrow_rows) {
+                close(r0);
+                open_rows = 0;
+                const int32_t chunk = std::max(1, opt.tile_threads >> sc.lev_lg[l]);
+                for (int32_t s0 = r0; s0 < r1; s0 += chunk) {
+                    sc.tile_lev.push_back(l);
+                    close(std::min(s0 + chunk, r1));
+                }
+                continue;
+            }
+            if (open_rows > 0 && open_rows + cnt > opt.tile_rows) {
+                close(r0);
+                open_rows = 0;
+            }
+            if (open_rows == 0) sc.tile_lev.push_back(l);
+            open_rows += cnt;
+        }
+        close((int32_t)n);
+        if ((int64_t)sc.tile_lev.size() != sc.tiles()) {
+            *msg = "internal: tile bookkeeping";
+            return false;
+        }
+        // encoded references
+        std::vector<int32_t> pos(n), tile_of(n);
+        for (int64_t r = 0; r < n; ++r) pos[sc.rows[r]] = (int32_t)r;
+        for (int64_t t = 0; t < sc.tiles(); ++t)
+            for (int32_t r = sc.tile_row[t]; r < sc.tile_row[t + 1]; ++r) tile_of[r] = (int32_t)t;
+        sc.ref.resize(ci.size());
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t ti = tile_of[pos[i]];
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+                const int32_t k = ci[p];
+                const int32_t pk = pos[k];
+                sc.ref[p] = tile_of[pk] == ti ? -(pk - sc.tile_row[ti] + 1) : k;
+            }
+        }
+        return true;
     };
-    schedule(true, a.l_rows, a.l_task, a.levels_l);
-    schedule(false, a.u_rows, a.u_task, a.levels_u);
+    if (!schedule(true, a.lsched) || !schedule(false, a.usched)) return AN_EINVAL;
     return AN_OK;
 }
 

@@ -11,7 +11,24 @@ namespace kkt {
 struct AnalysisOptions {
     int64_t nd_leaf = 64;
     double pivot_tau = 0.1;
-    int trsv_rows_per_task = 8;  // rows handled together by one wavefront in a solve task
+    int tile_threads = 256;      // threads of a triangular-solve block
+    int narrow_rows = 256;       // levels with at most this many rows join multi-level tiles
+    int tile_rows = 2048;        // rows of a multi-level tile (its values live in LDS)
+};
+
+// Schedule of one triangular solve.  Rows are sorted by DAG level.  A tile is a contiguous
+// run of rows processed by one block: either a run of whole narrow levels (processed level
+// by level with a block barrier in between, values kept in LDS) or a slice of one wide level.
+struct TriSchedule {
+    std::vector<int32_t> rows;      // solve order
+    std::vector<int32_t> lev_ptr;   // start of each level in rows (levels + 1)
+    std::vector<int8_t> lev_lg;     // log2 of the lanes per row of each level
+    std::vector<int32_t> tile_row;  // start of each tile in rows (tiles + 1)
+    std::vector<int32_t> tile_lev;  // level of each tile's first row
+    std::vector<int32_t> ref;       // per CSR entry: source row (>= 0), or -(slot + 1) when the
+                                    // source row is in the same tile (LDS slot)
+    int64_t levels = 0;
+    int64_t tiles() const { return (int64_t)tile_row.size() - 1; }
 };
 
 // Everything derived from the pattern and the first system's values.
@@ -56,11 +73,8 @@ struct Analysis {
     std::vector<int32_t> lci, uci;  // column indices (steps), ascending per row
     std::vector<int32_t> f2t;
 
-    // Triangular-solve schedules: rows sorted by (level, row); tasks = runs of at most
-    // trsv_rows_per_task rows from one level.
-    std::vector<int32_t> l_rows, u_rows;
-    std::vector<int32_t> l_task, u_task;  // task boundaries into *_rows (ntasks+1)
-    int64_t levels_l = 0, levels_u = 0;
+    // Triangular-solve schedules (L forward, U backward).
+    TriSchedule lsched, usched;
 
     // Exchange layout -> F position (for copying device values back).
     std::vector<int64_t> l2f, u2f;

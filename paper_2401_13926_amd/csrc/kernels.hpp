@@ -9,8 +9,10 @@ namespace kkt {
 
 constexpr int kRestartMax = 64;        // largest supported FGMRES restart length
 constexpr int kStreamBlock = 256;      // threads per block of the streaming kernels
-constexpr int kStreamGridMax = 1024;   // blocks of the streaming kernels (partials rows)
-constexpr int kCoopBlock = 256;        // threads per block of the dependency-driven kernels
+constexpr int kStreamGridMax = 256;    // blocks of the streaming kernels (partial-sum rows)
+constexpr int kCoopBlock = 256;        // threads per block of the refactorization
+constexpr int kTileThreads = 256;      // threads per block of the triangular solves
+constexpr int kTileRows = 2048;        // rows of a multi-level solve tile (values in LDS)
 constexpr int kRefactorLds = 1024;     // factor entries staged in LDS per wavefront
 // Spin limit of one dependency wait (iterations of a short sleep, a few seconds in all);
 // exceeding it marks Control::hang and lets every wave run to completion.

@@ -9,14 +9,15 @@
 // Kernels (all wave64):
 //   k_ingest / k_rownorm     new values -> factor storage (fill = 0), ||K||_inf, finiteness
 //   k_refactor<T>            eager left-looking numeric LU, one wavefront per column, columns
-//                            in dependency-level order on a co-resident grid; a column starts
-//                            its update chain at once and waits per source column on a done
-//                            flag (acquire fence once per batch of ready sources)
+//                            handed out in dependency-level order; a column starts its update
+//                            chain at once and waits per entry of each source column (every
+//                            finished L entry is its own ready flag, so no memory fences)
 //   k_trsv<T, LOWER>         row-oriented triangular solve; rows in level order, a wavefront
 //                            takes up to 64/g rows of one level (g lanes per row); a solution
 //                            entry is its own ready flag (a NaN sentinel until written)
-//   k_spmv_dots, k_cgs_*, k_normalize, k_resid, k_lsq, k_xupdate   Krylov kernels with
-//                            deterministic two-level reductions (last block reduces)
+//   k_spmv_dots, k_cgs_*, k_normalize, k_resid, k_xupdate   Krylov kernels; block partial
+//                            sums are reduced by the next kernel in fixed order (deterministic,
+//                            no fences)
 //
 // Floating point: compiled with -ffp-contract=off, so the refactorization performs exactly
 // the roundings of a left-looking column LU with ascending updates (reproducible factors).
@@ -63,10 +64,13 @@ template <typename T> __device__ __forceinline__ bool is_sentinel(T v) {
     return __builtin_bit_cast(typename Bits<T>::U, v) == Bits<T>::sent;
 }
 
+// Ready-flag values are published and polled at system scope: on a multi-XCD device a
+// device-scope store can sit in the producer XCD's L2 until that line is evicted (observed:
+// about a millisecond), while system-scope accesses go through to memory.
 template <typename T> __device__ __forceinline__ void store_ready(T *p, T v) {
     using U = typename Bits<T>::U;
     __hip_atomic_store(reinterpret_cast<U *>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+                       __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Value of a solution entry produced by another wavefront: a plain load first (it can only
@@ -81,7 +85,7 @@ template <typename T> __device__ __forceinline__ T load_ready(const T *p, unsign
     unsigned int spins = 0;
     do {
         __builtin_amdgcn_s_sleep(1);
-        b = __hip_atomic_load(reinterpret_cast<const U *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b = __hip_atomic_load(reinterpret_cast<const U *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         if (++spins >= kSpinLimit ||
             ((spins & 1023u) == 0 && __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
             __hip_atomic_store(hang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -119,17 +123,6 @@ __device__ double block_sum(double v, double *red) {
     return s;
 }
 
-// Arrival of a block in a two-level reduction; true in every thread of the last block.
-__device__ bool last_block(unsigned int *counter) {
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
 // Row range of block b when `total` rows are split into gridDim.x contiguous chunks.
 __device__ __forceinline__ void block_rows(int64_t total, int64_t &r0, int64_t &r1) {
     const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
@@ -159,9 +152,11 @@ __global__ void k_prep_refactor(Control *c) {
 }
 
 // kval == nullptr: the values are already in the workspace (re-ingest for a fallback).
+// Also arms the finished-value array of the refactorization with sentinels.
 __global__ void k_ingest(int64_t nnz, const double *vals, double *kval, int64_t f,
                          const int64_t *__restrict__ fsrc, double *__restrict__ F64,
-                         float *__restrict__ F32, int mixed, Control *c) {
+                         float *__restrict__ F32, double *__restrict__ Ld64, float *__restrict__ Ld32,
+                         int mixed, Control *c) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     bool bad = false;
     if (kval)
@@ -173,8 +168,13 @@ __global__ void k_ingest(int64_t nnz, const double *vals, double *kval, int64_t 
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < f; t += stride) {
         const int64_t s = fsrc[t];
         const double v = s >= 0 ? vals[s] : 0.0;
-        if (mixed) F32[t] = (float)v;
-        else F64[t] = v;
+        if (mixed) {
+            F32[t] = (float)v;
+            Ld32[t] = sentinel<float>();
+        } else {
+            F64[t] = v;
+            Ld64[t] = sentinel<double>();
+        }
     }
     if (bad) atomicOr(&c->nonfinite, 1u);
 }
@@ -207,8 +207,7 @@ template <typename T> struct RefactorArgs {
     const int32_t *f2t;
     T *F;                // factor values (ingested on entry, final on exit)
     T *Tv;               // solve layout copy
-    unsigned int *flag;  // per column: epoch when done
-    unsigned int epoch;
+    T *Ld;               // finished L values in F layout; sentinel until written (ready flags)
     unsigned int chunk;  // columns taken per grab
     int guard_fail_policy;
     Control *ctl;
@@ -218,52 +217,76 @@ template <typename T> __device__ __forceinline__ T unit_roundoff();
 template <> __device__ __forceinline__ double unit_roundoff<double>() { return 0x1p-53; }
 template <> __device__ __forceinline__ float unit_roundoff<float>() { return 0x1p-24f; }
 
-// Applies the update chain of column j to x (LDS or the column's own global storage).
+// Applies the update chain of column j to x (LDS or the column's own global storage): for
+// each source step k of U(:,j) in ascending order, x[relpos] -= L(:,k) * x[k].  The values
+// of L(:,k) come from the finished-value array; an entry still holding the sentinel is
+// polled until its column's wavefront has written it (no fences: every entry is its own
+// flag, written once with a coherent store).
 template <typename T, bool kLds>
 __device__ void refactor_chain(const RefactorArgs<T> &a, int j, int64_t c0, int nu, T *x) {
     const int lane = threadIdx.x & 63;
+    unsigned int *hang = &a.ctl->hang;
     int64_t rp = a.relptr[j];
-    int t0 = 0;
-    unsigned int spins = 0;
-    while (t0 < nu) {
+    for (int t0 = 0; t0 < nu; t0 += 64) {
         const int cnt = nu - t0 < 64 ? nu - t0 : 64;
-        bool ready = true;
+        // lane s holds the metadata of source step t0 + s: its L part [l0, l0 + nl)
+        int64_t l0_l = 0;
+        int nl_l = 0;
         if (lane < cnt) {
             const int k = a.fi[c0 + t0 + lane];
-            ready = __hip_atomic_load(a.flag + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.epoch;
+            l0_l = a.fp[k] + a.fdiag[k] + 1;
+            nl_l = (int)(a.fp[k + 1] - l0_l);
         }
-        const unsigned long long waiting = __ballot(!ready);
-        int nready = waiting ? __builtin_ctzll(waiting) : cnt;
-        if (nready == 0) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins >= kSpinLimit ||
-                ((spins & 1023u) == 0 &&
-                 __hip_atomic_load(&a.ctl->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                if (lane == 0) __hip_atomic_store(&a.ctl->hang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                nready = cnt;  // give up: finish with whatever values are there
-            } else {
-                continue;
+        // offset of each step's update positions: exclusive prefix sum of nl over lanes
+        int off_l = nl_l;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(off_l, o, 64);
+            if (lane >= o) off_l += v;
+        }
+        off_l -= nl_l;
+        // first 64 updates of step 0; each step prefetches the next step's
+        int64_t l0 = __shfl(l0_l, 0, 64);
+        int nl = __shfl(nl_l, 0, 64);
+        int64_t ro = rp + __shfl(off_l, 0, 64);
+        T lv = lane < nl ? a.Ld[l0 + lane] : T(0);
+        int pos = lane < nl ? a.relpos[ro + lane] : 0;
+        for (int s = 0; s < cnt; ++s) {
+            int64_t l0n = 0, ron = 0;
+            int nln = 0;
+            T lvn = T(0);
+            int posn = 0;
+            if (s + 1 < cnt) {
+                l0n = __shfl(l0_l, s + 1, 64);
+                nln = __shfl(nl_l, s + 1, 64);
+                ron = rp + __shfl(off_l, s + 1, 64);
+                if (lane < nln) {
+                    lvn = a.Ld[l0n + lane];
+                    posn = a.relpos[ron + lane];
+                }
             }
-        }
-        spins = 0;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the ready sources' values
-        for (int s = 0; s < nready; ++s) {
-            const int k = a.fi[c0 + t0 + s];
+            if (lane < nl && is_sentinel(lv)) lv = load_ready(a.Ld + l0 + lane, hang);
             const T u = x[t0 + s];
-            const int64_t l0 = a.fp[k] + a.fdiag[k] + 1;
-            const int64_t nl = a.fp[k + 1] - l0;
-            for (int64_t e = lane; e < nl; e += 64) {
-                const T lv = a.F[l0 + e];
-                const int pos = a.relpos[rp + e];
+            if (lane < nl) {
                 const T prod = lv * u;
                 x[pos] = x[pos] - prod;
             }
-            rp += nl;
+            for (int e = 64 + lane; e < nl; e += 64) {
+                T lv2 = a.Ld[l0 + e];
+                if (is_sentinel(lv2)) lv2 = load_ready(a.Ld + l0 + e, hang);
+                const int p2 = a.relpos[ro + e];
+                const T prod = lv2 * u;
+                x[p2] = x[p2] - prod;
+            }
             if (kLds) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
+            l0 = l0n;
+            nl = nln;
+            ro = ron;
+            lv = lvn;
+            pos = posn;
         }
-        t0 += nready;
+        rp += __shfl(off_l + nl_l, cnt - 1, 64);
     }
 }
 
@@ -314,10 +337,8 @@ __global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
             else if (e > nu) v = v / d;
             a.F[c0 + e] = v;
             a.Tv[a.f2t[c0 + e]] = v;
+            if (e > nu) store_ready(a.Ld + c0 + e, v);  // publishes L(:,j) entry by entry
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // column j visible before its flag
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) __hip_atomic_store(a.flag + j, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -327,59 +348,99 @@ __global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
 // ---------------------------------------------------------------------------------------
 
 template <typename T> struct TrsvArgs {
-    int64_t ntasks;
-    const int32_t *task;   // task boundaries into rows
-    const int8_t *tlog;    // log2 of lanes per row of each task
-    const int32_t *rows;
+    int64_t ntiles;
+    const int32_t *tile_row;  // tile start in rows (ntiles + 1)
+    const int32_t *tile_lev;  // level of each tile's first row
+    const int32_t *lev_ptr;   // level start in rows
+    const int8_t *lev_lg;     // log2 lanes per row of each level
+    const int32_t *rows;      // solve order
     const int64_t *rp;
-    const int32_t *ci;
+    const int32_t *ref;       // source row, or -(LDS slot + 1) inside the tile
     const T *val;
-    const T *diag;         // upper only
-    const double *rhs64;   // lower: right-hand side in original order (gathered by prow)
-    const int32_t *prow;   // lower: pivot rows
-    const T *rhs_step;     // upper: L-solve result (step order)
-    T *out;                // step-order result; sentinel on entry
-    double *xout;          // upper: solution scattered to original order by q
+    const T *diag;            // upper only
+    const double *rhs64;      // lower: right-hand side in original order (gathered by prow)
+    const int32_t *prow;      // lower: pivot rows
+    const T *rhs_step;        // upper: L-solve result (step order)
+    T *out;                   // step-order result; sentinel on entry
+    double *xout;             // upper: solution scattered to original order by q
     const int32_t *q;
     const Control *stopflag;  // when non-null, skip if the FGMRES cycle has stopped
-    unsigned int *work;       // task counter (zeroed before the launch)
+    unsigned int *work;       // tile counter (zeroed before the launch)
     unsigned int *hang;
-    unsigned int chunk;       // tasks taken per grab
 };
 
+// Solution entry of another tile: coherent (system-scope) polling until it is written.
+template <typename T> __device__ __forceinline__ T load_remote(const T *p, unsigned int *hang) {
+    using U = typename Bits<T>::U;
+    U b = __hip_atomic_load(reinterpret_cast<const U *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (b != Bits<T>::sent) return __builtin_bit_cast(T, b);
+    return load_ready(p, hang);
+}
+
+// Triangular solve by tiles.  Tiles are handed out in level order to running blocks.  A
+// multi-level tile walks its levels with a block barrier in between and keeps its values in
+// LDS (dependencies inside the tile are LDS slots); dependencies on other tiles read the
+// global solution, whose entries are their own ready flags.  Rows of one level are
+// independent, so the lane groups of a wavefront never wait on each other.
 template <typename T, bool kLower>
-__global__ void __launch_bounds__(kCoopBlock) k_trsv(TrsvArgs<T> a) {
+__global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
+    __shared__ T lds[kTileRows];
+    __shared__ unsigned int tile_sh;
     if (a.stopflag && a.stopflag->stop) return;
-    const int lane = threadIdx.x & 63;
-    // tasks in level order, handed to running wavefronts only (see k_refactor)
+    const int tid = threadIdx.x;
     for (;;) {
-      const unsigned int t0w = grab(a.work, a.chunk);
-      if ((int64_t)t0w >= a.ntasks) break;
-      const int64_t tend = (int64_t)t0w + a.chunk < a.ntasks ? (int64_t)t0w + a.chunk : a.ntasks;
-      for (int64_t t = t0w; t < tend; ++t) {
-        const int lg = a.tlog[t];
-        const int g = 1 << lg;
-        const int grp = lane >> lg, sub = lane & (g - 1);
-        const int idx = a.task[t] + grp;
-        const bool active = idx < a.task[t + 1];
-        const int i = active ? a.rows[idx] : 0;
-        T acc = 0;
-        if (active) {
-            for (int64_t p = a.rp[i] + sub; p < a.rp[i + 1]; p += g) {
-                const T xk = load_ready(a.out + a.ci[p], a.hang);
-                const T prod = a.val[p] * xk;
-                acc = acc + prod;
+        if (tid == 0) tile_sh = atomicAdd(a.work, 1u);
+        __syncthreads();
+        const unsigned int t = tile_sh;
+        __syncthreads();
+        if ((int64_t)t >= a.ntiles) break;
+        const int32_t rb = a.tile_row[t], re = a.tile_row[t + 1];
+        for (int32_t lev = a.tile_lev[t];; ++lev) {
+            const int32_t lb = a.lev_ptr[lev] > rb ? a.lev_ptr[lev] : rb;
+            if (lb >= re) break;  // (lev <= number of levels here: lev_ptr[levels] = n >= re)
+            const int32_t le = a.lev_ptr[lev + 1] < re ? a.lev_ptr[lev + 1] : re;
+            const int lg = a.lev_lg[lev];
+            const int g = 1 << lg;
+            const int grp = tid >> lg, sub = tid & (g - 1);
+            const int ngrp = kTileThreads >> lg;
+            for (int32_t r = lb + grp; r < le; r += ngrp) {
+                const int i = a.rows[r];
+                T acc = 0;
+                const int64_t pe = a.rp[i + 1];
+                for (int64_t p = a.rp[i] + sub; p < pe; p += 4 * g) {
+                    int c[4];
+                    T v[4], xv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t pp = p + (int64_t)u * g;
+                        c[u] = pp < pe ? a.ref[pp] : INT32_MIN;
+                        v[u] = pp < pe ? a.val[pp] : T(0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (c[u] == INT32_MIN) xv[u] = T(0);
+                        else if (c[u] < 0) xv[u] = lds[-c[u] - 1];
+                        else xv[u] = load_remote(a.out + c[u], a.hang);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (c[u] != INT32_MIN) {
+                            const T prod = v[u] * xv[u];
+                            acc = acc + prod;
+                        }
+                }
+                for (int o = 1; o < g; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
+                if (sub == 0) {
+                    T res;
+                    if (kLower) res = (T)a.rhs64[a.prow[i]] - acc;
+                    else res = (a.rhs_step[i] - acc) / a.diag[i];
+                    lds[r - rb] = res;
+                    store_ready(a.out + i, res);
+                    if (!kLower) a.xout[a.q[i]] = (double)res;
+                }
             }
+            __syncthreads();
         }
-        for (int o = 1; o < g; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
-        if (active && sub == 0) {
-            T r;
-            if (kLower) r = (T)a.rhs64[a.prow[i]] - acc;
-            else r = (a.rhs_step[i] - acc) / a.diag[i];
-            store_ready(a.out + i, r);
-            if (!kLower) a.xout[a.q[i]] = (double)r;
-        }
-      }
     }
 }
 
@@ -397,9 +458,12 @@ __global__ void k_fill_sentinel(int64_t n, T *a, T *b, Control *ctl) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Krylov kernels (FP64).  Streaming grid: G blocks of kStreamBlock threads, block b owns a
-// contiguous chunk of rows; partial sums go to part[b * kPartStride + t] and the last block
-// to arrive reduces them in block order (deterministic).
+// Krylov kernels (FP64).  Streaming grid: G <= kStreamGridMax blocks of kStreamBlock threads,
+// block b owns a contiguous chunk of rows and writes its partial sums to
+// part[b * kPartStride + t] with plain stores; the NEXT kernel reduces the partials in every
+// block, in block order (deterministic, identical in every block), so no reduction needs a
+// memory fence: the kernel boundary makes the partials visible.  Three partial buffers
+// rotate so a kernel never overwrites the partials it is reading.
 // ---------------------------------------------------------------------------------------
 
 constexpr int kPartStride = kRestartMax + 4;
@@ -412,14 +476,30 @@ struct KrylovArgs {
     double *V;        // (R+1) columns of n
     double *Z;        // R columns of n
     double *w;
-    double *part;
+    double *part;     // 3 buffers of kStreamGridMax * kPartStride
     Control *ctl;
 };
 
-// w = K z_j; partial dots V_t . w (t <= j) and w . w
+__device__ __forceinline__ double *partbuf(const KrylovArgs &a, int which) {
+    return a.part + (int64_t)which * kStreamGridMax * kPartStride;
+}
+
+// Sum of partial column t over the G blocks of the previous kernel (fixed order).
+__device__ __forceinline__ double reduce_part(const double *buf, int G, int t) {
+    double s = 0.0;
+    for (int b = 0; b < G; ++b) s += buf[(int64_t)b * kPartStride + t];
+    return s;
+}
+
+// Reduces columns 0..m-1 of buf into out[] (shared memory), one column per thread.
+__device__ void reduce_cols(const double *buf, int G, int m, double *out) {
+    for (int t = threadIdx.x; t < m; t += blockDim.x) out[t] = reduce_part(buf, G, t);
+    __syncthreads();
+}
+
+// w = K z_j; partials (buffer 0): V_t . w for t <= j, and w . w at t = j + 1
 __global__ void __launch_bounds__(kStreamBlock) k_spmv_dots(KrylovArgs a, int j) {
     __shared__ double red[kStreamBlock / 64];
-    if (a.ctl->stop) return;
     int64_t r0, r1;
     block_rows(a.n, r0, r1);
     const double *z = a.Z + (int64_t)j * a.n;
@@ -432,33 +512,28 @@ __global__ void __launch_bounds__(kStreamBlock) k_spmv_dots(KrylovArgs a, int j)
         a.w[i] = s;
     }
     __syncthreads();
+    double *out = partbuf(a, 0) + (int64_t)blockIdx.x * kPartStride;
     for (int t = 0; t <= j + 1; ++t) {
         const double *v = t <= j ? a.V + (int64_t)t * a.n : a.w;
         double s = 0.0;
         for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) s += v[i] * a.w[i];
         s = block_sum(s, red);
-        if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * kPartStride + t] = s;
-    }
-    if (last_block(&a.ctl->counter)) {
-        for (int t = threadIdx.x; t <= j + 1; t += blockDim.x) {
-            double s = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += a.part[(int64_t)b * kPartStride + t];
-            if (t <= j) a.ctl->h1[t] = s;
-            else a.ctl->wnorm_in = sqrt(s);
-        }
-        if (threadIdx.x == 0) a.ctl->counter = 0;
+        if (threadIdx.x == 0) out[t] = s;
     }
 }
 
-// w -= V h1; partial dots V_t . w for the second Gram-Schmidt pass
+// h1 = reduce(buffer 0); w -= V h1; partials (buffer 1): V_t . w (second CGS pass)
 __global__ void __launch_bounds__(kStreamBlock) k_cgs_pass2(KrylovArgs a, int j) {
     __shared__ double red[kStreamBlock / 64];
-    __shared__ double h[kRestartMax + 1];
-    if (a.ctl->stop) return;
+    __shared__ double h[kRestartMax + 2];
+    const int G = gridDim.x;
+    reduce_cols(partbuf(a, 0), G, j + 2, h);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int t = 0; t <= j; ++t) a.ctl->h1[t] = h[t];
+        a.ctl->wnorm_in = sqrt(h[j + 1]);
+    }
     int64_t r0, r1;
     block_rows(a.n, r0, r1);
-    for (int t = threadIdx.x; t <= j; t += blockDim.x) h[t] = a.ctl->h1[t];
-    __syncthreads();
     for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
         double s = a.w[i];
         for (int t = 0; t <= j; ++t) {
@@ -468,32 +543,26 @@ __global__ void __launch_bounds__(kStreamBlock) k_cgs_pass2(KrylovArgs a, int j)
         a.w[i] = s;
     }
     __syncthreads();
+    double *out = partbuf(a, 1) + (int64_t)blockIdx.x * kPartStride;
     for (int t = 0; t <= j; ++t) {
         const double *v = a.V + (int64_t)t * a.n;
         double s = 0.0;
         for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) s += v[i] * a.w[i];
         s = block_sum(s, red);
-        if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * kPartStride + t] = s;
-    }
-    if (last_block(&a.ctl->counter)) {
-        for (int t = threadIdx.x; t <= j; t += blockDim.x) {
-            double s = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += a.part[(int64_t)b * kPartStride + t];
-            a.ctl->h2[t] = s;
-        }
-        if (threadIdx.x == 0) a.ctl->counter = 0;
+        if (threadIdx.x == 0) out[t] = s;
     }
 }
 
-// w -= V h2; ||w||; then (last block) Hessenberg column, Givens rotations, estimate, stop
-__global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j, int restart) {
+// h2 = reduce(buffer 1); w -= V h2; partial (buffer 2): w . w
+__global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j) {
     __shared__ double red[kStreamBlock / 64];
     __shared__ double h[kRestartMax + 1];
-    if (a.ctl->stop) return;
+    const int G = gridDim.x;
+    reduce_cols(partbuf(a, 1), G, j + 1, h);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int t = 0; t <= j; ++t) a.ctl->h2[t] = h[t];
     int64_t r0, r1;
     block_rows(a.n, r0, r1);
-    for (int t = threadIdx.x; t <= j; t += blockDim.x) h[t] = a.ctl->h2[t];
-    __syncthreads();
     double ss = 0.0;
     for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
         double s = a.w[i];
@@ -505,12 +574,19 @@ __global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j
         ss += s * s;
     }
     ss = block_sum(ss, red);
-    if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * kPartStride] = ss;
-    if (last_block(&a.ctl->counter) && threadIdx.x == 0) {
-        Control *c = a.ctl;
-        double s = 0.0;
-        for (unsigned b = 0; b < gridDim.x; ++b) s += a.part[(int64_t)b * kPartStride];
-        const double hn = sqrt(s);
+    if (threadIdx.x == 0) partbuf(a, 2)[(int64_t)blockIdx.x * kPartStride] = ss;
+}
+
+// hn = ||w|| (reduce buffer 2); Hessenberg column h1 + h2, previous rotations, a new
+// Givens rotation, the estimated residual |g_{j+1}| and the stop test -- computed
+// identically in every block (only block 0 stores them); then v_{j+1} = w / hn unless the
+// step broke down, and the solve sentinels are re-armed when the cycle goes on.
+template <typename T>
+__global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j, int restart, T *s1, T *s2) {
+    __shared__ double sh[3];
+    Control *c = a.ctl;
+    if (threadIdx.x == 0) {
+        const double hn = sqrt(reduce_part(partbuf(a, 2), gridDim.x, 0));
         double col[kRestartMax + 1];
         for (int t = 0; t <= j; ++t) col[t] = c->h1[t] + c->h2[t];
         col[j + 1] = hn;
@@ -525,37 +601,37 @@ __global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j
             cs = col[j] / rr;
             sn = col[j + 1] / rr;
         }
-        c->cs[j] = cs;
-        c->sn[j] = sn;
         col[j] = rr;
         const double gj = c->g[j];
-        c->g[j + 1] = -sn * gj;
-        c->g[j] = cs * gj;
-        for (int t = 0; t <= j; ++t) c->H[j * (kRestartMax + 1) + t] = col[t];
-        c->hn = hn;
-        c->est = fabs(c->g[j + 1]);
-        c->jdone = j + 1;
+        const double gj1 = -sn * gj;
+        const double est = fabs(gj1);
         const int brk = !(hn > 1e-14 * c->wnorm_in);
-        c->breakdown = brk;
-        if (c->est <= c->inner_tol || brk || j + 1 >= restart) c->stop = 1;
-        c->counter = 0;
+        const int stop = est <= c->inner_tol || brk || j + 1 >= restart;
+        sh[0] = hn;
+        sh[1] = brk;
+        sh[2] = stop;
+        if (blockIdx.x == 0) {
+            c->cs[j] = cs;
+            c->sn[j] = sn;
+            c->g[j + 1] = gj1;
+            c->g[j] = cs * gj;
+            for (int t = 0; t <= j; ++t) c->H[j * (kRestartMax + 1) + t] = col[t];
+            c->hn = hn;
+            c->est = est;
+            c->jdone = j + 1;
+            c->breakdown = brk;
+            c->stop = stop;
+            if (!stop) {
+                c->work_lower = 0;
+                c->work_upper = 0;
+            }
+        }
     }
-}
-
-// v_{j+1} = w / ||w|| (skipped after a breakdown); re-arm the solve sentinels
-template <typename T>
-__global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j, T *s1, T *s2) {
-    const Control *c = a.ctl;
-    if (c->jdone != j + 1) return;  // the cycle ended before step j
-    const bool write_v = !c->breakdown;
-    const bool rearm = !c->stop;
-    if (!write_v && !rearm) return;
-    const double hn = c->hn;
+    __syncthreads();
+    const double hn = sh[0];
+    const bool write_v = sh[1] == 0.0;
+    const bool rearm = sh[2] == 0.0;
     double *v = a.V + (int64_t)(j + 1) * a.n;
-    if (rearm && blockIdx.x == 0 && threadIdx.x == 0) {
-        a.ctl->work_lower = 0;
-        a.ctl->work_upper = 0;
-    }
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
         if (write_v) v[i] = a.w[i] / hn;
@@ -566,7 +642,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j,
     }
 }
 
-// rho = b - K x; partial ||rho||^2, ||x||^2, ||b||^2
+// rho = b - K x; partials (buffer 0): ||rho||^2, ||x||^2, ||b||^2, non-finite b flag
 __global__ void __launch_bounds__(kStreamBlock) k_resid(KrylovArgs a, const double *b, const double *x, double *r) {
     __shared__ double red[kStreamBlock / 64];
     int64_t r0, r1;
@@ -590,25 +666,25 @@ __global__ void __launch_bounds__(kStreamBlock) k_resid(KrylovArgs a, const doub
     sr = block_sum(sr, red);
     sx = block_sum(sx, red);
     sb = block_sum(sb, red);
+    const double bad = block_sum((double)badb, red);
     if (threadIdx.x == 0) {
-        double *p = a.part + (int64_t)blockIdx.x * kPartStride;
+        double *p = partbuf(a, 0) + (int64_t)blockIdx.x * kPartStride;
         p[0] = sr;
         p[1] = sx;
         p[2] = sb;
+        p[3] = bad;
     }
-    if (badb) a.ctl->nonfinite_b = 1;
-    if (last_block(&a.ctl->counter) && threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (unsigned bb = 0; bb < gridDim.x; ++bb) {
-            const double *p = a.part + (int64_t)bb * kPartStride;
-            s0 += p[0];
-            s1 += p[1];
-            s2 += p[2];
-        }
-        a.ctl->rnorm2 = s0;
-        a.ctl->xnorm2 = s1;
-        a.ctl->bnorm2 = s2;
-        a.ctl->counter = 0;
+}
+
+// One block: sums of the residual kernel's partials into the control block.
+__global__ void k_resid_reduce(KrylovArgs a, int G) {
+    __shared__ double h[4];
+    reduce_cols(partbuf(a, 0), G, 4, h);
+    if (threadIdx.x == 0) {
+        a.ctl->rnorm2 = h[0];
+        a.ctl->xnorm2 = h[1];
+        a.ctl->bnorm2 = h[2];
+        if (h[3] != 0.0) a.ctl->nonfinite_b = 1;
     }
 }
 
@@ -638,26 +714,22 @@ __global__ void __launch_bounds__(kStreamBlock) k_cycle_start(KrylovArgs a, cons
     }
 }
 
-// y = H^-1 g (jdone x jdone upper triangular), one thread
-__global__ void k_lsq(Control *c) {
-    if (threadIdx.x != 0) return;
-    const int m = c->jdone;
-    for (int t = m - 1; t >= 0; --t) {
-        double s = c->g[t];
-        for (int u = t + 1; u < m; ++u) {
-            const double prod = c->H[u * (kRestartMax + 1) + t] * c->y[u];
-            s = s - prod;
-        }
-        const double dgn = c->H[t * (kRestartMax + 1) + t];
-        c->y[t] = dgn != 0.0 ? s / dgn : 0.0;
-    }
-}
-
-// x += Z y
+// x += Z y with y = H^-1 g (jdone x jdone upper triangular, solved in every block)
 __global__ void __launch_bounds__(kStreamBlock) k_xupdate(KrylovArgs a, double *x) {
     __shared__ double y[kRestartMax];
-    const int m = a.ctl->jdone;
-    for (int t = threadIdx.x; t < m; t += blockDim.x) y[t] = a.ctl->y[t];
+    const Control *c = a.ctl;
+    const int m = c->jdone;
+    if (threadIdx.x == 0) {
+        for (int t = m - 1; t >= 0; --t) {
+            double s = c->g[t];
+            for (int u = t + 1; u < m; ++u) {
+                const double prod = c->H[u * (kRestartMax + 1) + t] * y[u];
+                s = s - prod;
+            }
+            const double dgn = c->H[t * (kRestartMax + 1) + t];
+            y[t] = dgn != 0.0 ? s / dgn : 0.0;
+        }
+    }
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
@@ -696,12 +768,16 @@ struct DevLayout {
     int32_t *relpos;
     int64_t *lrp, *urp, *krp;
     int32_t *lci, *uci, *kci;
-    int32_t *l_rows, *l_task, *u_rows, *u_task, *prow, *q;
-    int8_t *l_tlog, *u_tlog;
+    int32_t *prow, *q;
+    // triangular-solve schedules (L, U): rows, level starts, lanes, tiles, references
+    int32_t *l_rows, *l_lev, *l_tile, *l_tlev, *l_ref;
+    int32_t *u_rows, *u_lev, *u_tile, *u_tlev, *u_ref;
+    int8_t *l_lg, *u_lg;
     // values
     double *kval, *F64, *T64;
     float *F32, *T32;
-    unsigned int *flag;
+    double *Ld64;
+    float *Ld32;
     // vectors
     double *V, *Z, *w, *r, *y64, *z64;
     float *y32, *z32;
@@ -717,8 +793,6 @@ struct kkt_handle_s {
     kkt_opts_t opts{};
     kkt::Analysis an;
     std::string err;
-    // schedule extras
-    std::vector<int8_t> l_tlog, u_tlog;
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -728,7 +802,6 @@ struct kkt_handle_s {
     bool device_failed = false;
     bool have_factors = false;
     int factor_precision = 0;
-    unsigned int epoch = 0;
     int grid_refactor64 = 0, grid_refactor32 = 0, grid_trsv64 = 0, grid_trsv32 = 0, grid_stream = 0;
     kkt::ControlSummary *host_ctl = nullptr;  // pinned
     int restart_alloc = 0;
@@ -813,39 +886,6 @@ void prof_collect(kkt_handle_t h) {
     h->ev_pending.clear();
 }
 
-// Lanes per row for the rows of one task: enough lanes that a lane handles about four
-// entries of the longest row, at most 64.
-void task_lanes(const std::vector<int64_t> &rp, const std::vector<int32_t> &rows,
-                const std::vector<int32_t> &task, std::vector<int8_t> &tlog) {
-    // retile: tasks are cut so that (rows in task) * lanes <= 64
-    tlog.assign(task.size() - 1, 0);
-    for (size_t t = 0; t + 1 < task.size(); ++t) {
-        int64_t mx = 0;
-        for (int32_t k = task[t]; k < task[t + 1]; ++k) mx = std::max(mx, rp[rows[k] + 1] - rp[rows[k]]);
-        int lg = 0;
-        while ((1 << lg) < 64 && (int64_t)(1 << lg) * 4 < mx) ++lg;
-        tlog[t] = (int8_t)lg;
-    }
-}
-
-// Split tasks so that rows * lanes <= 64 in every task.
-void retile(const std::vector<int64_t> &rp, const std::vector<int32_t> &rows, std::vector<int32_t> &task,
-            std::vector<int8_t> &tlog) {
-    std::vector<int8_t> lg0;
-    task_lanes(rp, rows, task, lg0);
-    std::vector<int32_t> nt{0};
-    std::vector<int8_t> nl;
-    for (size_t t = 0; t + 1 < task.size(); ++t) {
-        const int per = 64 >> lg0[t];
-        for (int32_t s = task[t]; s < task[t + 1]; s += per) {
-            nt.push_back(std::min(s + per, task[t + 1]));
-            nl.push_back(lg0[t]);
-        }
-    }
-    task.swap(nt);
-    tlog.swap(nl);
-}
-
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Planner {
@@ -859,8 +899,8 @@ struct Planner {
 
 // Offsets of every array inside the workspace (also gives the total size).
 struct Offsets {
-    size_t fp, fi, fdiag, order, f2t, relptr, fsrc, relpos, lrp, urp, krp, lci, uci, kci, l_rows, l_task,
-        u_rows, u_task, prow, q, l_tlog, u_tlog, kval, F64, T64, F32, T32, flag, V, Z, w, r, y64, z64, y32,
+    size_t fp, fi, fdiag, order, f2t, relptr, fsrc, relpos, lrp, urp, krp, kci, l_rows, l_lev, l_tile,
+        l_tlev, l_ref, l_lg, u_rows, u_lev, u_tile, u_tlev, u_ref, u_lg, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
         z32, part, ctl, total;
 };
 
@@ -881,23 +921,28 @@ Offsets plan(const kkt_handle_t h) {
     o.lrp = p.take<int64_t>(n + 1);
     o.urp = p.take<int64_t>(n + 1);
     o.krp = p.take<int64_t>(n + 1);
-    o.lci = p.take<int32_t>(a.lci.size());
-    o.uci = p.take<int32_t>(a.uci.size());
     o.kci = p.take<int32_t>(a.nnz);
     o.l_rows = p.take<int32_t>(n);
-    o.l_task = p.take<int32_t>(a.l_task.size());
+    o.l_lev = p.take<int32_t>(a.lsched.lev_ptr.size());
+    o.l_tile = p.take<int32_t>(a.lsched.tile_row.size());
+    o.l_tlev = p.take<int32_t>(a.lsched.tile_lev.size());
+    o.l_ref = p.take<int32_t>(a.lsched.ref.size());
+    o.l_lg = p.take<int8_t>(a.lsched.lev_lg.size());
     o.u_rows = p.take<int32_t>(n);
-    o.u_task = p.take<int32_t>(a.u_task.size());
+    o.u_lev = p.take<int32_t>(a.usched.lev_ptr.size());
+    o.u_tile = p.take<int32_t>(a.usched.tile_row.size());
+    o.u_tlev = p.take<int32_t>(a.usched.tile_lev.size());
+    o.u_ref = p.take<int32_t>(a.usched.ref.size());
+    o.u_lg = p.take<int8_t>(a.usched.lev_lg.size());
     o.prow = p.take<int32_t>(n);
     o.q = p.take<int32_t>(n);
-    o.l_tlog = p.take<int8_t>(h->l_tlog.size());
-    o.u_tlog = p.take<int8_t>(h->u_tlog.size());
     o.kval = p.take<double>(a.nnz);
     o.F64 = p.take<double>(f);
     o.T64 = p.take<double>(f);
     o.F32 = p.take<float>(f);
     o.T32 = p.take<float>(f);
-    o.flag = p.take<unsigned int>(n);
+    o.Ld64 = p.take<double>(f);
+    o.Ld32 = p.take<float>(f);
     o.V = p.take<double>((size_t)(R + 1) * n);
     o.Z = p.take<double>((size_t)R * n);
     o.w = p.take<double>(n);
@@ -906,7 +951,7 @@ Offsets plan(const kkt_handle_t h) {
     o.z64 = p.take<double>(n);
     o.y32 = p.take<float>(n);
     o.z32 = p.take<float>(n);
-    o.part = p.take<double>((size_t)kStreamGridMax * kPartStride);
+    o.part = p.take<double>((size_t)3 * kStreamGridMax * kPartStride);
     o.ctl = p.take<Control>(1);
     o.total = p.off;
     return o;
@@ -917,6 +962,7 @@ template <typename T> hipError_t up(char *base, size_t off, const std::vector<T>
     return hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
+// Blocks of 256 threads that fit on the device at once (a persistent grid size).
 int coop_grid(const void *func, int device) {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kCoopBlock, 0) != hipSuccess) return 0;
@@ -955,38 +1001,36 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     const Analysis &a = h->an;
     TrsvArgs<T> t{};
     const bool is64 = sizeof(T) == 8;
+    const TriSchedule &sc = lower ? a.lsched : a.usched;
+    t.ntiles = sc.tiles();
+    const DevLayout &d = h->d;
+    t.tile_row = lower ? d.l_tile : d.u_tile;
+    t.tile_lev = lower ? d.l_tlev : d.u_tlev;
+    t.lev_ptr = lower ? d.l_lev : d.u_lev;
+    t.lev_lg = lower ? d.l_lg : d.u_lg;
+    t.rows = lower ? d.l_rows : d.u_rows;
+    t.ref = lower ? d.l_ref : d.u_ref;
+    const T *base = (const T *)(is64 ? (void *)d.T64 : (void *)d.T32);
     if (lower) {
-        t.ntasks = (int64_t)a.l_task.size() - 1;
-        t.task = h->d.l_task;
-        t.tlog = h->d.l_tlog;
-        t.rows = h->d.l_rows;
-        t.rp = h->d.lrp;
-        t.ci = h->d.lci;
-        t.val = (const T *)(is64 ? (void *)h->d.T64 : (void *)h->d.T32);
+        t.rp = d.lrp;
+        t.val = base;
         t.rhs64 = rhs64;
-        t.prow = h->d.prow;
+        t.prow = d.prow;
     } else {
-        t.ntasks = (int64_t)a.u_task.size() - 1;
-        t.task = h->d.u_task;
-        t.tlog = h->d.u_tlog;
-        t.rows = h->d.u_rows;
-        t.rp = h->d.urp;
-        t.ci = h->d.uci;
-        const T *base = (const T *)(is64 ? (void *)h->d.T64 : (void *)h->d.T32);
+        t.rp = d.urp;
         t.val = base + a.lrp[a.n];
         t.diag = base + a.lrp[a.n] + a.urp[a.n];
         t.rhs_step = rhs_step;
         t.xout = xout;
-        t.q = h->d.q;
+        t.q = d.q;
     }
     t.out = out;
     t.stopflag = stopflag;
-    t.work = lower ? &h->d.ctl->work_lower : &h->d.ctl->work_upper;
-    t.hang = &h->d.ctl->hang;
-    const int grid = is64 ? h->grid_trsv64 : h->grid_trsv32;
-    t.chunk = work_chunk(t.ntasks, grid * (kCoopBlock / 64));
-    if (lower) k_trsv<T, true><<<grid, kCoopBlock, 0, s>>>(t);
-    else k_trsv<T, false><<<grid, kCoopBlock, 0, s>>>(t);
+    t.work = lower ? &d.ctl->work_lower : &d.ctl->work_upper;
+    t.hang = &d.ctl->hang;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(is64 ? h->grid_trsv64 : h->grid_trsv32, t.ntiles));
+    if (lower) k_trsv<T, true><<<grid, kTileThreads, 0, s>>>(t);
+    else k_trsv<T, false><<<grid, kTileThreads, 0, s>>>(t);
     return hipGetLastError();
 }
 
@@ -1023,24 +1067,24 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
     hipEvent_t e0 = prof_begin(h, s);
     k_prep_refactor<<<1, 1, 0, s>>>(d.ctl);
     if (dev_values)
-        k_ingest<<<2048, 256, 0, s>>>(a.nnz, dev_values, d.kval, f, d.fsrc, d.F64, d.F32, precision, d.ctl);
+        k_ingest<<<2048, 256, 0, s>>>(a.nnz, dev_values, d.kval, f, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32,
+                                      precision, d.ctl);
     else
-        k_ingest<<<2048, 256, 0, s>>>(a.nnz, d.kval, nullptr, f, d.fsrc, d.F64, d.F32, precision, d.ctl);
+        k_ingest<<<2048, 256, 0, s>>>(a.nnz, d.kval, nullptr, f, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32,
+                                      precision, d.ctl);
     k_rownorm<<<rows_grid, 256, 0, s>>>(a.n, d.krp, d.kval, d.ctl);
     prof_end(h, KKT_K_INGEST, e0, s);
     KKT_HIP(h, hipGetLastError());
-    h->epoch += 1;
-    if (h->epoch == 0) h->epoch = 1;
     e0 = prof_begin(h, s);
     if (precision == KKT_PREC_MIXED) {
         const unsigned int chunk = work_chunk(a.n, h->grid_refactor32 * (kCoopBlock / 64));
         RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F32, d.T32,
-                              d.flag, h->epoch, chunk, h->opts.guard_policy, d.ctl};
+                              d.Ld32, chunk, h->opts.guard_policy, d.ctl};
         k_refactor<float><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r);
     } else {
         const unsigned int chunk = work_chunk(a.n, h->grid_refactor64 * (kCoopBlock / 64));
         RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F64, d.T64,
-                               d.flag, h->epoch, chunk, h->opts.guard_policy, d.ctl};
+                               d.Ld64, chunk, h->opts.guard_policy, d.ctl};
         k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r);
     }
     prof_end(h, KKT_K_REFACTOR, e0, s);
@@ -1082,6 +1126,7 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
     e0 = prof_begin(h, s);
     k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+    k_resid_reduce<<<1, 64, 0, s>>>(ka, G);
     prof_end(h, KKT_K_RESID, e0, s);
     KKT_HIP(h, hipGetLastError());
     kkt_status_t st = read_ctl(h, s);
@@ -1130,8 +1175,8 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
             prof_end(h, KKT_K_SPMV, e0, s);
             e0 = prof_begin(h, s);
             k_cgs_pass2<<<G, kStreamBlock, 0, s>>>(ka, j);
-            k_cgs_finish<<<G, kStreamBlock, 0, s>>>(ka, j, R);
-            k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, y, z);
+            k_cgs_finish<<<G, kStreamBlock, 0, s>>>(ka, j);
+            k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, R, y, z);
             prof_end(h, KKT_K_CGS, e0, s);
             KKT_HIP(h, hipGetLastError());
             st = read_ctl(h, s);
@@ -1139,11 +1184,11 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
             if (h->host_ctl->stop) break;
         }
         e0 = prof_begin(h, s);
-        k_lsq<<<1, 64, 0, s>>>(d.ctl);
         k_xupdate<<<G, kStreamBlock, 0, s>>>(ka, x);
         prof_end(h, KKT_K_OTHER, e0, s);
         e0 = prof_begin(h, s);
         k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+        k_resid_reduce<<<1, 64, 0, s>>>(ka, G);
         prof_end(h, KKT_K_RESID, e0, s);
         KKT_HIP(h, hipGetLastError());
         st = read_ctl(h, s);
@@ -1207,19 +1252,14 @@ kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowpt
     AnalysisOptions ao;
     ao.nd_leaf = h->opts.nd_leaf;
     ao.pivot_tau = h->opts.pivot_tau;
+    ao.tile_threads = kTileThreads;
+    ao.tile_rows = kTileRows;
     std::string msg;
     int rc = analyze(ao, n, rowptr, colidx, values_first, h->an, &msg);
     if (rc != AN_OK) {
         delete h;
         const kkt_status_t s = rc == AN_EINVAL ? KKT_EINVAL : rc == AN_ESINGULAR ? KKT_ESINGULAR : KKT_ENOMEM;
         return fail(nullptr, s, msg);
-    }
-    try {
-        retile(h->an.lrp, h->an.l_rows, h->an.l_task, h->l_tlog);
-        retile(h->an.urp, h->an.u_rows, h->an.u_task, h->u_tlog);
-    } catch (const std::bad_alloc &) {
-        delete h;
-        return fail(nullptr, KKT_ENOMEM, "out of host memory");
     }
     *out = h;
     return KKT_OK;
@@ -1234,8 +1274,8 @@ kkt_status_t kkt_get_analysis_info(kkt_handle_t h, kkt_analysis_info_t *info) {
     info->nnz_u = a.nnz_u();
     info->offdiag_pivots = a.offdiag_pivots;
     info->levels_refactor = a.levels_refactor;
-    info->levels_l = a.levels_l;
-    info->levels_u = a.levels_u;
+    info->levels_l = a.lsched.levels;
+    info->levels_u = a.usched.levels;
     info->updates = a.updates();
     info->analysis_seconds = a.seconds;
     return KKT_OK;
@@ -1294,23 +1334,28 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.lrp = (int64_t *)(b + o.lrp);
     d.urp = (int64_t *)(b + o.urp);
     d.krp = (int64_t *)(b + o.krp);
-    d.lci = (int32_t *)(b + o.lci);
-    d.uci = (int32_t *)(b + o.uci);
     d.kci = (int32_t *)(b + o.kci);
     d.l_rows = (int32_t *)(b + o.l_rows);
-    d.l_task = (int32_t *)(b + o.l_task);
+    d.l_lev = (int32_t *)(b + o.l_lev);
+    d.l_tile = (int32_t *)(b + o.l_tile);
+    d.l_tlev = (int32_t *)(b + o.l_tlev);
+    d.l_ref = (int32_t *)(b + o.l_ref);
+    d.l_lg = (int8_t *)(b + o.l_lg);
     d.u_rows = (int32_t *)(b + o.u_rows);
-    d.u_task = (int32_t *)(b + o.u_task);
+    d.u_lev = (int32_t *)(b + o.u_lev);
+    d.u_tile = (int32_t *)(b + o.u_tile);
+    d.u_tlev = (int32_t *)(b + o.u_tlev);
+    d.u_ref = (int32_t *)(b + o.u_ref);
+    d.u_lg = (int8_t *)(b + o.u_lg);
     d.prow = (int32_t *)(b + o.prow);
     d.q = (int32_t *)(b + o.q);
-    d.l_tlog = (int8_t *)(b + o.l_tlog);
-    d.u_tlog = (int8_t *)(b + o.u_tlog);
     d.kval = (double *)(b + o.kval);
     d.F64 = (double *)(b + o.F64);
     d.T64 = (double *)(b + o.T64);
     d.F32 = (float *)(b + o.F32);
     d.T32 = (float *)(b + o.T32);
-    d.flag = (unsigned int *)(b + o.flag);
+    d.Ld64 = (double *)(b + o.Ld64);
+    d.Ld32 = (float *)(b + o.Ld32);
     d.V = (double *)(b + o.V);
     d.Z = (double *)(b + o.Z);
     d.w = (double *)(b + o.w);
@@ -1332,22 +1377,24 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.lrp, a.lrp, s));
     KKT_HIP(h, up(b, o.urp, a.urp, s));
     KKT_HIP(h, up(b, o.krp, a.rowptr, s));
-    KKT_HIP(h, up(b, o.lci, a.lci, s));
-    KKT_HIP(h, up(b, o.uci, a.uci, s));
     KKT_HIP(h, up(b, o.kci, a.colidx, s));
-    KKT_HIP(h, up(b, o.l_rows, a.l_rows, s));
-    KKT_HIP(h, up(b, o.l_task, a.l_task, s));
-    KKT_HIP(h, up(b, o.u_rows, a.u_rows, s));
-    KKT_HIP(h, up(b, o.u_task, a.u_task, s));
+    KKT_HIP(h, up(b, o.l_rows, a.lsched.rows, s));
+    KKT_HIP(h, up(b, o.l_lev, a.lsched.lev_ptr, s));
+    KKT_HIP(h, up(b, o.l_tile, a.lsched.tile_row, s));
+    KKT_HIP(h, up(b, o.l_tlev, a.lsched.tile_lev, s));
+    KKT_HIP(h, up(b, o.l_ref, a.lsched.ref, s));
+    KKT_HIP(h, up(b, o.l_lg, a.lsched.lev_lg, s));
+    KKT_HIP(h, up(b, o.u_rows, a.usched.rows, s));
+    KKT_HIP(h, up(b, o.u_lev, a.usched.lev_ptr, s));
+    KKT_HIP(h, up(b, o.u_tile, a.usched.tile_row, s));
+    KKT_HIP(h, up(b, o.u_tlev, a.usched.tile_lev, s));
+    KKT_HIP(h, up(b, o.u_ref, a.usched.ref, s));
+    KKT_HIP(h, up(b, o.u_lg, a.usched.lev_lg, s));
     KKT_HIP(h, up(b, o.prow, a.prow, s));
     KKT_HIP(h, up(b, o.q, a.q, s));
-    KKT_HIP(h, up(b, o.l_tlog, h->l_tlog, s));
-    KKT_HIP(h, up(b, o.u_tlog, h->u_tlog, s));
-    KKT_HIP(h, hipMemsetAsync(d.flag, 0, a.n * sizeof(unsigned int), s));
     KKT_HIP(h, hipMemsetAsync(d.ctl, 0, sizeof(Control), s));
-    KKT_HIP(h, hipMemsetAsync(d.part, 0, (size_t)kStreamGridMax * kPartStride * sizeof(double), s));
+    KKT_HIP(h, hipMemsetAsync(d.part, 0, (size_t)3 * kStreamGridMax * kPartStride * sizeof(double), s));
     KKT_HIP(h, hipStreamSynchronize(s));
-    h->epoch = 0;
     h->grid_refactor64 = coop_grid((const void *)k_refactor<double>, h->device);
     h->grid_refactor32 = coop_grid((const void *)k_refactor<float>, h->device);
     h->grid_trsv64 = std::min(coop_grid((const void *)k_trsv<double, true>, h->device),

@@ -1,0 +1,33 @@
+"""CPU checks of the benchmark's host logic."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_multi_gpu_request_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_algorithmic_bytes_counts():
+    ai = dict(n=10, nnz=40, nnz_l=20, nnz_u=30, updates=100)
+    assert bench.algorithmic_bytes("trsv_l", ai) == 20 * 12 + 11 * 8 + 10 * 32
+    assert bench.algorithmic_bytes("trsv_u", ai) == 20 * 12 + 10 * 8 + 11 * 8 + 10 * 40
+    assert bench.algorithmic_bytes("refactor", ai) == 50 * 28 + 100 * 4 + 10 * 28
+    assert bench.algorithmic_bytes("spmv", ai) == 40 * 12 + 11 * 8 + 10 * 24
+    with pytest.raises(KeyError):
+        bench.algorithmic_bytes("nope", ai)
+
+
+def test_percentile():
+    assert bench.percentile([1, 2, 3, 4], 50) == 2.5
+    assert bench.percentile([5], 99) == 5
