@@ -53,8 +53,13 @@ enum { KKT_PREC_FP64 = 0, KKT_PREC_MIXED = 1 };     /* factor / preconditioner p
 enum { KKT_GUARD_PERTURB = 0, KKT_GUARD_FAIL = 1 }; /* tiny static pivot policy */
 enum { KKT_STOP_PAPER = 0, KKT_STOP_NRBE = 1 };     /* FGMRES-IR stopping control */
 
+enum { KKT_ORDER_MD = 0, KKT_ORDER_ND = 1 };      /* fill-reducing ordering */
+
 typedef struct {
-    int32_t nd_leaf;        /* ordering: sets of <= nd_leaf vertices are not dissected (64) */
+    int32_t ordering;       /* KKT_ORDER_MD: exact minimum degree on the elimination graph of
+                               K + K^T (ties: smallest index), default; KKT_ORDER_ND: BFS nested
+                               dissection */
+    int32_t nd_leaf;        /* nested dissection: sets of <= nd_leaf vertices are not dissected (64) */
     double pivot_tau;       /* threshold partial pivoting: keep the diagonal row when
                                |x_c| >= tau * max |x_i| (0.1) */
     int32_t restart;        /* FGMRES restart length R (10, Section 4.1.1) */
@@ -129,7 +134,7 @@ void kkt_opts_default(kkt_opts_t *opts);
 
 /* Analyse a pattern on the host with the values of the first system (Section 1.3: symbolic
  * analysis plus factorization with pivoting on system 1): validates the CSR, computes the
- * nested-dissection ordering Q and a threshold-pivoted left-looking LU of K(:,Q), and builds
+ * fill-reducing ordering Q and a threshold-pivoted left-looking LU of K(:,Q), and builds
  * every schedule the GPU kernels need.  rowptr/colidx/values_first are HOST pointers.  Does
  * not touch the GPU.  On success *out owns a new handle (release with kkt_release).
  * Errors: KKT_EINVAL (bad CSR, N < 1, non-finite value), KKT_ESINGULAR (no nonzero pivot

@@ -47,6 +47,7 @@ def lib():
         L.or_check_csr.argtypes = [i64, i64p, i32p]
         L.or_order.argtypes = [i64, i64p, i32p, i32p]
         L.or_order_leaf.argtypes = [i64, i64p, i32p, i64, i32p]
+        L.or_order_md.argtypes = [i64, i64p, i32p, i32p]
         L.or_factor.restype = C.c_void_p
         L.or_factor.argtypes = [i64, i64p, i32p, f64p, i32p, C.c_double, C.POINTER(C.c_int), i64p]
         L.or_free.argtypes = [C.c_void_p]
@@ -91,12 +92,18 @@ def check_csr(rowptr, colidx) -> bool:
     return lib().or_check_csr(rp.size - 1, _p(rp, C.c_int64), _p(ci, C.c_int32)) == OK
 
 
-def order(rowptr, colidx, leaf: int = 64) -> np.ndarray:
-    """Fill-reducing ordering Q (Q[j] = original column eliminated at step j)."""
+def order(rowptr, colidx, method: str = "md", leaf: int = 64) -> np.ndarray:
+    """Fill-reducing ordering Q (Q[j] = original column eliminated at step j):
+    method "md" = exact minimum degree (default), "nd" = BFS nested dissection."""
     rp, ci, _ = _csr(rowptr, colidx)
     n = rp.size - 1
     Q = np.empty(n, dtype=np.int32)
-    rc = lib().or_order_leaf(n, _p(rp, C.c_int64), _p(ci, C.c_int32), int(leaf), _p(Q, C.c_int32))
+    if method == "md":
+        rc = lib().or_order_md(n, _p(rp, C.c_int64), _p(ci, C.c_int32), _p(Q, C.c_int32))
+    elif method == "nd":
+        rc = lib().or_order_leaf(n, _p(rp, C.c_int64), _p(ci, C.c_int32), int(leaf), _p(Q, C.c_int32))
+    else:
+        raise ValueError(method)
     if rc != OK:
         raise OracleError(rc, "or_order failed: %d" % rc)
     return Q

@@ -105,3 +105,27 @@ def dense_symbolic(Apat: np.ndarray, Q: np.ndarray, prow: np.ndarray):
         pivoted[prow[j]] = True
         Lpat[:, j] = x & ~pivoted
     return Lpat, Upat
+
+
+def md_order_bruteforce(n: int, edges) -> list:
+    """Exact minimum degree by explicit elimination-graph sets: repeatedly take the live
+    vertex of least degree (ties: smallest index), join its neighbours into a clique and
+    drop it.  Pure Python, tiny graphs only."""
+    adj = [set() for _ in range(n)]
+    for a, b in edges:
+        if a != b:
+            adj[a].add(b)
+            adj[b].add(a)
+    alive = set(range(n))
+    order = []
+    while alive:
+        v = min(alive, key=lambda u: (len(adj[u]), u))
+        order.append(v)
+        alive.discard(v)
+        nb = adj[v]
+        for u in nb:
+            adj[u] |= nb
+            adj[u].discard(u)
+            adj[u].discard(v)
+        adj[v] = set()
+    return order

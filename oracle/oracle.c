@@ -381,8 +381,157 @@ int or_order_leaf(int64_t n, const int64_t *rp, const int32_t *ci, int64_t leaf,
     return rc;
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* Ordering: exact minimum degree on the elimination graph.                               */
+/*                                                                                        */
+/* Graph: pattern of A + A^T without the diagonal.  Repeat n times: eliminate the vertex  */
+/* of least current degree (ties: smallest original index); its neighbours become a      */
+/* clique (the fill of symmetric elimination) and lose it as a neighbour.  Written on    */
+/* the explicit elimination graph with sorted adjacency arrays.                          */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t deg;
+    int32_t v;
+} md_item;
+
+static int md_less(md_item a, md_item b) { return a.deg < b.deg || (a.deg == b.deg && a.v < b.v); }
+
+static void md_push(md_item *h, int64_t *hn, md_item x) {
+    int64_t i = (*hn)++;
+    h[i] = x;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!md_less(h[i], h[p])) break;
+        md_item t = h[i];
+        h[i] = h[p];
+        h[p] = t;
+        i = p;
+    }
+}
+
+static md_item md_pop(md_item *h, int64_t *hn) {
+    md_item top = h[0];
+    h[0] = h[--(*hn)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < *hn && md_less(h[l], h[m])) m = l;
+        if (r < *hn && md_less(h[r], h[m])) m = r;
+        if (m == i) break;
+        md_item t = h[i];
+        h[i] = h[m];
+        h[m] = t;
+        i = m;
+    }
+    return top;
+}
+
+int or_order_md(int64_t n, const int64_t *rp, const int32_t *ci, int32_t *Q) {
+    if (or_check_csr(n, rp, ci) != OR_OK) return OR_EINVAL;
+    int64_t *gp;
+    int32_t *gi;
+    int rc = build_sym_graph(n, rp, ci, &gp, &gi);
+    if (rc != OR_OK) return rc;
+    int32_t **adj = (int32_t **)calloc((size_t)n, sizeof(int32_t *));
+    int64_t *len = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    int64_t *cap = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    char *gone = (char *)calloc((size_t)n, 1);
+    int64_t hcap = 4 * n + 16, hn = 0;
+    md_item *heap = (md_item *)malloc((size_t)hcap * sizeof(md_item));
+    int32_t *merged = NULL;
+    int64_t mcap = 0;
+    if (!adj || !len || !cap || !gone || !heap) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    for (int64_t v = 0; v < n; v++) {
+        len[v] = gp[v + 1] - gp[v];
+        cap[v] = len[v] + 4;
+        adj[v] = (int32_t *)malloc((size_t)cap[v] * sizeof(int32_t));
+        if (!adj[v]) {
+            rc = OR_ENOMEM;
+            goto done;
+        }
+        memcpy(adj[v], gi + gp[v], (size_t)len[v] * sizeof(int32_t));
+        md_item it = {len[v], (int32_t)v};
+        md_push(heap, &hn, it);
+    }
+    for (int64_t step = 0; step < n; step++) {
+        md_item it;
+        do {
+            it = md_pop(heap, &hn);
+        } while (gone[it.v] || it.deg != len[it.v]);
+        int32_t p = it.v;
+        Q[step] = p;
+        gone[p] = 1;
+        /* neighbours of p (all alive, sorted) become a clique */
+        int32_t *nb = adj[p];
+        int64_t nn = len[p];
+        for (int64_t a = 0; a < nn; a++) {
+            int32_t u = nb[a];
+            /* new adjacency of u: (adj[u] \ {p}) U (nb \ {u}), sorted merge */
+            int64_t need = len[u] + nn;
+            if (need > mcap) {
+                mcap = 2 * need;
+                int32_t *t = (int32_t *)realloc(merged, (size_t)mcap * sizeof(int32_t));
+                if (!t) {
+                    rc = OR_ENOMEM;
+                    goto done;
+                }
+                merged = t;
+            }
+            int64_t x = 0, y = 0, w = 0;
+            int32_t *au = adj[u];
+            while (x < len[u] || y < nn) {
+                int32_t c;
+                if (y >= nn || (x < len[u] && au[x] < nb[y])) c = au[x++];
+                else if (x >= len[u] || nb[y] < au[x]) c = nb[y++];
+                else {
+                    c = au[x];
+                    x++;
+                    y++;
+                }
+                if (c == p || c == u) continue;
+                merged[w++] = c;
+            }
+            if (w > cap[u]) {
+                int32_t *t = (int32_t *)realloc(adj[u], (size_t)(2 * w) * sizeof(int32_t));
+                if (!t) {
+                    rc = OR_ENOMEM;
+                    goto done;
+                }
+                adj[u] = t;
+                cap[u] = 2 * w;
+            }
+            memcpy(adj[u], merged, (size_t)w * sizeof(int32_t));
+            len[u] = w;
+            if (hn == hcap) {
+                hcap *= 2;
+                md_item *t = (md_item *)realloc(heap, (size_t)hcap * sizeof(md_item));
+                if (!t) {
+                    rc = OR_ENOMEM;
+                    goto done;
+                }
+                heap = t;
+            }
+            md_item ni = {w, u};
+            md_push(heap, &hn, ni);
+        }
+        free(adj[p]);
+        adj[p] = NULL;
+        len[p] = 0;
+    }
+done:
+    if (adj)
+        for (int64_t v = 0; v < n; v++) free(adj[v]);
+    free(adj); free(len); free(cap); free(gone); free(heap); free(merged); free(gp); free(gi);
+    return rc;
+}
+
+/* Default ordering (minimum degree); or_order_leaf gives the nested dissection. */
 int or_order(int64_t n, const int64_t *rp, const int32_t *ci, int32_t *Q) {
-    return or_order_leaf(n, rp, ci, 64, Q);
+    return or_order_md(n, rp, ci, Q);
 }
 
 /* ------------------------------------------------------------------------------------ */

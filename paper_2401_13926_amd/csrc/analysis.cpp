@@ -12,6 +12,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <iterator>
+#include <set>
 #include <cmath>
 #include <limits>
 #include <new>
@@ -249,6 +251,48 @@ class Dissector {
         emit_ascending(middle);
     }
 };
+
+// ---------------------------------------------------------------------------------------
+// Exact minimum degree: n times, take the live vertex whose current elimination-graph
+// degree is smallest (ties: smallest index), make its live neighbours pairwise adjacent and
+// remove it.  Priority: an ordered set of (degree, vertex); adjacency kept sorted.
+// ---------------------------------------------------------------------------------------
+void minimum_degree(int64_t n, const int64_t *rp, const int32_t *ci, std::vector<int32_t> &q) {
+    std::vector<std::vector<int32_t>> nbr(n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] != i) {
+                nbr[i].push_back(ci[p]);
+                nbr[ci[p]].push_back((int32_t)i);
+            }
+    std::set<std::pair<int64_t, int32_t>> queue;
+    for (int64_t v = 0; v < n; ++v) {
+        auto &a = nbr[v];
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
+        queue.emplace((int64_t)a.size(), (int32_t)v);
+    }
+    q.clear();
+    q.reserve(n);
+    std::vector<int32_t> scratch;
+    while (!queue.empty()) {
+        const int32_t v = queue.begin()->second;
+        queue.erase(queue.begin());
+        q.push_back(v);
+        const std::vector<int32_t> clique = std::move(nbr[v]);
+        nbr[v].clear();
+        for (const int32_t u : clique) {
+            auto &a = nbr[u];
+            queue.erase({(int64_t)a.size(), u});
+            scratch.clear();
+            std::set_union(a.begin(), a.end(), clique.begin(), clique.end(), std::back_inserter(scratch));
+            a.clear();
+            for (const int32_t w : scratch)
+                if (w != u && w != v) a.push_back(w);
+            queue.emplace((int64_t)a.size(), u);
+        }
+    }
+}
 
 // ---------------------------------------------------------------------------------------
 // Left-looking LU of A(:,Q) with threshold partial pivoting.  For step j (column c = q[j]):
@@ -624,10 +668,12 @@ int analyze(const AnalysisOptions &opt, int64_t n, const int64_t *rowptr, const 
         a.nnz = rowptr[n];
         a.rowptr.assign(rowptr, rowptr + n + 1);
         a.colidx.assign(colidx, colidx + a.nnz);
-        int rc = nested_dissection(n, rowptr, colidx, opt.nd_leaf, a.q);
-        if (rc != AN_OK) {
+        int rc = AN_OK;
+        if (opt.ordering == ORDER_ND) rc = nested_dissection(n, rowptr, colidx, opt.nd_leaf, a.q);
+        else minimum_degree(n, rowptr, colidx, a.q);
+        if (rc != AN_OK || (int64_t)a.q.size() != n) {
             *msg = "ordering failed";
-            return rc;
+            return AN_EINVAL;
         }
         rc = pivoted_lu(n, rowptr, colidx, values, opt.pivot_tau, a, msg);
         if (rc != AN_OK) return rc;

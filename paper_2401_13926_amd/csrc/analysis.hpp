@@ -8,7 +8,10 @@
 
 namespace kkt {
 
+enum { ORDER_MD = 0, ORDER_ND = 1 };
+
 struct AnalysisOptions {
+    int ordering = ORDER_MD;     // exact minimum degree, or BFS nested dissection
     int64_t nd_leaf = 64;
     double pivot_tau = 0.1;
     int tile_threads = 256;      // threads of a triangular-solve block

@@ -1224,6 +1224,7 @@ extern "C" {
 
 void kkt_opts_default(kkt_opts_t *o) {
     if (!o) return;
+    o->ordering = KKT_ORDER_MD;
     o->nd_leaf = 64;
     o->pivot_tau = 0.1;
     o->restart = 10;
@@ -1250,6 +1251,7 @@ kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowpt
         return fail(nullptr, KKT_EINVAL, "restart must be in 1..64");
     }
     AnalysisOptions ao;
+    ao.ordering = h->opts.ordering == KKT_ORDER_ND ? ORDER_ND : ORDER_MD;
     ao.nd_leaf = h->opts.nd_leaf;
     ao.pivot_tau = h->opts.pivot_tau;
     ao.tile_threads = kTileThreads;

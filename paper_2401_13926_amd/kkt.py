@@ -20,6 +20,7 @@ KKT_OK, KKT_EINVAL, KKT_ENOMEM, KKT_ESINGULAR, KKT_ENOCONV, KKT_EDEVICE, KKT_EST
 PREC_FP64, PREC_MIXED = 0, 1
 GUARD_PERTURB, GUARD_FAIL = 0, 1
 STOP_PAPER, STOP_NRBE = 0, 1
+ORDER_MD, ORDER_ND = 0, 1
 
 #: every entry point declared in include/kkt.h
 EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
@@ -32,7 +33,7 @@ KERNEL_CLASSES = ["ingest", "refactor", "trsv_l", "trsv_u", "spmv", "cgs", "resi
 
 
 class Opts(C.Structure):
-    _fields_ = [("nd_leaf", C.c_int32), ("pivot_tau", C.c_double), ("restart", C.c_int32),
+    _fields_ = [("ordering", C.c_int32), ("nd_leaf", C.c_int32), ("pivot_tau", C.c_double), ("restart", C.c_int32),
                 ("max_restarts", C.c_int32), ("delta_tol", C.c_double), ("nrbe_target", C.c_double),
                 ("precision", C.c_int32), ("guard_policy", C.c_int32), ("stop_mode", C.c_int32),
                 ("mixed_fallback", C.c_int32), ("mixed_max_cycles", C.c_int32)]

@@ -26,9 +26,10 @@ def test_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
-def check_parity(rowptr, colidx, values, leaf=64, tau=0.1):
-    s = P.Solver(rowptr, colidx, values, nd_leaf=leaf, pivot_tau=tau)
-    Q = oracle.order(rowptr, colidx, leaf=leaf)
+def check_parity(rowptr, colidx, values, leaf=64, tau=0.1, method="md"):
+    s = P.Solver(rowptr, colidx, values, nd_leaf=leaf, pivot_tau=tau,
+                 ordering=P.ORDER_MD if method == "md" else P.ORDER_ND)
+    Q = oracle.order(rowptr, colidx, method=method, leaf=leaf)
     f = oracle.LU(rowptr, colidx, values, Q=Q, tau=tau)
     prow, q = s.permutations()
     assert np.array_equal(q, f.Q)
@@ -89,3 +90,17 @@ def test_errors():
     assert e.value.code == P.KKT_EINVAL
     s = P.Solver(p.rowptr, p.colidx, v)
     assert s.workspace_size() > 0
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_analysis_bit_exact_nested_dissection(cfg):
+    p = ks.make_pattern(cfg)
+    v, _ = p.system(1)
+    check_parity(p.rowptr, p.colidx, v, method="nd")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_analysis_bit_exact_small_nd(seed):
+    p = ks.small_kkt(60 + 7 * seed, 35 + 4 * seed, 700 + seed)
+    v, _ = p.system(2)
+    check_parity(p.rowptr, p.colidx, v, leaf=[1, 4, 16, 64][seed], method="nd")

@@ -90,15 +90,15 @@ def test_order_path7():
     rp, ci = csr_pattern_of_edges(7, [(i, i + 1) for i in range(6)])
     # root 0 (min degree, smallest); levels {0}..{6}; separator level 3; halves {0,1,2}
     # -> [0, 2, 1] and {4,5,6} -> [4, 6, 5]
-    assert oracle.order(rp, ci, leaf=1).tolist() == [0, 2, 1, 4, 6, 5, 3]
-    assert oracle.order(rp, ci).tolist() == list(range(7))  # a leaf at the default size
+    assert oracle.order(rp, ci, method="nd", leaf=1).tolist() == [0, 2, 1, 4, 6, 5, 3]
+    assert oracle.order(rp, ci, method="nd").tolist() == list(range(7))  # a leaf at the default size
 
 
 def test_order_star():
     rp, ci = csr_pattern_of_edges(7, [(0, i) for i in range(1, 7)])
     # root 1; levels {1},{0},{2..6}; s clamped to 1 -> separator {0}; {2..6} splits into
     # five single-vertex components
-    assert oracle.order(rp, ci, leaf=1).tolist() == [1, 2, 3, 4, 5, 6, 0]
+    assert oracle.order(rp, ci, method="nd", leaf=1).tolist() == [1, 2, 3, 4, 5, 6, 0]
 
 
 def test_order_grid3x3():
@@ -113,7 +113,7 @@ def test_order_grid3x3():
     rp, ci = csr_pattern_of_edges(9, edges)
     # root 0; levels {0},{1,3},{2,4,6},{5,7},{8}; separator {2,4,6}; {0,1,3} -> [1,3,0];
     # {5,7,8} -> [5,7,8]
-    assert oracle.order(rp, ci, leaf=1).tolist() == [1, 3, 0, 5, 7, 8, 2, 4, 6]
+    assert oracle.order(rp, ci, method="nd", leaf=1).tolist() == [1, 3, 0, 5, 7, 8, 2, 4, 6]
 
 
 def test_order_two_components():
@@ -121,7 +121,7 @@ def test_order_two_components():
     # B = path 0-1-2 (smallest vertex 0) -> B first
     edges = [(3, 4), (4, 5), (0, 1), (1, 2)]
     rp, ci = csr_pattern_of_edges(6, edges)
-    assert oracle.order(rp, ci, leaf=1).tolist() == [0, 2, 1, 3, 5, 4]
+    assert oracle.order(rp, ci, method="nd", leaf=1).tolist() == [0, 2, 1, 3, 5, 4]
 
 
 def test_order_is_permutation_and_reduces_fill():
@@ -442,3 +442,51 @@ def test_fgmres_ir_exact_preconditioner_and_sequence():
     m = oracle.metrics(p2.rowptr, p2.colidx, w3, x, b3)
     assert info["converged"] and 1 <= info["iters"] <= 30
     assert m["nrbe"] <= 1e-12 and m["resid"] < 1e-3 * m0["resid"]
+
+
+# ----------------------------------------------------------------------------------------
+# minimum degree ordering (default): hand-derived orders and an elimination-graph brute force
+# ----------------------------------------------------------------------------------------
+
+def test_md_path_star_grid():
+    rp, ci = csr_pattern_of_edges(7, [(i, i + 1) for i in range(6)])
+    # ends have degree 1; eliminating 0 leaves 1 with degree 1, and so on
+    assert oracle.order(rp, ci).tolist() == [0, 1, 2, 3, 4, 5, 6]
+    rp, ci = csr_pattern_of_edges(7, [(0, i) for i in range(1, 7)])
+    # leaves 1..5 (degree 1) go first; then 0 and 6 both have degree 1 -> 0 first
+    assert oracle.order(rp, ci).tolist() == [1, 2, 3, 4, 5, 0, 6]
+    edges = []
+    for r in range(3):
+        for c in range(3):
+            v = 3 * r + c
+            if c < 2:
+                edges.append((v, v + 1))
+            if r < 2:
+                edges.append((v, v + 3))
+    rp, ci = csr_pattern_of_edges(9, edges)
+    # corners (degree 2) 0, 2, 6, 8; then 1 (degree 3, smallest), 3, then 4, 5, 7
+    assert oracle.order(rp, ci).tolist() == [0, 2, 6, 8, 1, 3, 4, 5, 7]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_md_matches_elimination_graph_bruteforce(seed):
+    if seed % 2:
+        p = ks.small_kkt(50 + 3 * seed, 30 + 2 * seed, 900 + seed)
+        rp, ci = p.rowptr, p.colidx
+        n = p.N
+    else:
+        n = 80
+        A = random_sparse(n, 0.04, 950 + seed)
+        rp, ci, _ = csr_of(A)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    edges = [(int(a), int(b)) for a, b in zip(rows, ci) if a != b]
+    assert oracle.order(rp, ci).tolist() == dense.md_order_bruteforce(n, edges)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_md_fill_below_nested_dissection(cfg):
+    p = ks.make_pattern(cfg)
+    v, _ = p.system(1)
+    f_md = oracle.LU(p.rowptr, p.colidx, v, Q=oracle.order(p.rowptr, p.colidx))
+    f_nd = oracle.LU(p.rowptr, p.colidx, v, Q=oracle.order(p.rowptr, p.colidx, method="nd"))
+    assert f_md.lnz + f_md.unz < 0.5 * (f_nd.lnz + f_nd.unz)
