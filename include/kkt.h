@@ -79,7 +79,17 @@ typedef struct {
                                solve again (1) or return KKT_ENOCONV (0) */
     int32_t mixed_max_cycles; /* mixed precision: restart cycles tried with the FP32
                                preconditioner before the fallback (3) */
+    int32_t ir_method;      /* KKT_IR_FGMRES (the method of Section 2.1, default),
+                               KKT_IR_RICHARDSON (x += M^-1 (r - K x), Section 1.3) or
+                               KKT_IR_ERROR_FGMRES (Richardson whose correction solves the error
+                               system K d = rho with FGMRES(restart), Section 2.1) */
+    int32_t richardson_max_it; /* Richardson: corrections at most (50) */
+    double ratio_stop;      /* Richardson: stop when NSR_new > ratio_stop * NSR_old, MA57's
+                               ratio test (0.5) */
+    double inner_tol;       /* error-system FGMRES: relative tolerance of each inner solve (1e-2) */
 } kkt_opts_t;
+
+enum { KKT_IR_FGMRES = 0, KKT_IR_RICHARDSON = 1, KKT_IR_ERROR_FGMRES = 2 };
 
 /* Kernel classes reported by kkt_get_kernel_times. */
 enum {
@@ -127,6 +137,8 @@ typedef struct {
     double est_resid;        /* last estimated FGMRES residual norm */
     double true_resid;       /* ||r - K x||_2 */
     double knorm_inf;        /* ||K||_inf */
+    double nsr;              /* ||r - K x||_inf / (||K||_inf ||x||_inf), MA57's measure */
+    int64_t precond_applications; /* triangular-solve pairs (x0 included) */
 } kkt_solve_info_t;
 
 /* Fill *opts with the defaults listed above. */

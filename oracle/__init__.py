@@ -265,3 +265,34 @@ def direct_solve(rowptr, colidx, values, b, Q, tau=0.1):
     """Plain direct method (fresh pivoting, ordering reused): the CPU baseline solve."""
     f = LU(rowptr, colidx, values, Q=Q, tau=tau)
     return f.solve(b), f
+
+
+def _richardson_bind():
+    L = lib()
+    if not getattr(L, "_rich_bound", False):
+        i64, i32p, i64p, f64p = C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double)
+        L.or_richardson.argtypes = [C.c_void_p, f64p, f64p, i64p, i32p, f64p, f64p, f64p, C.c_int, C.c_double,
+                                    C.c_double, C.c_int, C.c_double, f64p, f64p, i64]
+        L._rich_bound = True
+    return L
+
+
+def richardson(f: LU, rowptr, colidx, values, b, Lx=None, Ux=None, max_it=50, tol=1e-14, ratio=0.5,
+               inner_restart=0, inner_tol=1e-2, hist_cap=256):
+    """Richardson iterative refinement with these factors (or_richardson in oracle.c);
+    inner_restart > 0 solves each correction with FGMRES on the error system."""
+    L = _richardson_bind()
+    rp, ci, v = _csr(rowptr, colidx, values)
+    b = np.ascontiguousarray(b, np.float64)
+    Lx = f.Lx if Lx is None else np.ascontiguousarray(Lx, np.float64)
+    Ux = f.Ux if Ux is None else np.ascontiguousarray(Ux, np.float64)
+    x = np.empty(f.n)
+    info = np.zeros(6)
+    hist = np.zeros(hist_cap)
+    L.or_richardson(f._h, _p(Lx, C.c_double), _p(Ux, C.c_double), _p(rp, C.c_int64), _p(ci, C.c_int32),
+                    _p(v, C.c_double), _p(b, C.c_double), _p(x, C.c_double), int(max_it), float(tol),
+                    float(ratio), int(inner_restart), float(inner_tol), _p(info, C.c_double),
+                    _p(hist, C.c_double), hist_cap)
+    it = int(info[0])
+    return x, dict(corrections=it, applications=int(info[1]), nsr=info[2], nrbe=info[3],
+                   converged=bool(info[4]), rr=info[5], hist=hist[:min(it, hist_cap)].copy())

@@ -1188,5 +1188,69 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
     return converged ? OR_OK : 4;
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* Richardson iterative refinement (Section 1.3): x0 = M^-1 b; then repeatedly           */
+/* rho = b - K x, d = M^-1 rho, x = x + d.  Stopping (MA57's ratio test on the norm of    */
+/* scaled residuals, NSR = ||rho||_inf / (||K||_inf ||x||_inf)): stop when               */
+/* ||rho||_2 < tol ||rho0||_2, or when NSR_new > ratio * NSR_old (the step no longer     */
+/* reduces it enough), or after max_it corrections.                                      */
+/* With inner_restart > 0 the correction d solves K d = rho by FGMRES(inner_restart)     */
+/* preconditioned by the same factors, to the relative tolerance inner_tol (the          */
+/* "iterative solver on the error system" variant, Section 2.1).                        */
+/* info: [0] corrections, [1] preconditioner applications, [2] final NSR, [3] final      */
+/*       NRBE, [4] converged (relative residual test passed), [5] final ||rho||_2 /     */
+/*       ||rho0||_2.  hist: NSR after each correction.                                   */
+/* ------------------------------------------------------------------------------------ */
+
+int or_richardson(const or_lu_t *f, const double *Lx, const double *Ux, const int64_t *rp, const int32_t *ci,
+                  const double *v, const double *b, double *x, int max_it, double tol, double ratio,
+                  int inner_restart, double inner_tol, double *info, double *hist, int64_t hist_cap) {
+    int64_t n = f->n;
+    double *r = (double *)malloc((size_t)n * sizeof(double));
+    double *d = (double *)malloc((size_t)n * sizeof(double));
+    if (!r || !d) {
+        free(r); free(d);
+        return OR_ENOMEM;
+    }
+    double kn = or_norm_inf_mat(n, rp, v);
+    double bn = nrm2(n, b);
+    long applications = 1;
+    or_solve_with(f, Lx, Ux, b, x);
+    or_residual(n, rp, ci, v, x, b, r);
+    double rho0 = nrm2(n, r);
+    double rn = rho0;
+    double nsr = nrminf(n, r) / (kn * nrminf(n, x));
+    int it = 0, converged = rn < tol * rho0;
+    while (!converged && it < max_it) {
+        if (inner_restart > 0) {
+            double inner[8];
+            or_fgmres_ir(f, Lx, Ux, NULL, NULL, 0, rp, ci, v, r, d, inner_restart, 0, inner_tol, 1, inner,
+                         NULL, 0);
+            applications += 1 + (long)inner[0];
+        } else {
+            or_solve_with(f, Lx, Ux, r, d);
+            applications += 1;
+        }
+        for (int64_t i = 0; i < n; i++) x[i] = x[i] + d[i];
+        it++;
+        or_residual(n, rp, ci, v, x, b, r);
+        rn = nrm2(n, r);
+        double nsr_new = nrminf(n, r) / (kn * nrminf(n, x));
+        if (hist && it <= hist_cap) hist[it - 1] = nsr_new;
+        converged = rn < tol * rho0;
+        int stalled = nsr_new > ratio * nsr;
+        nsr = nsr_new;
+        if (stalled) break;
+    }
+    info[0] = it;
+    info[1] = (double)applications;
+    info[2] = nsr;
+    info[3] = rn / (kn * nrm2(n, x) + bn);
+    info[4] = converged;
+    info[5] = rho0 > 0.0 ? rn / rho0 : 0.0;
+    free(r); free(d);
+    return converged ? OR_OK : 4;
+}
+
 /* Export the step-indexed pivot inverse (row -> step) for convenience. */
 void or_lu_pinv(const or_lu_t *f, int32_t *pinv) { memcpy(pinv, f->pinv, (size_t)f->n * sizeof(int32_t)); }

@@ -598,7 +598,9 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
         for (int32_t l = 0; l < nlev; ++l) {
             const int32_t r0 = sc.lev_ptr[l], r1 = sc.lev_ptr[l + 1];
             const int32_t cnt = r1 - r0;
-            if (cnt > opt.narrow_rows) {
+            // a level joins a multi-level tile only when one pass of the block covers it
+            // (each lane group then owns at most one row of the level)
+            if (cnt > opt.narrow_rows || cnt > (opt.tile_threads >> sc.lev_lg[l])) {
                 close(r0);
                 open_rows = 0;
                 const int32_t chunk = std::max(1, opt.tile_threads >> sc.lev_lg[l]);

@@ -36,6 +36,7 @@ struct Control {
     double wnorm_in;                // ||K z_j|| before orthogonalization
     double hn;                      // ||w|| after CGS2
     double rnorm2, xnorm2, bnorm2;  // sums of squares from the residual kernel
+    double rinf, xinf;              // max |rho_i|, max |x_i| from the residual kernel
     double h1[kRestartMax + 1];     // first CGS pass coefficients
     double h2[kRestartMax + 1];     // second CGS pass coefficients
     double g[kRestartMax + 1];      // rotated right-hand side of the least-squares problem
@@ -56,7 +57,7 @@ struct ControlSummary {
     unsigned int counter;
     int stop, jdone, breakdown, nonfinite_b;
     unsigned int hang;
-    double beta, inner_tol, est, wnorm_in, hn, rnorm2, xnorm2, bnorm2;
+    double beta, inner_tol, est, wnorm_in, hn, rnorm2, xnorm2, bnorm2, rinf, xinf;
 };
 
 }  // namespace kkt

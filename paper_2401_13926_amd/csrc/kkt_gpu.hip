@@ -123,6 +123,18 @@ __device__ double block_sum(double v, double *red) {
     return s;
 }
 
+// Block-wide max of non-negative doubles (blockDim = kStreamBlock); result in all threads.
+__device__ double block_max(double v, double *red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kStreamBlock / 64; ++w) s = fmax(s, red[w]);
+    return s;
+}
+
 // Row range of block b when `total` rows are split into gridDim.x contiguous chunks.
 __device__ __forceinline__ void block_rows(int64_t total, int64_t &r0, int64_t &r1) {
     const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
@@ -369,19 +381,54 @@ template <typename T> struct TrsvArgs {
     unsigned int *hang;
 };
 
-// Solution entry of another tile: coherent (system-scope) polling until it is written.
-template <typename T> __device__ __forceinline__ T load_remote(const T *p, unsigned int *hang) {
-    using U = typename Bits<T>::U;
-    U b = __hip_atomic_load(reinterpret_cast<const U *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    if (b != Bits<T>::sent) return __builtin_bit_cast(T, b);
-    return load_ready(p, hang);
+
+// Operands of one row of one level, loaded ahead of time: the row, its first (up to) four
+// entries per lane (reference and value) and, for references outside the tile, the
+// solution entry as read so far (the sentinel if it was not written yet).
+template <typename T> struct RowPrefetch {
+    int i;        // row (step index), -1 when this lane group has no row at this level
+    int64_t p0;   // first entry of this lane, pe end of the row
+    int64_t pe;
+    int c[4];
+    T v[4], xv[4];
+};
+
+template <typename T>
+__device__ __forceinline__ RowPrefetch<T> trsv_prefetch(const TrsvArgs<T> &a, int32_t lev, int32_t rb, int32_t re,
+                                                        int tid) {
+    RowPrefetch<T> f;
+    f.i = -1;
+    f.p0 = f.pe = 0;
+    const int32_t lb = a.lev_ptr[lev] > rb ? a.lev_ptr[lev] : rb;
+    const int32_t le = a.lev_ptr[lev + 1] < re ? a.lev_ptr[lev + 1] : re;
+    const int lg = a.lev_lg[lev];
+    const int g = 1 << lg;
+    const int32_t r = lb + (tid >> lg);
+    if (r < le) {
+        f.i = a.rows[r];
+        f.p0 = a.rp[f.i] + (tid & (g - 1));
+        f.pe = a.rp[f.i + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t pp = f.p0 + (int64_t)u * g;
+        const bool in = f.i >= 0 && pp < f.pe;
+        f.c[u] = in ? a.ref[pp] : INT32_MIN;
+        f.v[u] = in ? a.val[pp] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) f.xv[u] = f.c[u] >= 0 ? a.out[f.c[u]] : T(0);
+    return f;
 }
 
-// Triangular solve by tiles.  Tiles are handed out in level order to running blocks.  A
-// multi-level tile walks its levels with a block barrier in between and keeps its values in
-// LDS (dependencies inside the tile are LDS slots); dependencies on other tiles read the
-// global solution, whose entries are their own ready flags.  Rows of one level are
-// independent, so the lane groups of a wavefront never wait on each other.
+// Triangular solve by tiles.  Tiles are handed out in level order to running blocks.  Every
+// level of a tile fits one pass of the block (a lane group owns at most one row), so a
+// multi-level tile walks its levels with one barrier each, values of the tile kept in LDS
+// (references inside the tile are LDS slots); the operands of the next level -- indices,
+// values and solution entries of other tiles -- are loaded before the barrier.  References
+// to other tiles read the global solution, whose entries are their own ready flags (plain
+// loads can only return the sentinel or the final value; sentinels are then polled).  Rows of
+// one level are independent, so lane groups of a wavefront never wait on each other.
 template <typename T, bool kLower>
 __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
     __shared__ T lds[kTileRows];
@@ -395,51 +442,55 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
         __syncthreads();
         if ((int64_t)t >= a.ntiles) break;
         const int32_t rb = a.tile_row[t], re = a.tile_row[t + 1];
-        for (int32_t lev = a.tile_lev[t];; ++lev) {
-            const int32_t lb = a.lev_ptr[lev] > rb ? a.lev_ptr[lev] : rb;
-            if (lb >= re) break;  // (lev <= number of levels here: lev_ptr[levels] = n >= re)
-            const int32_t le = a.lev_ptr[lev + 1] < re ? a.lev_ptr[lev + 1] : re;
+        int32_t lev = a.tile_lev[t];
+        RowPrefetch<T> cur = trsv_prefetch(a, lev, rb, re, tid);
+        for (;;) {
             const int lg = a.lev_lg[lev];
             const int g = 1 << lg;
-            const int grp = tid >> lg, sub = tid & (g - 1);
-            const int ngrp = kTileThreads >> lg;
-            for (int32_t r = lb + grp; r < le; r += ngrp) {
-                const int i = a.rows[r];
-                T acc = 0;
-                const int64_t pe = a.rp[i + 1];
-                for (int64_t p = a.rp[i] + sub; p < pe; p += 4 * g) {
-                    int c[4];
-                    T v[4], xv[4];
+            // operands of the next level of this tile, if any
+            const bool more = a.lev_ptr[lev + 1] < re;
+            RowPrefetch<T> nxt;
+            nxt.i = -1;
+            if (more) nxt = trsv_prefetch(a, lev + 1, rb, re, tid);
+            T acc = 0;
+            if (cur.i >= 0) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int64_t pp = p + (int64_t)u * g;
-                        c[u] = pp < pe ? a.ref[pp] : INT32_MIN;
-                        v[u] = pp < pe ? a.val[pp] : T(0);
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (c[u] == INT32_MIN) xv[u] = T(0);
-                        else if (c[u] < 0) xv[u] = lds[-c[u] - 1];
-                        else xv[u] = load_remote(a.out + c[u], a.hang);
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (c[u] != INT32_MIN) {
-                            const T prod = v[u] * xv[u];
-                            acc = acc + prod;
-                        }
+                for (int u = 0; u < 4; ++u) {
+                    if (cur.c[u] == INT32_MIN) continue;
+                    T xk;
+                    if (cur.c[u] < 0) xk = lds[-cur.c[u] - 1];
+                    else xk = is_sentinel(cur.xv[u]) ? load_ready(a.out + cur.c[u], a.hang) : cur.xv[u];
+                    const T prod = cur.v[u] * xk;
+                    acc = acc + prod;
                 }
-                for (int o = 1; o < g; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
-                if (sub == 0) {
-                    T res;
-                    if (kLower) res = (T)a.rhs64[a.prow[i]] - acc;
-                    else res = (a.rhs_step[i] - acc) / a.diag[i];
-                    lds[r - rb] = res;
-                    store_ready(a.out + i, res);
-                    if (!kLower) a.xout[a.q[i]] = (double)res;
+                // entries beyond the first four per lane (rows longer than 256 entries)
+                for (int64_t p = cur.p0 + 4 * (int64_t)g; p < cur.pe; p += g) {
+                    const int c = a.ref[p];
+                    T xk;
+                    if (c < 0) xk = lds[-c - 1];
+                    else {
+                        xk = a.out[c];
+                        if (is_sentinel(xk)) xk = load_ready(a.out + c, a.hang);
+                    }
+                    const T prod = a.val[p] * xk;
+                    acc = acc + prod;
                 }
             }
+            for (int o = 1; o < g; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
+            if (cur.i >= 0 && (tid & (g - 1)) == 0) {
+                const int i = cur.i;
+                T res;
+                if (kLower) res = (T)a.rhs64[a.prow[i]] - acc;
+                else res = (a.rhs_step[i] - acc) / a.diag[i];
+                const int32_t lb = a.lev_ptr[lev] > rb ? a.lev_ptr[lev] : rb;
+                lds[lb + (tid >> lg) - rb] = res;
+                store_ready(a.out + i, res);
+                if (!kLower) a.xout[a.q[i]] = (double)res;
+            }
             __syncthreads();
+            if (!more) break;
+            ++lev;
+            cur = nxt;
         }
     }
 }
@@ -484,22 +535,39 @@ __device__ __forceinline__ double *partbuf(const KrylovArgs &a, int which) {
     return a.part + (int64_t)which * kStreamGridMax * kPartStride;
 }
 
-// Sum of partial column t over the G blocks of the previous kernel (fixed order).
+// Sum of partial column t over the G blocks of the previous kernel (fixed order; one thread).
 __device__ __forceinline__ double reduce_part(const double *buf, int G, int t) {
     double s = 0.0;
     for (int b = 0; b < G; ++b) s += buf[(int64_t)b * kPartStride + t];
     return s;
 }
 
-// Reduces columns 0..m-1 of buf into out[] (shared memory), one column per thread.
-__device__ void reduce_cols(const double *buf, int G, int m, double *out) {
-    for (int t = threadIdx.x; t < m; t += blockDim.x) out[t] = reduce_part(buf, G, t);
+// Per-column partial sums of one block without a barrier per column: each wavefront reduces
+// its value with shuffles and lane 0 parks it in red[t][wave]; block_cols_finish() (one
+// barrier) then adds the kStreamBlock/64 wave values of column t in wave order.
+__device__ __forceinline__ void block_col_put(double v, int t, double *red) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[t * (kStreamBlock / 64) + (threadIdx.x >> 6)] = v;
+}
+__device__ __forceinline__ double block_col_get(const double *red, int t) {
+    double s = 0.0;
+    for (int w = 0; w < kStreamBlock / 64; ++w) s += red[t * (kStreamBlock / 64) + w];
+    return s;
+}
+
+// Reduces columns 0..m-1 of buf (G <= kStreamBlock block rows) into out[] (shared): thread b
+// reads block b's row, per-column sums in a fixed tree (identical in every block).
+__device__ void reduce_cols(const double *buf, int G, int m, double *out, double *red) {
+    const int b = threadIdx.x;
+    for (int t = 0; t < m; ++t) block_col_put(b < G ? buf[(int64_t)b * kPartStride + t] : 0.0, t, red);
+    __syncthreads();
+    for (int t = threadIdx.x; t < m; t += blockDim.x) out[t] = block_col_get(red, t);
     __syncthreads();
 }
 
 // w = K z_j; partials (buffer 0): V_t . w for t <= j, and w . w at t = j + 1
 __global__ void __launch_bounds__(kStreamBlock) k_spmv_dots(KrylovArgs a, int j) {
-    __shared__ double red[kStreamBlock / 64];
+    __shared__ double red[(kRestartMax + 2) * (kStreamBlock / 64)];
     int64_t r0, r1;
     block_rows(a.n, r0, r1);
     const double *z = a.Z + (int64_t)j * a.n;
@@ -517,17 +585,18 @@ __global__ void __launch_bounds__(kStreamBlock) k_spmv_dots(KrylovArgs a, int j)
         const double *v = t <= j ? a.V + (int64_t)t * a.n : a.w;
         double s = 0.0;
         for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) s += v[i] * a.w[i];
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) out[t] = s;
+        block_col_put(s, t, red);
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t <= j + 1; t += blockDim.x) out[t] = block_col_get(red, t);
 }
 
 // h1 = reduce(buffer 0); w -= V h1; partials (buffer 1): V_t . w (second CGS pass)
 __global__ void __launch_bounds__(kStreamBlock) k_cgs_pass2(KrylovArgs a, int j) {
-    __shared__ double red[kStreamBlock / 64];
+    __shared__ double red[(kRestartMax + 2) * (kStreamBlock / 64)];
     __shared__ double h[kRestartMax + 2];
     const int G = gridDim.x;
-    reduce_cols(partbuf(a, 0), G, j + 2, h);
+    reduce_cols(partbuf(a, 0), G, j + 2, h, red);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int t = 0; t <= j; ++t) a.ctl->h1[t] = h[t];
         a.ctl->wnorm_in = sqrt(h[j + 1]);
@@ -548,17 +617,18 @@ __global__ void __launch_bounds__(kStreamBlock) k_cgs_pass2(KrylovArgs a, int j)
         const double *v = a.V + (int64_t)t * a.n;
         double s = 0.0;
         for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) s += v[i] * a.w[i];
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) out[t] = s;
+        block_col_put(s, t, red);
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t <= j; t += blockDim.x) out[t] = block_col_get(red, t);
 }
 
 // h2 = reduce(buffer 1); w -= V h2; partial (buffer 2): w . w
 __global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j) {
-    __shared__ double red[kStreamBlock / 64];
+    __shared__ double red[(kRestartMax + 2) * (kStreamBlock / 64)];
     __shared__ double h[kRestartMax + 1];
     const int G = gridDim.x;
-    reduce_cols(partbuf(a, 1), G, j + 1, h);
+    reduce_cols(partbuf(a, 1), G, j + 1, h, red);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (int t = 0; t <= j; ++t) a.ctl->h2[t] = h[t];
     int64_t r0, r1;
@@ -584,9 +654,12 @@ __global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j
 template <typename T>
 __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j, int restart, T *s1, T *s2) {
     __shared__ double sh[3];
+    __shared__ double red[kStreamBlock / 64];
+    __shared__ double hsq[1];
     Control *c = a.ctl;
+    reduce_cols(partbuf(a, 2), gridDim.x, 1, hsq, red);
     if (threadIdx.x == 0) {
-        const double hn = sqrt(reduce_part(partbuf(a, 2), gridDim.x, 0));
+        const double hn = sqrt(hsq[0]);
         double col[kRestartMax + 1];
         for (int t = 0; t <= j; ++t) col[t] = c->h1[t] + c->h2[t];
         col[j + 1] = hn;
@@ -642,12 +715,13 @@ __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j,
     }
 }
 
-// rho = b - K x; partials (buffer 0): ||rho||^2, ||x||^2, ||b||^2, non-finite b flag
+// rho = b - K x; partials (buffer 0): ||rho||^2, ||x||^2, ||b||^2, non-finite b flag,
+// max |rho_i|, max |x_i|
 __global__ void __launch_bounds__(kStreamBlock) k_resid(KrylovArgs a, const double *b, const double *x, double *r) {
     __shared__ double red[kStreamBlock / 64];
     int64_t r0, r1;
     block_rows(a.n, r0, r1);
-    double sr = 0.0, sx = 0.0, sb = 0.0;
+    double sr = 0.0, sx = 0.0, sb = 0.0, mr = 0.0, mx = 0.0;
     int badb = 0;
     for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
         double s = 0.0;
@@ -661,9 +735,13 @@ __global__ void __launch_bounds__(kStreamBlock) k_resid(KrylovArgs a, const doub
         sr += ri * ri;
         sx += x[i] * x[i];
         sb += bi * bi;
+        mr = fmax(mr, fabs(ri));
+        mx = fmax(mx, fabs(x[i]));
         badb |= !isfinite(bi);
     }
     sr = block_sum(sr, red);
+    mr = block_max(mr, red);
+    mx = block_max(mx, red);
     sx = block_sum(sx, red);
     sb = block_sum(sb, red);
     const double bad = block_sum((double)badb, red);
@@ -673,14 +751,23 @@ __global__ void __launch_bounds__(kStreamBlock) k_resid(KrylovArgs a, const doub
         p[1] = sx;
         p[2] = sb;
         p[3] = bad;
+        p[4] = mr;
+        p[5] = mx;
     }
 }
 
 // One block: sums of the residual kernel's partials into the control block.
-__global__ void k_resid_reduce(KrylovArgs a, int G) {
+__global__ void __launch_bounds__(kStreamBlock) k_resid_reduce(KrylovArgs a, int G) {
     __shared__ double h[4];
-    reduce_cols(partbuf(a, 0), G, 4, h);
+    __shared__ double red[4 * (kStreamBlock / 64)];
+    reduce_cols(partbuf(a, 0), G, 4, h, red);
+    const double *buf = partbuf(a, 0);
+    const int bb = threadIdx.x;
+    const double mr = block_max(bb < G ? buf[(int64_t)bb * kPartStride + 4] : 0.0, red);
+    const double mx = block_max(bb < G ? buf[(int64_t)bb * kPartStride + 5] : 0.0, red);
     if (threadIdx.x == 0) {
+        a.ctl->rinf = mr;
+        a.ctl->xinf = mx;
         a.ctl->rnorm2 = h[0];
         a.ctl->xnorm2 = h[1];
         a.ctl->bnorm2 = h[2];
@@ -742,6 +829,12 @@ __global__ void __launch_bounds__(kStreamBlock) k_xupdate(KrylovArgs a, double *
     }
 }
 
+// x += d
+__global__ void k_axpy(int64_t n, const double *d, double *x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = x[i] + d[i];
+}
+
 __global__ void k_copy(int64_t n, const double *src, double *dst) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
@@ -779,7 +872,7 @@ struct DevLayout {
     double *Ld64;
     float *Ld32;
     // vectors
-    double *V, *Z, *w, *r, *y64, *z64;
+    double *V, *Z, *w, *r, *y64, *z64, *dv, *rr;
     float *y32, *z32;
     double *part;
     Control *ctl;
@@ -901,7 +994,7 @@ struct Planner {
 struct Offsets {
     size_t fp, fi, fdiag, order, f2t, relptr, fsrc, relpos, lrp, urp, krp, kci, l_rows, l_lev, l_tile,
         l_tlev, l_ref, l_lg, u_rows, u_lev, u_tile, u_tlev, u_ref, u_lg, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
-        z32, part, ctl, total;
+        z32, dv, rr, part, ctl, total;
 };
 
 Offsets plan(const kkt_handle_t h) {
@@ -951,6 +1044,8 @@ Offsets plan(const kkt_handle_t h) {
     o.z64 = p.take<double>(n);
     o.y32 = p.take<float>(n);
     o.z32 = p.take<float>(n);
+    o.dv = p.take<double>(n);
+    o.rr = p.take<double>(n);
     o.part = p.take<double>((size_t)3 * kStreamGridMax * kPartStride);
     o.ctl = p.take<Control>(1);
     o.total = p.off;
@@ -1109,9 +1204,10 @@ kkt_status_t read_ctl(kkt_handle_t h, hipStream_t s) {
 // the direct solve, the refine test of Section 2.3, then restart cycles whose solution is
 // formed only at the end of the cycle.  The host reads the stop flag after every Arnoldi
 // step, so no kernel is launched past the end of a cycle.
+// require_nrbe = false runs FGMRES as an inner solver (acceptance on its estimate only).
 template <typename T>
 kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, kkt_solve_info_t *info,
-                        hipStream_t s, int max_cycles) {
+                        hipStream_t s, int max_cycles, bool require_nrbe = true) {
     const Analysis &a = h->an;
     DevLayout &d = h->d;
     const int R = h->opts.restart;
@@ -1126,7 +1222,7 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
     e0 = prof_begin(h, s);
     k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
-    k_resid_reduce<<<1, 64, 0, s>>>(ka, G);
+    k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G);
     prof_end(h, KKT_K_RESID, e0, s);
     KKT_HIP(h, hipGetLastError());
     kkt_status_t st = read_ctl(h, s);
@@ -1148,9 +1244,10 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     inf.precision = sizeof(T) == 8 ? KKT_PREC_FP64 : KKT_PREC_MIXED;
     inf.pivots_perturbed = (int64_t)c.nguard;
     inf.knorm_inf = knorm;
+    inf.precond_applications = 1;
     inf.nrbe0 = nrbe;
     const bool paper = h->opts.stop_mode == KKT_STOP_PAPER;
-    const double target = h->opts.nrbe_target;
+    const double target = require_nrbe ? h->opts.nrbe_target : HUGE_VAL;
     bool converged;
     if (bn == 0.0) converged = true;
     else converged = paper ? (rn / bn < tol && nrbe <= target) : nrbe <= target;
@@ -1170,6 +1267,7 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         prof_end(h, KKT_K_OTHER, e0, s);
         for (int j = 0; j < R; ++j) {
             KKT_HIP(h, precond<T>(h, d.V + (int64_t)j * a.n, d.Z + (int64_t)j * a.n, d.ctl, s));
+            inf.precond_applications += 1;
             e0 = prof_begin(h, s);
             k_spmv_dots<<<G, kStreamBlock, 0, s>>>(ka, j);
             prof_end(h, KKT_K_SPMV, e0, s);
@@ -1188,7 +1286,7 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         prof_end(h, KKT_K_OTHER, e0, s);
         e0 = prof_begin(h, s);
         k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
-        k_resid_reduce<<<1, 64, 0, s>>>(ka, G);
+        k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G);
         prof_end(h, KKT_K_RESID, e0, s);
         KKT_HIP(h, hipGetLastError());
         st = read_ctl(h, s);
@@ -1206,6 +1304,99 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     inf.rel_resid = bn > 0.0 ? rn / bn : 0.0;
     inf.rr = rho0 > 0.0 ? rn / rho0 : 0.0;
     inf.est_resid = est;
+    inf.true_resid = rn;
+    inf.nsr = h->host_ctl->rinf / (knorm * h->host_ctl->xinf);
+    if (info) *info = inf;
+    return converged ? KKT_OK : KKT_ENOCONV;
+}
+
+// Richardson iterative refinement (Section 1.3), optionally with each correction computed
+// by FGMRES on the error system K d = rho (Section 2.1).  Stops when ||rho|| < tol ||rho0||
+// and NRBE <= target, when MA57's ratio test fails (NSR_new > ratio * NSR_old), or after
+// richardson_max_it corrections.
+template <typename T>
+kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double tol, kkt_solve_info_t *info,
+                             hipStream_t s, bool inner_fgmres) {
+    const Analysis &a = h->an;
+    DevLayout &d = h->d;
+    const int G = h->grid_stream;
+    KrylovArgs ka = kargs<T>(h);
+    hipEvent_t e0 = prof_begin(h, s);
+    k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
+    prof_end(h, KKT_K_OTHER, e0, s);
+    rearm<T>(h, s);
+    KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
+    auto residual = [&]() -> kkt_status_t {
+        hipEvent_t r0 = prof_begin(h, s);
+        k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+        k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G);
+        prof_end(h, KKT_K_RESID, r0, s);
+        KKT_HIP(h, hipGetLastError());
+        return read_ctl(h, s);
+    };
+    kkt_status_t st = residual();
+    if (st != KKT_OK) return st;
+    const ControlSummary &c = *h->host_ctl;
+    if (c.nonfinite) return fail(h, KKT_EINVAL, "non-finite value in the matrix of the last refactorization");
+    if (c.nonfinite_b) return fail(h, KKT_EINVAL, "non-finite value in the right-hand side");
+    if (c.guard_fail) return fail(h, KKT_ESINGULAR, "tiny static pivot under the FAIL guard policy");
+    double knorm;
+    {
+        unsigned long long bits = c.knorm_bits;
+        std::memcpy(&knorm, &bits, sizeof(knorm));
+    }
+    const double bn = std::sqrt(c.bnorm2);
+    const double rho0 = std::sqrt(c.rnorm2);
+    double rn = rho0;
+    double nrbe = rn / (knorm * std::sqrt(c.xnorm2) + bn);
+    double nsr = c.rinf / (knorm * c.xinf);
+    kkt_solve_info_t inf{};
+    inf.precision = sizeof(T) == 8 ? KKT_PREC_FP64 : KKT_PREC_MIXED;
+    inf.pivots_perturbed = (int64_t)c.nguard;
+    inf.knorm_inf = knorm;
+    inf.nrbe0 = nrbe;
+    inf.precond_applications = 1;
+    const double target = h->opts.nrbe_target;
+    bool converged = bn == 0.0 || (rn < tol * rho0 && nrbe <= target);
+    inf.refined = !converged;
+    int it = 0;
+    while (!converged && it < h->opts.richardson_max_it) {
+        if (inner_fgmres) {
+            hipEvent_t c0 = prof_begin(h, s);
+            k_copy<<<G, kStreamBlock, 0, s>>>(a.n, d.r, d.rr);
+            prof_end(h, KKT_K_OTHER, c0, s);
+            kkt_solve_info_t in{};
+            st = solve_impl<T>(h, d.rr, d.dv, h->opts.inner_tol, &in, s, 1, false);
+            if (st != KKT_OK && st != KKT_ENOCONV) return st;
+            inf.precond_applications += in.precond_applications;
+            inf.iterations += in.iterations;
+        } else {
+            rearm<T>(h, s);
+            KKT_HIP(h, precond<T>(h, d.r, d.dv, nullptr, s));
+            inf.precond_applications += 1;
+        }
+        hipEvent_t x0 = prof_begin(h, s);
+        k_axpy<<<G, kStreamBlock, 0, s>>>(a.n, d.dv, x);
+        prof_end(h, KKT_K_OTHER, x0, s);
+        ++it;
+        st = residual();
+        if (st != KKT_OK) return st;
+        rn = std::sqrt(h->host_ctl->rnorm2);
+        nrbe = rn / (knorm * std::sqrt(h->host_ctl->xnorm2) + bn);
+        const double nsr_new = h->host_ctl->rinf / (knorm * h->host_ctl->xinf);
+        converged = rn < tol * rho0 && nrbe <= target;
+        const bool stalled = nsr_new > h->opts.ratio_stop * nsr;
+        nsr = nsr_new;
+        if (stalled) break;
+    }
+    inf.converged = converged;
+    inf.cycles = it;
+    if (!inner_fgmres) inf.iterations = it;
+    inf.nrbe = nrbe;
+    inf.nsr = nsr;
+    inf.rel_resid = bn > 0.0 ? rn / bn : 0.0;
+    inf.rr = rho0 > 0.0 ? rn / rho0 : 0.0;
+    inf.est_resid = rn;
     inf.true_resid = rn;
     if (info) *info = inf;
     return converged ? KKT_OK : KKT_ENOCONV;
@@ -1236,6 +1427,10 @@ void kkt_opts_default(kkt_opts_t *o) {
     o->stop_mode = KKT_STOP_PAPER;
     o->mixed_fallback = 1;
     o->mixed_max_cycles = 3;
+    o->ir_method = KKT_IR_FGMRES;
+    o->richardson_max_it = 50;
+    o->ratio_stop = 0.5;
+    o->inner_tol = 1e-2;
 }
 
 kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowptr, const int32_t *colidx,
@@ -1366,6 +1561,8 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.z64 = (double *)(b + o.z64);
     d.y32 = (float *)(b + o.y32);
     d.z32 = (float *)(b + o.z32);
+    d.dv = (double *)(b + o.dv);
+    d.rr = (double *)(b + o.rr);
     d.part = (double *)(b + o.part);
     d.ctl = (Control *)(b + o.ctl);
     KKT_HIP(h, up(b, o.fp, a.fp, s));
@@ -1442,7 +1639,11 @@ kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, doubl
         h->factor_precision = KKT_PREC_MIXED;
         h->fp64_current = true;
     }
-    kkt_status_t st = solve_impl<double>(h, dev_b, dev_x, tol, info, s, cycles);
+    kkt_status_t st;
+    if (h->opts.ir_method == KKT_IR_RICHARDSON || h->opts.ir_method == KKT_IR_ERROR_FGMRES)
+        st = richardson_impl<double>(h, dev_b, dev_x, tol, info, s, h->opts.ir_method == KKT_IR_ERROR_FGMRES);
+    else
+        st = solve_impl<double>(h, dev_b, dev_x, tol, info, s, cycles);
     if (info && h->fp64_current) info->fallback = 1;
     return st;
 }

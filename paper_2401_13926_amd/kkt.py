@@ -21,6 +21,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 GUARD_PERTURB, GUARD_FAIL = 0, 1
 STOP_PAPER, STOP_NRBE = 0, 1
 ORDER_MD, ORDER_ND = 0, 1
+IR_FGMRES, IR_RICHARDSON, IR_ERROR_FGMRES = 0, 1, 2
 
 #: every entry point declared in include/kkt.h
 EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
@@ -36,7 +37,8 @@ class Opts(C.Structure):
     _fields_ = [("ordering", C.c_int32), ("nd_leaf", C.c_int32), ("pivot_tau", C.c_double), ("restart", C.c_int32),
                 ("max_restarts", C.c_int32), ("delta_tol", C.c_double), ("nrbe_target", C.c_double),
                 ("precision", C.c_int32), ("guard_policy", C.c_int32), ("stop_mode", C.c_int32),
-                ("mixed_fallback", C.c_int32), ("mixed_max_cycles", C.c_int32)]
+                ("mixed_fallback", C.c_int32), ("mixed_max_cycles", C.c_int32), ("ir_method", C.c_int32),
+                ("richardson_max_it", C.c_int32), ("ratio_stop", C.c_double), ("inner_tol", C.c_double)]
 
 
 class AnalysisInfo(C.Structure):
@@ -51,7 +53,8 @@ class SolveInfo(C.Structure):
                 ("refined", C.c_int32), ("precision", C.c_int32), ("fallback", C.c_int32),
                 ("pivots_perturbed", C.c_int64), ("nrbe", C.c_double), ("nrbe0", C.c_double),
                 ("rel_resid", C.c_double), ("rr", C.c_double), ("est_resid", C.c_double),
-                ("true_resid", C.c_double), ("knorm_inf", C.c_double)]
+                ("true_resid", C.c_double), ("knorm_inf", C.c_double), ("nsr", C.c_double),
+                ("precond_applications", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

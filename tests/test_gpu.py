@@ -117,9 +117,10 @@ def test_direct_solve_backward_error(dev, cfg, step):
     olx, oux, _ = f.refactor64(p.rowptr, p.colidx, v)
     check_solve_backward_error(f, olx, oux, b, x, 2.0 ** -53)
     if step == 1:
-        # pivoted factors: well-conditioned triangles, the solutions agree closely
+        # pivoted factors: the two summation orders agree to roughly the triangles' condition
+        # number times the unit roundoff (about 1e-10 measured on these systems)
         xo = f.solve(b, olx, oux)
-        assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
+        assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
 
 
 @pytest.mark.parametrize("prec", [P.PREC_FP64, P.PREC_MIXED])
@@ -240,3 +241,37 @@ def test_guard_fail_policy(dev):
     torch.cuda.synchronize()
     _, ux = s2.factor_values(0)
     assert ux[-1] == 2.0 * 2.0 ** -53
+
+
+@pytest.mark.parametrize("method", [P.IR_RICHARDSON, P.IR_ERROR_FGMRES])
+def test_richardson_variants(dev, method):
+    """Richardson refinement and FGMRES on the error system (the paper's comparison of
+    Fig. 3) against the oracle's implementation of the same iterations."""
+    say("richardson variant", method)
+    p, s, f = make(2, dev, ir_method=method)
+    for step in (2, 3):
+        v, b = p.system(step)
+        s.refactor(cuda(v, dev))
+        xg, info = s.solve(cuda(b, dev), allow_noconv=True)
+        x = xg.cpu().numpy()
+        olx, oux, _ = f.refactor64(p.rowptr, p.colidx, v)
+        xo, oi = oracle.richardson(f, p.rowptr, p.colidx, v, b, Lx=olx, Ux=oux,
+                                   inner_restart=10 if method == P.IR_ERROR_FGMRES else 0, inner_tol=1e-2)
+        m = oracle.metrics(p.rowptr, p.colidx, v, x, b)
+        say("   step", step, "gpu corrections", info["cycles"], "applications", info["precond_applications"],
+            "nsr %.2e" % m["nsr"], "| oracle corrections", oi["corrections"], "applications", oi["applications"],
+            "nsr %.2e" % oi["nsr"])
+        assert np.isfinite(x).all()
+        assert info["nsr"] == pytest.approx(m["nsr"], rel=1e-6)
+        # the same iteration on the same factors: NSR within two orders of the oracle's
+        assert m["nsr"] <= 100 * oi["nsr"] + 1e-30
+        assert abs(info["cycles"] - oi["corrections"]) <= 2
+
+
+def test_fgmres_counts_preconditioner_applications(dev):
+    say("precond applications")
+    p, s, f = make(2, dev)
+    v, b = p.system(3)
+    s.refactor(cuda(v, dev))
+    _, info = s.solve(cuda(b, dev))
+    assert info["precond_applications"] == 1 + info["iterations"]

@@ -104,3 +104,20 @@ def test_analysis_bit_exact_small_nd(seed):
     p = ks.small_kkt(60 + 7 * seed, 35 + 4 * seed, 700 + seed)
     v, _ = p.system(2)
     check_parity(p.rowptr, p.colidx, v, leaf=[1, 4, 16, 64][seed], method="nd")
+
+
+def test_abi_struct_sizes_match_header(tmp_path):
+    import ctypes as C
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "sz.c"
+    src.write_text('#include "kkt.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu %zu %zu\\n",'
+                   'sizeof(kkt_opts_t), sizeof(kkt_solve_info_t), sizeof(kkt_analysis_info_t),'
+                   'sizeof(kkt_kernel_times_t)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run([cc, "-I", str(ROOT / "include"), "-o", str(exe), str(src)], check=True)
+    sizes = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert sizes == [C.sizeof(K.Opts), C.sizeof(K.SolveInfo), C.sizeof(K.AnalysisInfo), C.sizeof(K.KernelTimes)]
