@@ -518,6 +518,17 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
         std::stable_sort(a.col_order.begin(), a.col_order.end(),
                          [&](int32_t x, int32_t y) { return level[x] < level[y]; });
         a.levels_refactor = n ? 1 + *std::max_element(level.begin(), level.end()) : 0;
+        std::vector<int64_t> width(a.levels_refactor + 1, 0);
+        for (int64_t j = 0; j < n; ++j) ++width[level[j]];
+        a.refactor_split = n;
+        int64_t pos = 0;
+        for (int64_t l = 0; l < a.levels_refactor; ++l) {
+            if (width[l] <= opt.narrow_columns) {
+                a.refactor_split = pos;
+                break;
+            }
+            pos += width[l];
+        }
     }
     // --- solve layout: L strict CSR, U strict CSR, diagonal; map F -> T
     {

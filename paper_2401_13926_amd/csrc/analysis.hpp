@@ -17,6 +17,8 @@ struct AnalysisOptions {
     int tile_threads = 256;      // threads of a triangular-solve block
     int narrow_rows = 256;       // levels with at most this many rows join multi-level tiles
     int tile_rows = 2048;        // rows of a multi-level tile (its values live in LDS)
+    int narrow_columns = 1024;   // refactorization levels with at most this many columns are
+                                 // handed out one column at a time
 };
 
 // Schedule of one triangular solve.  Rows are sorted by DAG level.  A tile is a contiguous
@@ -69,6 +71,10 @@ struct Analysis {
     // Refactorization schedule: columns sorted by (DAG level, index).
     std::vector<int32_t> col_order;
     int64_t levels_refactor = 0;
+    // Columns at col_order positions >= refactor_split belong to narrow levels (few columns
+    // each, mostly a dependency chain): they are handed out one at a time so that each starts
+    // its update chain as early as possible.
+    int64_t refactor_split = 0;
 
     // Solve layout T = [L strict CSR (nnz_l) | U strict CSR (nnz_u - n) | U diagonal (n)],
     // all in step space; f2t maps each F entry to its T index.

@@ -46,6 +46,7 @@ struct Control {
     unsigned int work_refactor;     // next column-order index to hand out (refactorization)
     unsigned int work_lower;        // next task index to hand out (L solve)
     unsigned int work_upper;        // next task index to hand out (U solve)
+    unsigned int work_refactor2;    // next narrow-level column to hand out (refactorization)
 };
 
 // Host-visible summary copied back once per cycle.

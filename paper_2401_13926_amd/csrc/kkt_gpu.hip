@@ -155,6 +155,7 @@ __global__ void k_prep_solve(Control *c) {
 
 __global__ void k_prep_refactor(Control *c) {
     c->work_refactor = 0;
+    c->work_refactor2 = 0;
     c->hang = 0;
     c->knorm_bits = 0;
     c->nonfinite = 0;
@@ -220,7 +221,8 @@ template <typename T> struct RefactorArgs {
     T *F;                // factor values (ingested on entry, final on exit)
     T *Tv;               // solve layout copy
     T *Ld;               // finished L values in F layout; sentinel until written (ready flags)
-    unsigned int chunk;  // columns taken per grab
+    unsigned int chunk;  // columns taken per grab below split
+    int64_t split;       // first column-order position handed out one column at a time
     int guard_fail_policy;
     Control *ctl;
 };
@@ -308,14 +310,29 @@ __global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     T *xs = lds + wid * kRefactorLds;
     (void)wid;
-    // Columns are handed out in dependency-level order, a chunk at a time, to running
-    // wavefronts only: the earliest unfinished column is always held by a running wave
-    // whose earlier work is done, so the kernel finishes whatever the residency.
+    // Columns are handed out in dependency-level order to running wavefronts only: the
+    // earliest unfinished column is always held by a running wave whose earlier work is
+    // done, so the kernel finishes whatever the residency.  Positions below `split` (wide
+    // levels) go a chunk at a time; the narrow levels above it go one column at a time from
+    // a second counter, so that no column of a dependency chain waits behind another one
+    // grabbed by the same wave.
+    bool narrow = a.split <= 0;
     for (;;) {
-        const unsigned int c0w = grab(&a.ctl->work_refactor, a.chunk);
-        if ((int64_t)c0w >= a.n) break;
-        const int64_t cend = (int64_t)c0w + a.chunk < a.n ? (int64_t)c0w + a.chunk : a.n;
-        for (int64_t t = c0w; t < cend; ++t) {
+        int64_t cbeg = 0, cend = 0;
+        if (!narrow) {
+            const unsigned int c0w = grab(&a.ctl->work_refactor, a.chunk);
+            if ((int64_t)c0w >= a.split) narrow = true;
+            else {
+                cbeg = c0w;
+                cend = (int64_t)c0w + a.chunk < a.split ? (int64_t)c0w + a.chunk : a.split;
+            }
+        }
+        if (narrow) {
+            cbeg = a.split + (int64_t)grab(&a.ctl->work_refactor2, 1u);
+            if (cbeg >= a.n) break;
+            cend = cbeg + 1;
+        }
+        for (int64_t t = cbeg; t < cend; ++t) {
         const int j = a.order[t];
         const int64_t c0 = a.fp[j];
         const int len = (int)(a.fp[j + 1] - c0);
@@ -1174,12 +1191,12 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
     if (precision == KKT_PREC_MIXED) {
         const unsigned int chunk = work_chunk(a.n, h->grid_refactor32 * (kCoopBlock / 64));
         RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F32, d.T32,
-                              d.Ld32, chunk, h->opts.guard_policy, d.ctl};
+                              d.Ld32, chunk, h->an.refactor_split, h->opts.guard_policy, d.ctl};
         k_refactor<float><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r);
     } else {
         const unsigned int chunk = work_chunk(a.n, h->grid_refactor64 * (kCoopBlock / 64));
         RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F64, d.T64,
-                               d.Ld64, chunk, h->opts.guard_policy, d.ctl};
+                               d.Ld64, chunk, h->an.refactor_split, h->opts.guard_policy, d.ctl};
         k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r);
     }
     prof_end(h, KKT_K_REFACTOR, e0, s);
