@@ -57,11 +57,16 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile):
+# workload name and FGMRES restart of each configuration
+WORKLOADS = {1: ("kkt_single_7k", 10), 2: ("kkt_sequence_60k", 10), 3: ("kkt_sequence_500k", 30),
+             5: ("kkt_sequence_2m", 50)}
+
+
+def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, restart=10):
     dev = torch.device("cuda:0")
     v1, _ = systems[0]
     t0 = time.perf_counter()
-    s = P.Solver(pattern.rowptr, pattern.colidx, v1, precision=precision)
+    s = P.Solver(pattern.rowptr, pattern.colidx, v1, precision=precision, restart=restart)
     analysis_s = time.perf_counter() - t0
     s.bind(dev)
     vals = [torch.as_tensor(v, device=dev) for v, _ in systems]
@@ -90,25 +95,41 @@ def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile):
     wall = time.perf_counter() - t0
     lat = [a.elapsed_time(b) for a, b in ev]
     times = s.kernel_times() if profile else None
-    return dict(solver=s, analysis_s=analysis_s, wall=wall, lat=lat, infos=infos, times=times)
+    if profile:
+        s.set_profiling(False)
+    # solutions of every system of the sequence, after the timed region (for the comparison
+    # with the CPU baseline's solutions)
+    xs = []
+    for k in range(M):
+        s.refactor(vals[k])
+        s.solve(rhs[k], x, allow_noconv=True)
+        xs.append(x.cpu().numpy().copy())
+    return dict(solver=s, analysis_s=analysis_s, wall=wall, lat=lat, infos=infos, times=times, xs=xs)
 
 
-def cpu_baseline(pattern, systems, budget_s):
+def cpu_baseline(pattern, systems, budget_s, gpu_xs=None):
     """The oracle's plain direct method (ordering reused, fresh threshold-pivoted LU and
     triangular solves per system) on the first systems of the sequence, single-threaded,
-    until about budget_s seconds of work."""
+    until about budget_s seconds of work.  On the first pass over the sequence its solutions
+    are compared with the GPU's (relative difference in the infinity norm, against the bound
+    1e-8 times the condition estimate of that system); the condition estimates are not timed."""
     import oracle
     Q = oracle.order(pattern.rowptr, pattern.colidx)
     done = 0
-    t0 = time.perf_counter()
+    el = 0.0
+    cmp = []
     while True:
         v, b = systems[done % len(systems)]
-        oracle.direct_solve(pattern.rowptr, pattern.colidx, v, b, Q=Q)
+        t0 = time.perf_counter()
+        x_o, f = oracle.direct_solve(pattern.rowptr, pattern.colidx, v, b, Q=Q)
+        el += time.perf_counter() - t0
+        if gpu_xs is not None and done < len(systems):
+            rel = float(np.max(np.abs(gpu_xs[done] - x_o)) / np.max(np.abs(x_o)))
+            cmp.append((rel, f.condest(pattern.rowptr, v)))
         done += 1
-        el = time.perf_counter() - t0
         if el >= budget_s or done >= 200:
             break
-    return done, el
+    return done, el, cmp
 
 
 def main():
@@ -116,7 +137,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, help="workload: 1 (7k, one system) or 2 (60k x 20)")
+    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS),
+                    help="workload: 1 (7k, one system), 2 (60k x 20), 3 (500k x 10), 5 (2M x 5)")
     ap.add_argument("--mixed-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -147,12 +169,13 @@ def main():
     print("workload config %d: N=%d nnz=%d systems=%d" % (cfg, pattern.N, pattern.nnz, nsys),
           file=sys.stderr, flush=True)
 
-    r64 = run_gpu(P, torch, pattern, systems, args.steps, args.warmup, P.PREC_FP64, not args.no_profile)
+    wname, restart = WORKLOADS[cfg]
+    r64 = run_gpu(P, torch, pattern, systems, args.steps, args.warmup, P.PREC_FP64, not args.no_profile, restart)
     ai = r64["solver"].info()
     print("fp64 done: %.1f ms/step" % (1e3 * r64["wall"] / args.steps), file=sys.stderr, flush=True)
     rmx = None
     if args.mixed_steps > 0:
-        rmx = run_gpu(P, torch, pattern, systems, args.mixed_steps, 1, P.PREC_MIXED, False)
+        rmx = run_gpu(P, torch, pattern, systems, args.mixed_steps, 1, P.PREC_MIXED, False, restart)
         print("mixed done: %.1f ms/step" % (1e3 * rmx["wall"] / args.mixed_steps), file=sys.stderr, flush=True)
 
     infos = r64["infos"]
@@ -170,8 +193,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded KKT generator; the paper's ACTIVSg sequences are not available)",
-        "config": {"workload": "kkt_sequence_60k" if cfg == 2 else "kkt_single_7k", "N": pattern.N,
-                   "nnz": pattern.nnz, "systems": nsys, "restart": 10, "delta_tol": 1e-14,
+        "config": {"workload": wname, "N": pattern.N,
+                   "nnz": pattern.nnz, "systems": nsys, "restart": restart, "delta_tol": 1e-14,
                    "nrbe_target": 1e-12, "precision": "fp64"},
         "p50_ms": percentile(r64["lat"], 50),
         "p99_ms": percentile(r64["lat"], 99),
@@ -203,11 +226,19 @@ def main():
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per}
     if not args.no_cpu:
-        done, el = cpu_baseline(pattern, systems, args.cpu_seconds)
+        done, el, cmp = cpu_baseline(pattern, systems, args.cpu_seconds, r64["xs"])
         out["cpu_baseline"] = {"value": done / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
                                "sample": "%d systems of the same sequence, plain direct method (reused "
                                          "ordering, fresh threshold-pivoted LU + triangular solves), "
                                          "single thread, %.1f s" % (done, el)}
+        if cmp:
+            out["vs_oracle"] = {
+                "systems": len(cmp),
+                "max_rel_diff": max(r for r, _ in cmp),
+                "max_condest": max(c for _, c in cmp),
+                "all_within_1e-8_condest": all(r <= 1e-8 * c for r, c in cmp),
+                "max_ratio_to_bound": max(r / (1e-8 * c) for r, c in cmp),
+            }
     print(json.dumps(out), flush=True)
 
 

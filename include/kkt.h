@@ -87,9 +87,14 @@ typedef struct {
     double ratio_stop;      /* Richardson: stop when NSR_new > ratio_stop * NSR_old, MA57's
                                ratio test (0.5) */
     double inner_tol;       /* error-system FGMRES: relative tolerance of each inner solve (1e-2) */
+    int32_t residual;       /* KKT_RESID_FP64 (default) or KKT_RESID_DD: every true residual
+                               rho = b - K x of the refinement carried in double-double and
+                               rounded once (the extended-precision residual of three-precision
+                               iterative refinement, Section 2) */
 } kkt_opts_t;
 
 enum { KKT_IR_FGMRES = 0, KKT_IR_RICHARDSON = 1, KKT_IR_ERROR_FGMRES = 2 };
+enum { KKT_RESID_FP64 = 0, KKT_RESID_DD = 1 };
 
 /* Kernel classes reported by kkt_get_kernel_times. */
 enum {
@@ -189,8 +194,8 @@ kkt_status_t kkt_refactor(kkt_handle_t h, const double *dev_values, void *stream
 
 /* Solve K x = b for the last refactored K: direct solve, refine decision, FGMRES-IR
  * (Section 2).  dev_b, dev_x: DEVICE arrays of n float64 (distinct).  tol <= 0 uses
- * opts.delta_tol.  Synchronizes `stream` after each Arnoldi step (to read the stop flag)
- * and before returning; *info
+ * opts.delta_tol.  Waits for each Arnoldi step's stop flag while the next step runs, and
+ * synchronizes `stream` at each restart and before returning; *info
  * (may be NULL) is filled on return.  Errors: KKT_ESTATE (no refactor yet), KKT_EINVAL
  * (non-finite K values or b), KKT_ESINGULAR (guard_policy = FAIL and a guarded pivot),
  * KKT_ENOCONV (tolerance not met; x holds the last iterate, info is filled). */
@@ -201,6 +206,14 @@ kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, doubl
  * factors (the direct solve of Section 1.3, no refinement).  DEVICE arrays of n float64.
  * Enqueued on `stream`, not synchronized. */
 kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x, void *stream);
+
+/* Residual rho = b - K x of the last refactored K (original ordering), each row summed in
+ * CSR order; with opts.residual = KKT_RESID_DD the row is carried as a double-double sum
+ * (error-free products and the accurate double-word addition of Joldes, Muller and Popescu)
+ * and rounded once.  DEVICE arrays of n float64 (dev_r distinct from the others).  Enqueued
+ * on `stream`, not synchronized.  Errors: KKT_ESTATE (no refactor yet). */
+kkt_status_t kkt_residual(kkt_handle_t h, const double *dev_b, const double *dev_x, double *dev_r,
+                          void *stream);
 
 /* Copy the current device factor values (last kkt_refactor) to HOST arrays in the layout
  * of kkt_get_factor_pattern; precision 0 = FP64 factors, 1 = FP32 factors widened to

@@ -58,6 +58,7 @@ def lib():
         L.or_solve_with.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p]
         L.or_solve_with32.argtypes = [C.c_void_p, f32p, f32p, f64p, f64p]
         L.or_residual.argtypes = [i64, i64p, i32p, f64p, f64p, f64p, f64p]
+        L.or_residual_dd.argtypes = [i64, i64p, i32p, f64p, f64p, f64p, f64p]
         L.or_metrics.argtypes = [i64, i64p, i32p, f64p, f64p, f64p, f64p]
         L.or_norm_inf_mat.restype = C.c_double
         L.or_norm_inf_mat.argtypes = [i64, i64p, f64p]
@@ -205,8 +206,13 @@ class LU:
         return lib().or_condest(self._h, _p(rp, C.c_int64), _p(v, C.c_double))
 
     def fgmres_ir(self, rowptr, colidx, values, b, Lx=None, Ux=None, Lx32=None, Ux32=None,
-                  restart=10, max_restarts=20, eta=1e-12, mode=0, hist_cap=4096):
-        """FGMRES-IR with these factors as right preconditioner (see or_fgmres_ir)."""
+                  restart=10, max_restarts=20, eta=1e-12, mode=0, hist_cap=4096, residual="fp64"):
+        """FGMRES-IR with these factors as right preconditioner (see or_fgmres_ir);
+        residual="dd" forms every residual in extended precision (or_residual_dd)."""
+        if residual not in ("fp64", "dd"):
+            raise ValueError("residual must be 'fp64' or 'dd'")
+        if residual == "dd":
+            mode = int(mode) | 2
         rp, ci, v = _csr(rowptr, colidx, values)
         b = np.ascontiguousarray(b, np.float64)
         prec = 1 if Lx32 is not None else 0
@@ -233,13 +239,17 @@ class LU:
         return self.Lp, self.pinv[self.Li], self.Lx
 
 
-def residual(rowptr, colidx, values, x, b):
+def residual(rowptr, colidx, values, x, b, precision="fp64"):
+    """rho = b - K x; precision "dd" carries each row in double-double (or_residual_dd)."""
     rp, ci, v = _csr(rowptr, colidx, values)
     x = np.ascontiguousarray(x, np.float64)
     b = np.ascontiguousarray(b, np.float64)
     r = np.empty(rp.size - 1)
-    lib().or_residual(rp.size - 1, _p(rp, C.c_int64), _p(ci, C.c_int32), _p(v, C.c_double),
-                      _p(x, C.c_double), _p(b, C.c_double), _p(r, C.c_double))
+    if precision not in ("fp64", "dd"):
+        raise ValueError("precision must be 'fp64' or 'dd'")
+    fn = lib().or_residual_dd if precision == "dd" else lib().or_residual
+    fn(rp.size - 1, _p(rp, C.c_int64), _p(ci, C.c_int32), _p(v, C.c_double),
+       _p(x, C.c_double), _p(b, C.c_double), _p(r, C.c_double))
     return r
 
 

@@ -918,6 +918,58 @@ void or_residual(int64_t n, const int64_t *rp, const int32_t *ci, const double *
     }
 }
 
+/* Extended-precision residual (the higher-precision residual of iterative refinement,     */
+/* Section 2): each row's sum b_i - sum_p v_p x_c is carried as an unevaluated pair of     */
+/* doubles (hi + lo) and rounded to double once at the end.                                */
+/*   two_sum:  Knuth's error-free sum, s + e = a + b exactly.                               */
+/*   fast_two_sum: Dekker's version, valid when |a| >= |b| or a = 0.                         */
+/*   two_prod: p + e = a * b exactly, e from one fused multiply-add.                         */
+/*   dw_add: double-word + double-word, the accurate algorithm of Joldes, Muller and        */
+/*           Popescu (ACM TOMS 2017, Algorithm 6), relative error <= 3 u^2.                 */
+/* Row order: start from (b_i, 0), then add (-p_hi, -p_lo) of each product in CSR order.    */
+static void two_sum(double a, double b, double *s, double *e) {
+    double x = a + b;
+    double bv = x - a;
+    double av = x - bv;
+    *e = (a - av) + (b - bv);
+    *s = x;
+}
+
+static void fast_two_sum(double a, double b, double *s, double *e) {
+    double x = a + b;
+    *e = b - (x - a);
+    *s = x;
+}
+
+static void two_prod(double a, double b, double *p, double *e) {
+    double x = a * b;
+    *e = fma(a, b, -x);
+    *p = x;
+}
+
+static void dw_add(double xh, double xl, double yh, double yl, double *zh, double *zl) {
+    double sh, sl, th, tl, vh, vl;
+    two_sum(xh, yh, &sh, &sl);
+    two_sum(xl, yl, &th, &tl);
+    double c = sl + th;
+    fast_two_sum(sh, c, &vh, &vl);
+    double w = tl + vl;
+    fast_two_sum(vh, w, zh, zl);
+}
+
+void or_residual_dd(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
+                    const double *b, double *r) {
+    for (int64_t i = 0; i < n; i++) {
+        double hi = b[i], lo = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+            double ph, pl;
+            two_prod(v[p], x[ci[p]], &ph, &pl);
+            dw_add(hi, lo, -ph, -pl, &hi, &lo);
+        }
+        r[i] = hi;
+    }
+}
+
 double or_norm_inf_mat(int64_t n, const int64_t *rp, const double *v) {
     double m = 0.0;
     for (int64_t i = 0; i < n; i++) {
@@ -1039,6 +1091,7 @@ double or_condest(const or_lu_t *f, const int64_t *rp, const double *v) {
 /*          true NRBE <= eta; refine iff NRBE(x0) > eta.                                   */
 /*  mode 1 (paper's test): inner test |g_{j+1}| < eta ||rho0||_2 (RR on the estimated      */
 /*          residual), refine iff ||rho0||/||b|| >= eta, accept when the estimate passes. */
+/*  mode | 2: residuals rho = b - K x in extended precision (or_residual_dd).             */
 /* precision 0: FP64 factors; 1: FP32 factors (Lx32/Ux32), preconditioner in binary32.    */
 /* info: [0] iterations, [1] cycles, [2] final NRBE, [3] RR (true), [4] converged flag,   */
 /*       [5] NRBE of x0, [6] final estimated residual, [7] final true residual norm       */
@@ -1086,10 +1139,13 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
         return OR_ENOMEM;
     }
     int64_t nh = 0;
+    void (*resid)(int64_t, const int64_t *, const int32_t *, const double *, const double *, const double *,
+                  double *) = (mode & 2) ? or_residual_dd : or_residual;
+    mode &= 1;
     double kn = or_norm_inf_mat(n, rp, v);
     double bn = nrm2(n, b);
     apply_m(f, Lx, Ux, Lx32, Ux32, precision, b, x);
-    or_residual(n, rp, ci, v, x, b, r);
+    resid(n, rp, ci, v, x, b, r);
     double rho0 = nrm2(n, r);
     double rn = rho0;
     double nrbe = rn / (kn * nrm2(n, x) + bn);
@@ -1171,7 +1227,7 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
             const double *zt = Z + (size_t)t * n;
             for (int64_t i = 0; i < n; i++) x[i] += yv[t] * zt[i];
         }
-        or_residual(n, rp, ci, v, x, b, r);
+        resid(n, rp, ci, v, x, b, r);
         rn = nrm2(n, r);
         nrbe = rn / (kn * nrm2(n, x) + bn);
         if (mode == 0 ? (nrbe <= eta) : (est < eta * rho0)) converged = 1;

@@ -410,6 +410,303 @@ int pivoted_lu(int64_t n, const int64_t *rp, const int32_t *ci, const double *va
 }
 
 // Combined step-space factor F, the update positions, and the GPU schedules.
+// Triangular-solve schedule.
+//
+// The rows form a DAG (row i waits for every row it references).  Level = longest path from
+// a row without references.  Consecutive levels are grouped into *windows*; inside a window
+// the rows split into weakly connected components (edges between rows of the window), which
+// depend on each other only through earlier windows.  A component is solved by one block,
+// level by level with a barrier in between, from LDS, so a chain of dependencies inside a
+// window costs barriers, not cross-block waits.  A window grows one level at a time while
+// every component still fits a staged tile (rows, LDS bytes for its entries and externals,
+// each level covered by one pass of the block with at most `kSerial` entries per lane); a
+// single level always forms a window (its rows are independent).  Components of a window
+// are packed in order into tiles (next fit); a tile's rows at one level form a segment.  A
+// row too long to stage on its own becomes an unstaged tile.
+//
+// Tiles are numbered window by window, so every reference of a tile is to a row of an
+// earlier tile or of the same tile at an earlier segment.
+bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64_t> &rp,
+                  const std::vector<int32_t> &ci, bool lower, TriSchedule &sc, std::string *msg) {
+    constexpr int64_t kSerial = 16;  // entries per lane allowed when rows share a pass
+    const int threads = opt.tile_threads;
+    std::vector<int32_t> level(n, 0);
+    if (lower) {
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t l = 0;
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) l = std::max(l, level[ci[p]] + 1);
+            level[i] = l;
+        }
+    } else {
+        for (int64_t i = n - 1; i >= 0; --i) {
+            int32_t l = 0;
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) l = std::max(l, level[ci[p]] + 1);
+            level[i] = l;
+        }
+    }
+    const int32_t nlev = n ? 1 + *std::max_element(level.begin(), level.end()) : 0;
+    sc.levels = nlev;
+    // rows by level; within a level in the direction of the sweep
+    std::vector<int32_t> by_level(n);
+    std::vector<int32_t> lev_ptr(nlev + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++lev_ptr[level[i] + 1];
+    for (int32_t l = 0; l < nlev; ++l) lev_ptr[l + 1] += lev_ptr[l];
+    {
+        std::vector<int32_t> fill(lev_ptr.begin(), lev_ptr.end() - 1);
+        for (int64_t s = 0; s < n; ++s) {
+            const int32_t i = (int32_t)(lower ? s : n - 1 - s);
+            by_level[fill[level[i]]++] = i;
+        }
+    }
+    auto len = [&](int32_t i) { return rp[i + 1] - rp[i]; };
+    auto lanes_needed = [&](int64_t m) {  // fewest lanes (power of two) with <= kSerial entries each
+        int64_t g = 1;
+        while (g < 64 && g * kSerial < m) g <<= 1;
+        return g;
+    };
+    auto fits = [&](int64_t count, int64_t maxlen) { return count * lanes_needed(maxlen) <= threads; };
+
+    // Components of a window, with per-level statistics, by union-find over the window's rows.
+    struct LevStat {
+        int32_t level, count;
+        int64_t maxlen;
+    };
+    struct Size {
+        int64_t rows = 0, ent = 0, ext = 0;  // ext: references to earlier windows (upper bound)
+    };
+    auto stageable = [&](const Size &z) {
+        return z.rows <= opt.tile_rows && tile_lds_bytes(z.rows, z.ext, z.ent) <= opt.tile_lds;
+    };
+    std::vector<int32_t> parent(n, -1);
+    std::vector<Size> size(n);
+    std::vector<std::vector<LevStat>> stat(n);
+    auto find = [&](int32_t x) {
+        while (parent[x] != x) {
+            parent[x] = parent[parent[x]];
+            x = parent[x];
+        }
+        return x;
+    };
+    // merges the components of x and y; returns false when the result no longer fits a tile
+    auto unite = [&](int32_t x, int32_t y) {
+        x = find(x);
+        y = find(y);
+        if (x == y) return true;
+        if (stat[x].size() < stat[y].size()) std::swap(x, y);
+        std::vector<LevStat> merged;
+        merged.reserve(stat[x].size() + stat[y].size());
+        size_t u = 0, v = 0;
+        while (u < stat[x].size() || v < stat[y].size()) {
+            if (v == stat[y].size() || (u < stat[x].size() && stat[x][u].level < stat[y][v].level))
+                merged.push_back(stat[x][u++]);
+            else if (u == stat[x].size() || stat[y][v].level < stat[x][u].level)
+                merged.push_back(stat[y][v++]);
+            else {
+                merged.push_back({stat[x][u].level, stat[x][u].count + stat[y][v].count,
+                                  std::max(stat[x][u].maxlen, stat[y][v].maxlen)});
+                ++u;
+                ++v;
+            }
+        }
+        parent[y] = x;
+        size[x].rows += size[y].rows;
+        size[x].ent += size[y].ent;
+        size[x].ext += size[y].ext;
+        stat[x].swap(merged);
+        std::vector<LevStat>().swap(stat[y]);
+        if (!stageable(size[x])) return false;
+        for (const LevStat &e : stat[x])
+            if (!fits(e.count, e.maxlen)) return false;
+        return true;
+    };
+    auto add_level = [&](int32_t l, int32_t w0) {
+        bool ok = true;
+        for (int32_t r = lev_ptr[l]; r < lev_ptr[l + 1]; ++r) {
+            const int32_t i = by_level[r];
+            parent[i] = i;
+            Size z;
+            z.rows = 1;
+            z.ent = len(i);
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) z.ext += level[ci[p]] < w0;
+            size[i] = z;
+            stat[i].assign(1, LevStat{l, 1, len(i)});
+        }
+        for (int32_t r = lev_ptr[l]; r < lev_ptr[l + 1]; ++r) {
+            const int32_t i = by_level[r];
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+                if (level[ci[p]] >= w0 && !unite(i, ci[p])) ok = false;
+        }
+        return ok;
+    };
+    auto clear_window = [&](int32_t w0, int32_t w1) {
+        for (int32_t r = lev_ptr[w0]; r < lev_ptr[w1 + 1]; ++r) {
+            const int32_t i = by_level[r];
+            parent[i] = -1;
+            std::vector<LevStat>().swap(stat[i]);
+        }
+    };
+
+    sc.rows.clear();
+    sc.rows.reserve(n);
+    sc.tile_seg.assign(1, 0);
+    sc.seg_row.assign(1, 0);
+    sc.seg_lg.clear();
+    sc.tile_lds.clear();
+    sc.windows = 0;
+    std::vector<int32_t> tcount, comp_of_root(n, -1);
+    std::vector<int64_t> tmax;
+    // packs the components of window [w0, w1] into tiles
+    auto emit_window = [&](int32_t w0, int32_t w1) {
+        ++sc.windows;
+        const int32_t nl = w1 - w0 + 1;
+        // components in order of their first row (level-major order)
+        std::vector<int32_t> roots;
+        for (int32_t r = lev_ptr[w0]; r < lev_ptr[w1 + 1]; ++r) {
+            const int32_t x = find(by_level[r]);
+            if (comp_of_root[x] < 0) {
+                comp_of_root[x] = (int32_t)roots.size();
+                roots.push_back(x);
+            }
+        }
+        // rows of each component (level-major, sweep order inside a level)
+        std::vector<std::vector<int32_t>> crows(roots.size());
+        for (int32_t r = lev_ptr[w0]; r < lev_ptr[w1 + 1]; ++r) {
+            const int32_t i = by_level[r];
+            crows[comp_of_root[find(i)]].push_back(i);
+        }
+        tcount.assign(nl, 0);
+        tmax.assign(nl, 0);
+        Size tsize;
+        std::vector<int32_t> members;
+        auto close_tile = [&](bool staged) {
+            if (members.empty()) return;
+            for (int32_t l = w0; l <= w1; ++l) {
+                const int32_t cnt = tcount[l - w0];
+                if (!cnt) continue;
+                for (int32_t c : members)
+                    for (int32_t i : crows[c])
+                        if (level[i] == l) sc.rows.push_back(i);
+                int lg = 0;  // about four entries per lane, at most 64 lanes ...
+                while (lg < 6 && ((int64_t)1 << lg) * 4 < tmax[l - w0]) ++lg;
+                while (lg > 0 && ((int64_t)cnt << lg) > threads) --lg;  // ... one pass per segment
+                sc.seg_lg.push_back(lg);
+                sc.seg_row.push_back((int32_t)sc.rows.size());
+                tcount[l - w0] = 0;
+                tmax[l - w0] = 0;
+            }
+            sc.tile_seg.push_back((int32_t)sc.seg_lg.size());
+            sc.tile_lds.push_back(staged ? 1 : 0);
+            members.clear();
+            tsize = Size();
+        };
+        for (size_t c = 0; c < roots.size(); ++c) {
+            const std::vector<LevStat> &st = stat[roots[c]];
+            const Size &z = size[roots[c]];
+            if (!stageable(z)) {  // a single row too long to stage: a tile of its own
+                close_tile(true);
+                members.push_back((int32_t)c);
+                for (const LevStat &e : st) {
+                    tcount[e.level - w0] += e.count;
+                    tmax[e.level - w0] = std::max(tmax[e.level - w0], e.maxlen);
+                }
+                close_tile(false);
+                continue;
+            }
+            Size sum = tsize;
+            sum.rows += z.rows;
+            sum.ent += z.ent;
+            sum.ext += z.ext;
+            bool ok = stageable(sum);
+            for (size_t e = 0; ok && e < st.size(); ++e) {
+                const int32_t k = st[e].level - w0;
+                ok = fits(tcount[k] + st[e].count, std::max(tmax[k], st[e].maxlen));
+            }
+            if (!ok) {
+                close_tile(true);
+                sum = z;
+            }
+            for (const LevStat &e : st) {
+                tcount[e.level - w0] += e.count;
+                tmax[e.level - w0] = std::max(tmax[e.level - w0], e.maxlen);
+            }
+            tsize = sum;
+            members.push_back((int32_t)c);
+        }
+        close_tile(true);
+        for (int32_t x : roots) comp_of_root[x] = -1;
+    };
+
+    int32_t w0 = 0;
+    for (int32_t l = 0; l < nlev; ++l) {
+        if (add_level(l, w0) || l == w0) continue;
+        // level l does not fit the window: rebuild the window without it, emit it, and start
+        // a new window at l
+        clear_window(w0, l);
+        for (int32_t k = w0; k < l; ++k) add_level(k, w0);
+        emit_window(w0, l - 1);
+        clear_window(w0, l - 1);
+        w0 = l;
+        add_level(l, w0);
+    }
+    if (nlev) emit_window(w0, nlev - 1);
+    if ((int64_t)sc.rows.size() != n) {
+        *msg = "internal: triangular schedule lost rows";
+        return false;
+    }
+    // packed entries, externals and references
+    std::vector<int32_t> pos(n), tile_of(n), seg_of(n);
+    for (int64_t r = 0; r < n; ++r) pos[sc.rows[r]] = (int32_t)r;
+    for (int64_t t = 0; t < sc.tiles(); ++t)
+        for (int32_t g = sc.tile_seg[t]; g < sc.tile_seg[t + 1]; ++g)
+            for (int32_t r = sc.seg_row[g]; r < sc.seg_row[g + 1]; ++r) {
+                tile_of[r] = (int32_t)t;
+                seg_of[r] = g;
+            }
+    sc.row_ent.assign(n + 1, 0);
+    for (int64_t r = 0; r < n; ++r) sc.row_ent[r + 1] = sc.row_ent[r] + len(sc.rows[r]);
+    sc.ent_ref.assign(ci.size(), 0);
+    sc.csr2ent.assign(ci.size(), 0);
+    sc.tile_ext.assign(1, 0);
+    sc.ext_src.clear();
+    std::vector<int32_t> ext_slot(n, -1);
+    for (int64_t t = 0; t < sc.tiles(); ++t) {
+        const int32_t rb = sc.seg_row[sc.tile_seg[t]], re = sc.seg_row[sc.tile_seg[t + 1]];
+        const size_t x0 = sc.ext_src.size();
+        for (int32_t r = rb; r < re; ++r) {
+            const int32_t i = sc.rows[r];
+            int64_t e = sc.row_ent[r];
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p, ++e) {
+                const int32_t k = ci[p];
+                const int32_t pk = pos[k];
+                if (tile_of[pk] > t || seg_of[pk] >= seg_of[r]) {
+                    *msg = "internal: triangular schedule order";
+                    return false;
+                }
+                sc.csr2ent[p] = e;
+                if (!sc.tile_lds[t]) {
+                    sc.ent_ref[e] = k;
+                } else if (tile_of[pk] == t) {
+                    sc.ent_ref[e] = pk - rb;
+                } else {
+                    if (ext_slot[k] < 0) {
+                        ext_slot[k] = (int32_t)(sc.ext_src.size() - x0);
+                        sc.ext_src.push_back(k);
+                    }
+                    sc.ent_ref[e] = (re - rb) + ext_slot[k];
+                }
+            }
+        }
+        for (size_t k = x0; k < sc.ext_src.size(); ++k) ext_slot[sc.ext_src[k]] = -1;
+        sc.tile_ext.push_back((int32_t)sc.ext_src.size());
+        if (sc.tile_lds[t] &&
+            tile_lds_bytes(re - rb, (int64_t)(sc.ext_src.size() - x0), sc.row_ent[re] - sc.row_ent[rb]) > opt.tile_lds) {
+            *msg = "internal: staged tile exceeds its LDS budget";
+            return false;
+        }
+    }
+    return true;
+}
+
 int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
     const int64_t n = a.n;
     const int64_t lnz = a.nnz_l(), unz = a.nnz_u();
@@ -564,92 +861,19 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
             }
         }
     }
-    // --- triangular-solve schedules
-    auto schedule = [&](bool lower, TriSchedule &sc) {
-        const std::vector<int64_t> &rp = lower ? a.lrp : a.urp;
-        const std::vector<int32_t> &ci = lower ? a.lci : a.uci;
-        std::vector<int32_t> level(n, 0);
-        if (lower) {
-            for (int64_t i = 0; i < n; ++i) {
-                int32_t l = 0;
-                for (int64_t p = rp[i]; p < rp[i + 1]; ++p) l = std::max(l, level[ci[p]] + 1);
-                level[i] = l;
-            }
-        } else {
-            for (int64_t i = n - 1; i >= 0; --i) {
-                int32_t l = 0;
-                for (int64_t p = rp[i]; p < rp[i + 1]; ++p) l = std::max(l, level[ci[p]] + 1);
-                level[i] = l;
-            }
+    // --- triangular-solve schedules; T then holds each triangle's entries packed in solve
+    // order (L, then strict U), followed by the diagonal of U in step order
+    if (!tri_schedule(opt, n, a.lrp, a.lci, true, a.lsched, msg) ||
+        !tri_schedule(opt, n, a.urp, a.uci, false, a.usched, msg))
+        return AN_EINVAL;
+    {
+        const int64_t ubase = a.lrp[n], dbase = a.lrp[n] + a.urp[n];
+        for (int64_t t = 0; t < f; ++t) {
+            const int64_t d = a.f2t[t];
+            if (d < ubase) a.f2t[t] = (int32_t)a.lsched.csr2ent[d];
+            else if (d < dbase) a.f2t[t] = (int32_t)(ubase + a.usched.csr2ent[d - ubase]);
         }
-        const int32_t nlev = n ? 1 + *std::max_element(level.begin(), level.end()) : 0;
-        sc.levels = nlev;
-        sc.rows.resize(n);
-        for (int64_t i = 0; i < n; ++i) sc.rows[i] = (int32_t)(lower ? i : n - 1 - i);
-        std::stable_sort(sc.rows.begin(), sc.rows.end(), [&](int32_t x, int32_t y) { return level[x] < level[y]; });
-        sc.lev_ptr.assign(nlev + 1, 0);
-        for (int64_t i = 0; i < n; ++i) ++sc.lev_ptr[level[i] + 1];
-        for (int32_t l = 0; l < nlev; ++l) sc.lev_ptr[l + 1] += sc.lev_ptr[l];
-        sc.lev_lg.assign(nlev, 0);
-        for (int32_t l = 0; l < nlev; ++l) {
-            int64_t mx = 0;
-            for (int32_t r = sc.lev_ptr[l]; r < sc.lev_ptr[l + 1]; ++r)
-                mx = std::max(mx, rp[sc.rows[r] + 1] - rp[sc.rows[r]]);
-            int lg = 0;  // lanes such that each lane handles about four entries, at most 64
-            while (lg < 6 && ((int64_t)1 << lg) * 4 < mx) ++lg;
-            sc.lev_lg[l] = (int8_t)lg;
-        }
-        // tiles
-        sc.tile_row.assign(1, 0);
-        sc.tile_lev.clear();
-        int32_t open_rows = 0;  // rows in the current multi-level tile
-        auto close = [&](int32_t end) {
-            if (end > sc.tile_row.back()) sc.tile_row.push_back(end);
-        };
-        for (int32_t l = 0; l < nlev; ++l) {
-            const int32_t r0 = sc.lev_ptr[l], r1 = sc.lev_ptr[l + 1];
-            const int32_t cnt = r1 - r0;
-            // a level joins a multi-level tile only when one pass of the block covers it
-            // (each lane group then owns at most one row of the level)
-            if (cnt > opt.narrow_rows || cnt > (opt.tile_threads >> sc.lev_lg[l])) {
-                close(r0);
-                open_rows = 0;
-                const int32_t chunk = std::max(1, opt.tile_threads >> sc.lev_lg[l]);
-                for (int32_t s0 = r0; s0 < r1; s0 += chunk) {
-                    sc.tile_lev.push_back(l);
-                    close(std::min(s0 + chunk, r1));
-                }
-                continue;
-            }
-            if (open_rows > 0 && open_rows + cnt > opt.tile_rows) {
-                close(r0);
-                open_rows = 0;
-            }
-            if (open_rows == 0) sc.tile_lev.push_back(l);
-            open_rows += cnt;
-        }
-        close((int32_t)n);
-        if ((int64_t)sc.tile_lev.size() != sc.tiles()) {
-            *msg = "internal: tile bookkeeping";
-            return false;
-        }
-        // encoded references
-        std::vector<int32_t> pos(n), tile_of(n);
-        for (int64_t r = 0; r < n; ++r) pos[sc.rows[r]] = (int32_t)r;
-        for (int64_t t = 0; t < sc.tiles(); ++t)
-            for (int32_t r = sc.tile_row[t]; r < sc.tile_row[t + 1]; ++r) tile_of[r] = (int32_t)t;
-        sc.ref.resize(ci.size());
-        for (int64_t i = 0; i < n; ++i) {
-            const int32_t ti = tile_of[pos[i]];
-            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-                const int32_t k = ci[p];
-                const int32_t pk = pos[k];
-                sc.ref[p] = tile_of[pk] == ti ? -(pk - sc.tile_row[ti] + 1) : k;
-            }
-        }
-        return true;
-    };
-    if (!schedule(true, a.lsched) || !schedule(false, a.usched)) return AN_EINVAL;
+    }
     return AN_OK;
 }
 

@@ -15,26 +15,45 @@ struct AnalysisOptions {
     int64_t nd_leaf = 64;
     double pivot_tau = 0.1;
     int tile_threads = 256;      // threads of a triangular-solve block
-    int narrow_rows = 256;       // levels with at most this many rows join multi-level tiles
-    int tile_rows = 2048;        // rows of a multi-level tile (its values live in LDS)
+    int tile_rows = 2048;        // rows of a tile at most
+    int64_t tile_lds = 65536;    // LDS bytes of a staged tile at most (tile_lds_bytes)
     int narrow_columns = 1024;   // refactorization levels with at most this many columns are
                                  // handed out one column at a time
 };
 
-// Schedule of one triangular solve.  Rows are sorted by DAG level.  A tile is a contiguous
-// run of rows processed by one block: either a run of whole narrow levels (processed level
-// by level with a block barrier in between, values kept in LDS) or a slice of one wide level.
+// Schedule of one triangular solve.  A tile is a contiguous run of rows solved by one block;
+// it is cut into segments, each a set of mutually independent rows covered by one pass of the
+// block (2^lg lanes per row), with a block barrier between segments.  Tiles are handed out in
+// order; every reference of a row is to an earlier tile or an earlier segment of its own tile.
+//
+// Entries are stored "packed": the rows of the solve order one after the other, each row's
+// entries in ascending column order.  A staged tile (tile_lds = 1) is copied into LDS when its
+// block takes it: its entries, its rows' right-hand-side data, and the solution values of the
+// rows it references in earlier tiles ("externals"); its references are then LDS slots
+// (0..rows-1: the tile's own rows, rows + k: external k).  An unstaged tile (one row too long
+// to stage) reads its entries from global memory and its references are source rows.
 struct TriSchedule {
     std::vector<int32_t> rows;      // solve order
-    std::vector<int32_t> lev_ptr;   // start of each level in rows (levels + 1)
-    std::vector<int8_t> lev_lg;     // log2 of the lanes per row of each level
-    std::vector<int32_t> tile_row;  // start of each tile in rows (tiles + 1)
-    std::vector<int32_t> tile_lev;  // level of each tile's first row
-    std::vector<int32_t> ref;       // per CSR entry: source row (>= 0), or -(slot + 1) when the
-                                    // source row is in the same tile (LDS slot)
-    int64_t levels = 0;
-    int64_t tiles() const { return (int64_t)tile_row.size() - 1; }
+    std::vector<int32_t> tile_seg;  // first segment of each tile (tiles + 1)
+    std::vector<int32_t> seg_row;   // start of each segment in rows (segments + 1)
+    std::vector<int32_t> seg_lg;    // log2 of the lanes per row of each segment
+    std::vector<int64_t> row_ent;   // first packed entry of each position of rows (n + 1)
+    std::vector<int32_t> ent_ref;   // per packed entry: LDS slot (staged tile) or source row
+    std::vector<int32_t> tile_ext;  // first external of each tile (tiles + 1)
+    std::vector<int32_t> ext_src;   // source row of each external
+    std::vector<uint8_t> tile_lds;  // 1: staged in LDS, 0: entries read from global memory
+    std::vector<int64_t> csr2ent;   // CSR entry (row-wise layout of the triangle) -> packed entry
+    int64_t levels = 0;             // depth of the dependency DAG
+    int64_t windows = 0;            // groups of levels whose tiles are mutually independent
+    int64_t tiles() const { return (int64_t)tile_seg.size() - 1; }
+    int64_t segments() const { return (int64_t)seg_row.size() - 1; }
 };
+
+// LDS bytes a staged tile needs with FP64 values (the kernel's layout: solution slots, rhs,
+// diagonal, entry values; row ids, column-permutation ids, row offsets; 16-bit references).
+inline int64_t tile_lds_bytes(int64_t rows, int64_t ext, int64_t ent) {
+    return 8 * (rows + ext) + 36 * rows + 10 * ent + 32;
+}
 
 // Everything derived from the pattern and the first system's values.
 //
@@ -76,8 +95,10 @@ struct Analysis {
     // its update chain as early as possible.
     int64_t refactor_split = 0;
 
-    // Solve layout T = [L strict CSR (nnz_l) | U strict CSR (nnz_u - n) | U diagonal (n)],
-    // all in step space; f2t maps each F entry to its T index.
+    // Row-wise triangles in step space (strict L, strict U), from which the solve schedules
+    // are built.  Solve layout T = [L packed (nnz_l) | strict U packed (nnz_u - n) | U
+    // diagonal (n, step order)], the packed orders being those of lsched / usched; f2t maps
+    // each F entry to its T index.
     std::vector<int64_t> lrp, urp;  // n+1 each
     std::vector<int32_t> lci, uci;  // column indices (steps), ascending per row
     std::vector<int32_t> f2t;

@@ -13,6 +13,7 @@ constexpr int kStreamGridMax = 256;    // blocks of the streaming kernels (parti
 constexpr int kCoopBlock = 256;        // threads per block of the refactorization
 constexpr int kTileThreads = 256;      // threads per block of the triangular solves
 constexpr int kTileRows = 2048;        // rows of a multi-level solve tile (values in LDS)
+constexpr int kTileLds = 65536;        // LDS bytes of a staged solve tile
 constexpr int kRefactorLds = 1024;     // factor entries staged in LDS per wavefront
 // Spin limit of one dependency wait (iterations of a short sleep, a few seconds in all);
 // exceeding it marks Control::hang and lets every wave run to completion.
@@ -47,6 +48,16 @@ struct Control {
     unsigned int work_lower;        // next task index to hand out (L solve)
     unsigned int work_upper;        // next task index to hand out (U solve)
     unsigned int work_refactor2;    // next narrow-level column to hand out (refactorization)
+};
+
+// What the host needs after each Arnoldi step, written by the normalization kernel into
+// pinned host memory (one record per step of the cycle).
+struct StepRecord {
+    int stop;
+    unsigned int hang;
+    int jdone;
+    int pad;
+    double est;
 };
 
 // Host-visible summary copied back once per cycle.

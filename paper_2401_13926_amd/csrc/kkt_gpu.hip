@@ -12,9 +12,9 @@
 //                            handed out in dependency-level order; a column starts its update
 //                            chain at once and waits per entry of each source column (every
 //                            finished L entry is its own ready flag, so no memory fences)
-//   k_trsv<T, LOWER>         row-oriented triangular solve; rows in level order, a wavefront
-//                            takes up to 64/g rows of one level (g lanes per row); a solution
-//                            entry is its own ready flag (a NaN sentinel until written)
+//   k_trsv<T, LOWER>         row-oriented triangular solve by tiles (a block walks the
+//                            segments of its tile, g lanes per row); a solution entry is its
+//                            own ready flag (a NaN sentinel until written)
 //   k_spmv_dots, k_cgs_*, k_normalize, k_resid, k_xupdate   Krylov kernels; block partial
 //                            sums are reduced by the next kernel in fixed order (deterministic,
 //                            no fences)
@@ -373,20 +373,22 @@ __global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------------------
-// triangular solves in solve layout (step space), rows in level order
+// triangular solves in solve layout (step space), by tiles of segments
 // ---------------------------------------------------------------------------------------
 
 template <typename T> struct TrsvArgs {
     int64_t ntiles;
-    const int32_t *tile_row;  // tile start in rows (ntiles + 1)
-    const int32_t *tile_lev;  // level of each tile's first row
-    const int32_t *lev_ptr;   // level start in rows
-    const int8_t *lev_lg;     // log2 lanes per row of each level
+    const int32_t *tile_seg;  // first segment of each tile (ntiles + 1)
+    const int32_t *seg_row;   // segment start in rows
+    const int32_t *seg_lg;    // log2 lanes per row of each segment
     const int32_t *rows;      // solve order
-    const int64_t *rp;
-    const int32_t *ref;       // source row, or -(LDS slot + 1) inside the tile
-    const T *val;
-    const T *diag;            // upper only
+    const int64_t *row_ent;   // first packed entry of each position of rows
+    const int32_t *ent_ref;   // LDS slot (staged tile) or source row (unstaged tile)
+    const int32_t *tile_ext;  // first external of each tile
+    const int32_t *ext_src;   // source row of each external
+    const uint8_t *tile_lds;  // 1: staged tile
+    const T *val;             // packed entry values
+    const T *diag;            // upper only: diagonal of U in step order
     const double *rhs64;      // lower: right-hand side in original order (gathered by prow)
     const int32_t *prow;      // lower: pivot rows
     const T *rhs_step;        // upper: L-solve result (step order)
@@ -398,116 +400,129 @@ template <typename T> struct TrsvArgs {
     unsigned int *hang;
 };
 
-
-// Operands of one row of one level, loaded ahead of time: the row, its first (up to) four
-// entries per lane (reference and value) and, for references outside the tile, the
-// solution entry as read so far (the sentinel if it was not written yet).
-template <typename T> struct RowPrefetch {
-    int i;        // row (step index), -1 when this lane group has no row at this level
-    int64_t p0;   // first entry of this lane, pe end of the row
-    int64_t pe;
-    int c[4];
-    T v[4], xv[4];
-};
-
-template <typename T>
-__device__ __forceinline__ RowPrefetch<T> trsv_prefetch(const TrsvArgs<T> &a, int32_t lev, int32_t rb, int32_t re,
-                                                        int tid) {
-    RowPrefetch<T> f;
-    f.i = -1;
-    f.p0 = f.pe = 0;
-    const int32_t lb = a.lev_ptr[lev] > rb ? a.lev_ptr[lev] : rb;
-    const int32_t le = a.lev_ptr[lev + 1] < re ? a.lev_ptr[lev + 1] : re;
-    const int lg = a.lev_lg[lev];
-    const int g = 1 << lg;
-    const int32_t r = lb + (tid >> lg);
-    if (r < le) {
-        f.i = a.rows[r];
-        f.p0 = a.rp[f.i] + (tid & (g - 1));
-        f.pe = a.rp[f.i + 1];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t pp = f.p0 + (int64_t)u * g;
-        const bool in = f.i >= 0 && pp < f.pe;
-        f.c[u] = in ? a.ref[pp] : INT32_MIN;
-        f.v[u] = in ? a.val[pp] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) f.xv[u] = f.c[u] >= 0 ? a.out[f.c[u]] : T(0);
-    return f;
+// Triangular solve by tiles.  Tiles are handed out in order to running blocks; a tile's
+// references point to earlier tiles or to earlier segments of the same tile, so the earliest
+// unfinished tile is always held by a running block that can finish it.
+//
+// A staged tile is first copied into LDS with coalesced loads: its packed entries (values and
+// 16-bit slot references), each row's id, entry offset and right-hand-side data, and the
+// solution values of its externals (rows of earlier tiles; an entry still holding the
+// sentinel is polled until its producer stores it).  The segments then run from LDS only,
+// one pass of the block each (a lane group owns at most one row) with a barrier in between:
+// no global load, hence no wait on memory, inside the segment loop; results go to LDS for
+// the following segments and to the global solution with one coherent store each (every
+// solution entry is its own ready flag).  An unstaged tile (one long row) is solved by one
+// wavefront reading its entries and sources from global memory.
+// Read-only schedule data seen through the constant address space: with a uniform index the
+// compiler loads it through the scalar cache, so waiting for it never waits for the
+// kernel's outstanding vector stores.
+template <typename P> __device__ __forceinline__ const __attribute__((address_space(4))) P *uniform_ro(const P *p) {
+    return (const __attribute__((address_space(4))) P *)p;
 }
 
-// Triangular solve by tiles.  Tiles are handed out in level order to running blocks.  Every
-// level of a tile fits one pass of the block (a lane group owns at most one row), so a
-// multi-level tile walks its levels with one barrier each, values of the tile kept in LDS
-// (references inside the tile are LDS slots); the operands of the next level -- indices,
-// values and solution entries of other tiles -- are loaded before the barrier.  References
-// to other tiles read the global solution, whose entries are their own ready flags (plain
-// loads can only return the sentinel or the final value; sentinels are then polled).  Rows of
-// one level are independent, so lane groups of a wavefront never wait on each other.
 template <typename T, bool kLower>
 __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
-    __shared__ T lds[kTileRows];
+    __shared__ __align__(16) unsigned char smem[kTileLds];
     __shared__ unsigned int tile_sh;
     if (a.stopflag && a.stopflag->stop) return;
     const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0) tile_sh = atomicAdd(a.work, 1u);
         __syncthreads();
-        const unsigned int t = tile_sh;
+        const int t = __builtin_amdgcn_readfirstlane((int)tile_sh);
         __syncthreads();
         if ((int64_t)t >= a.ntiles) break;
-        const int32_t rb = a.tile_row[t], re = a.tile_row[t + 1];
-        int32_t lev = a.tile_lev[t];
-        RowPrefetch<T> cur = trsv_prefetch(a, lev, rb, re, tid);
-        for (;;) {
-            const int lg = a.lev_lg[lev];
-            const int g = 1 << lg;
-            // operands of the next level of this tile, if any
-            const bool more = a.lev_ptr[lev + 1] < re;
-            RowPrefetch<T> nxt;
-            nxt.i = -1;
-            if (more) nxt = trsv_prefetch(a, lev + 1, rb, re, tid);
-            T acc = 0;
-            if (cur.i >= 0) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (cur.c[u] == INT32_MIN) continue;
-                    T xk;
-                    if (cur.c[u] < 0) xk = lds[-cur.c[u] - 1];
-                    else xk = is_sentinel(cur.xv[u]) ? load_ready(a.out + cur.c[u], a.hang) : cur.xv[u];
-                    const T prod = cur.v[u] * xk;
+        const auto tile_seg = uniform_ro(a.tile_seg);
+        const auto seg_row = uniform_ro(a.seg_row);
+        const auto seg_lg = uniform_ro(a.seg_lg);
+        const auto row_ent = uniform_ro(a.row_ent);
+        const int s0 = tile_seg[t], s1 = tile_seg[t + 1];
+        const int rb = seg_row[s0], re = seg_row[s1];
+        const int nr = re - rb;
+        const int64_t eb = row_ent[rb];
+        const int ne = (int)(row_ent[re] - eb);
+        if (!uniform_ro(a.tile_lds)[t]) {
+            // one row, one wavefront, entries and sources in global memory
+            if (tid < 64) {
+                const int i = a.rows[rb];
+                T acc = 0;
+                for (int e = tid; e < ne; e += 64) {
+                    const int c = a.ent_ref[eb + e];
+                    T xk = a.out[c];
+                    if (is_sentinel(xk)) xk = load_ready(a.out + c, a.hang);
+                    const T prod = a.val[eb + e] * xk;
                     acc = acc + prod;
                 }
-                // entries beyond the first four per lane (rows longer than 256 entries)
-                for (int64_t p = cur.p0 + 4 * (int64_t)g; p < cur.pe; p += g) {
-                    const int c = a.ref[p];
-                    T xk;
-                    if (c < 0) xk = lds[-c - 1];
-                    else {
-                        xk = a.out[c];
-                        if (is_sentinel(xk)) xk = load_ready(a.out + c, a.hang);
-                    }
-                    const T prod = a.val[p] * xk;
+                for (int o = 1; o < 64; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
+                if (tid == 0) {
+                    T res;
+                    if (kLower) res = (T)a.rhs64[a.prow[i]] - acc;
+                    else res = (a.rhs_step[i] - acc) / a.diag[i];
+                    store_ready(a.out + i, res);
+                    if (!kLower) a.xout[a.q[i]] = (double)res;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        const int xb = uniform_ro(a.tile_ext)[t];
+        const int nx = uniform_ro(a.tile_ext)[t + 1] - xb;
+        // LDS carve-up: 8-byte arrays first, then 4-byte, then 2-byte
+        T *xs = reinterpret_cast<T *>(smem);       // nr + nx solution slots
+        T *rhs = xs + nr + nx;                     // nr
+        T *dg = rhs + nr;                          // nr (upper)
+        T *vals = dg + nr;                         // ne
+        int32_t *rid = reinterpret_cast<int32_t *>(vals + ne);  // nr
+        int32_t *qid = rid + nr;                   // nr (upper)
+        int32_t *roff = qid + nr;                  // nr + 1
+        uint16_t *refs = reinterpret_cast<uint16_t *>(roff + nr + 1);  // ne
+        for (int k = tid; k < ne; k += kTileThreads) {
+            vals[k] = a.val[eb + k];
+            refs[k] = (uint16_t)a.ent_ref[eb + k];
+        }
+        for (int r = tid; r < nr; r += kTileThreads) {
+            const int i = a.rows[rb + r];
+            rid[r] = i;
+            roff[r] = (int32_t)(a.row_ent[rb + r] - eb);
+            if (kLower) {
+                rhs[r] = (T)a.rhs64[a.prow[i]];
+            } else {
+                rhs[r] = a.rhs_step[i];
+                dg[r] = a.diag[i];
+                qid[r] = a.q[i];
+            }
+        }
+        if (tid == 0) roff[nr] = ne;
+        for (int k = tid; k < nx; k += kTileThreads) {
+            const int c = a.ext_src[xb + k];
+            T v = a.out[c];
+            if (is_sentinel(v)) v = load_ready(a.out + c, a.hang);
+            xs[nr + k] = v;
+        }
+        __syncthreads();
+        for (int sg = s0; sg < s1; ++sg) {
+            const int lb = seg_row[sg] - rb, le = seg_row[sg + 1] - rb;
+            const int lg = seg_lg[sg];
+            const int g = 1 << lg;
+            const int r = lb + (tid >> lg);
+            T acc = 0;
+            if (r < le) {
+                const int e1 = roff[r + 1];
+                for (int e = roff[r] + (tid & (g - 1)); e < e1; e += g) {
+                    const T prod = vals[e] * xs[refs[e]];
                     acc = acc + prod;
                 }
             }
             for (int o = 1; o < g; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
-            if (cur.i >= 0 && (tid & (g - 1)) == 0) {
-                const int i = cur.i;
+            if (r < le && (tid & (g - 1)) == 0) {
                 T res;
-                if (kLower) res = (T)a.rhs64[a.prow[i]] - acc;
-                else res = (a.rhs_step[i] - acc) / a.diag[i];
-                const int32_t lb = a.lev_ptr[lev] > rb ? a.lev_ptr[lev] : rb;
-                lds[lb + (tid >> lg) - rb] = res;
-                store_ready(a.out + i, res);
-                if (!kLower) a.xout[a.q[i]] = (double)res;
+                if (kLower) res = rhs[r] - acc;
+                else res = (rhs[r] - acc) / dg[r];
+                xs[r] = res;
+                store_ready(a.out + rid[r], res);
+                if (!kLower) a.xout[qid[r]] = (double)res;
             }
             __syncthreads();
-            if (!more) break;
-            ++lev;
-            cur = nxt;
         }
     }
 }
@@ -585,6 +600,7 @@ __device__ void reduce_cols(const double *buf, int G, int m, double *out, double
 // w = K z_j; partials (buffer 0): V_t . w for t <= j, and w . w at t = j + 1
 __global__ void __launch_bounds__(kStreamBlock) k_spmv_dots(KrylovArgs a, int j) {
     __shared__ double red[(kRestartMax + 2) * (kStreamBlock / 64)];
+    if (a.ctl->stop) return;  // enqueued ahead of the host's stop test
     int64_t r0, r1;
     block_rows(a.n, r0, r1);
     const double *z = a.Z + (int64_t)j * a.n;
@@ -612,6 +628,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_spmv_dots(KrylovArgs a, int j)
 __global__ void __launch_bounds__(kStreamBlock) k_cgs_pass2(KrylovArgs a, int j) {
     __shared__ double red[(kRestartMax + 2) * (kStreamBlock / 64)];
     __shared__ double h[kRestartMax + 2];
+    if (a.ctl->stop) return;
     const int G = gridDim.x;
     reduce_cols(partbuf(a, 0), G, j + 2, h, red);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -644,6 +661,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_cgs_pass2(KrylovArgs a, int j)
 __global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j) {
     __shared__ double red[(kRestartMax + 2) * (kStreamBlock / 64)];
     __shared__ double h[kRestartMax + 1];
+    if (a.ctl->stop) return;
     const int G = gridDim.x;
     reduce_cols(partbuf(a, 1), G, j + 1, h, red);
     if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -667,13 +685,16 @@ __global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j
 // hn = ||w|| (reduce buffer 2); Hessenberg column h1 + h2, previous rotations, a new
 // Givens rotation, the estimated residual |g_{j+1}| and the stop test -- computed
 // identically in every block (only block 0 stores them); then v_{j+1} = w / hn unless the
-// step broke down, and the solve sentinels are re-armed when the cycle goes on.
+// step broke down, and the solve sentinels are re-armed when the cycle goes on.  Block 0
+// also writes the step's record (stop, hang, estimate) to host memory.
 template <typename T>
-__global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j, int restart, T *s1, T *s2) {
+__global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j, int restart, T *s1, T *s2,
+                                                            StepRecord *rec) {
     __shared__ double sh[3];
     __shared__ double red[kStreamBlock / 64];
     __shared__ double hsq[1];
     Control *c = a.ctl;
+    if (c->stop) return;
     reduce_cols(partbuf(a, 2), gridDim.x, 1, hsq, red);
     if (threadIdx.x == 0) {
         const double hn = sqrt(hsq[0]);
@@ -715,6 +736,11 @@ __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j,
                 c->work_lower = 0;
                 c->work_upper = 0;
             }
+            StepRecord *r = rec + j;
+            __hip_atomic_store(&r->est, est, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&r->jdone, j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&r->hang, c->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&r->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
     __syncthreads();
@@ -732,8 +758,49 @@ __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j,
     }
 }
 
+// Row i of rho = b - K x in double-double: the pair (hi, lo) starts at (b_i, 0) and each
+// product v*x enters as its exact pair (v*x rounded, and the rounding error from one fused
+// multiply-add), added with the accurate double-word sum of Joldes, Muller and Popescu
+// (ACM TOMS 2017, relative error <= 3u^2); the row is rounded once, to hi.
+__device__ __forceinline__ void dd_accumulate(double &hi, double &lo, double v, double x) {
+    const double ph = v * x;
+    const double pl = fma(v, x, -ph);
+    const double yh = -ph, yl = -pl;
+    // exact sums of the high and of the low parts (Knuth)
+    const double sh = hi + yh;
+    const double sbv = sh - hi;
+    const double sl = (hi - (sh - sbv)) + (yh - sbv);
+    const double th = lo + yl;
+    const double tbv = th - lo;
+    const double tl = (lo - (th - tbv)) + (yl - tbv);
+    // renormalize twice (Dekker: |sh| >= |c|, |vh| >= |w|)
+    const double c = sl + th;
+    const double vh = sh + c;
+    const double vl = c - (vh - sh);
+    const double w = tl + vl;
+    const double zh = vh + w;
+    lo = w - (zh - vh);
+    hi = zh;
+}
+
+template <bool kDD>
+__device__ __forceinline__ double resid_row(const KrylovArgs &a, const double *x, double bi, int64_t i) {
+    if (kDD) {
+        double hi = bi, lo = 0.0;
+        for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) dd_accumulate(hi, lo, a.kval[p], x[a.ci[p]]);
+        return hi;
+    }
+    double s = 0.0;
+    for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+        const double prod = a.kval[p] * x[a.ci[p]];
+        s = s + prod;
+    }
+    return bi - s;
+}
+
 // rho = b - K x; partials (buffer 0): ||rho||^2, ||x||^2, ||b||^2, non-finite b flag,
 // max |rho_i|, max |x_i|
+template <bool kDD>
 __global__ void __launch_bounds__(kStreamBlock) k_resid(KrylovArgs a, const double *b, const double *x, double *r) {
     __shared__ double red[kStreamBlock / 64];
     int64_t r0, r1;
@@ -741,13 +808,8 @@ __global__ void __launch_bounds__(kStreamBlock) k_resid(KrylovArgs a, const doub
     double sr = 0.0, sx = 0.0, sb = 0.0, mr = 0.0, mx = 0.0;
     int badb = 0;
     for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        double s = 0.0;
-        for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
-            const double prod = a.kval[p] * x[a.ci[p]];
-            s = s + prod;
-        }
         const double bi = b[i];
-        const double ri = bi - s;
+        const double ri = resid_row<kDD>(a, x, bi, i);
         r[i] = ri;
         sr += ri * ri;
         sx += x[i] * x[i];
@@ -876,13 +938,15 @@ struct DevLayout {
     int32_t *fi, *fdiag, *order, *f2t;
     int64_t *relptr, *fsrc;
     int32_t *relpos;
-    int64_t *lrp, *urp, *krp;
+    int64_t *krp;
     int32_t *lci, *uci, *kci;
     int32_t *prow, *q;
     // triangular-solve schedules (L, U): rows, level starts, lanes, tiles, references
-    int32_t *l_rows, *l_lev, *l_tile, *l_tlev, *l_ref;
-    int32_t *u_rows, *u_lev, *u_tile, *u_tlev, *u_ref;
-    int8_t *l_lg, *u_lg;
+    int32_t *l_rows, *l_seg, *l_tseg, *l_ref, *l_text, *l_esrc;
+    int32_t *u_rows, *u_seg, *u_tseg, *u_ref, *u_text, *u_esrc;
+    int64_t *l_rent, *u_rent;
+    int32_t *l_slg, *u_slg;
+    uint8_t *l_tlds, *u_tlds;
     // values
     double *kval, *F64, *T64;
     float *F32, *T32;
@@ -914,6 +978,9 @@ struct kkt_handle_s {
     int factor_precision = 0;
     int grid_refactor64 = 0, grid_refactor32 = 0, grid_trsv64 = 0, grid_trsv32 = 0, grid_stream = 0;
     kkt::ControlSummary *host_ctl = nullptr;  // pinned
+    kkt::StepRecord *host_rec = nullptr;      // pinned, kRestartMax records
+    kkt::StepRecord *dev_rec = nullptr;       // the same memory as seen by kernels
+    hipEvent_t step_ev[2] = {nullptr, nullptr};
     int restart_alloc = 0;
     bool fp64_current = false;  // mixed mode: FP64 factors of the current system exist
     // per-launch timing (kkt_set_profiling)
@@ -1009,8 +1076,9 @@ struct Planner {
 
 // Offsets of every array inside the workspace (also gives the total size).
 struct Offsets {
-    size_t fp, fi, fdiag, order, f2t, relptr, fsrc, relpos, lrp, urp, krp, kci, l_rows, l_lev, l_tile,
-        l_tlev, l_ref, l_lg, u_rows, u_lev, u_tile, u_tlev, u_ref, u_lg, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
+    size_t fp, fi, fdiag, order, f2t, relptr, fsrc, relpos, krp, kci, l_rows, l_seg, l_tseg,
+        l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
+        u_rent, u_tlds, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
         z32, dv, rr, part, ctl, total;
 };
 
@@ -1028,22 +1096,26 @@ Offsets plan(const kkt_handle_t h) {
     o.relptr = p.take<int64_t>(n + 1);
     o.fsrc = p.take<int64_t>(f);
     o.relpos = p.take<int32_t>(a.relpos.size());
-    o.lrp = p.take<int64_t>(n + 1);
-    o.urp = p.take<int64_t>(n + 1);
     o.krp = p.take<int64_t>(n + 1);
     o.kci = p.take<int32_t>(a.nnz);
     o.l_rows = p.take<int32_t>(n);
-    o.l_lev = p.take<int32_t>(a.lsched.lev_ptr.size());
-    o.l_tile = p.take<int32_t>(a.lsched.tile_row.size());
-    o.l_tlev = p.take<int32_t>(a.lsched.tile_lev.size());
-    o.l_ref = p.take<int32_t>(a.lsched.ref.size());
-    o.l_lg = p.take<int8_t>(a.lsched.lev_lg.size());
+    o.l_seg = p.take<int32_t>(a.lsched.seg_row.size());
+    o.l_tseg = p.take<int32_t>(a.lsched.tile_seg.size());
+    o.l_ref = p.take<int32_t>(a.lsched.ent_ref.size());
+    o.l_text = p.take<int32_t>(a.lsched.tile_ext.size());
+    o.l_esrc = p.take<int32_t>(a.lsched.ext_src.size());
+    o.l_rent = p.take<int64_t>(a.lsched.row_ent.size());
+    o.l_tlds = p.take<uint8_t>(a.lsched.tile_lds.size());
+    o.l_slg = p.take<int32_t>(a.lsched.seg_lg.size());
     o.u_rows = p.take<int32_t>(n);
-    o.u_lev = p.take<int32_t>(a.usched.lev_ptr.size());
-    o.u_tile = p.take<int32_t>(a.usched.tile_row.size());
-    o.u_tlev = p.take<int32_t>(a.usched.tile_lev.size());
-    o.u_ref = p.take<int32_t>(a.usched.ref.size());
-    o.u_lg = p.take<int8_t>(a.usched.lev_lg.size());
+    o.u_seg = p.take<int32_t>(a.usched.seg_row.size());
+    o.u_tseg = p.take<int32_t>(a.usched.tile_seg.size());
+    o.u_ref = p.take<int32_t>(a.usched.ent_ref.size());
+    o.u_text = p.take<int32_t>(a.usched.tile_ext.size());
+    o.u_esrc = p.take<int32_t>(a.usched.ext_src.size());
+    o.u_rent = p.take<int64_t>(a.usched.row_ent.size());
+    o.u_tlds = p.take<uint8_t>(a.usched.tile_lds.size());
+    o.u_slg = p.take<int32_t>(a.usched.seg_lg.size());
     o.prow = p.take<int32_t>(n);
     o.q = p.take<int32_t>(n);
     o.kval = p.take<double>(a.nnz);
@@ -1116,20 +1188,21 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     const TriSchedule &sc = lower ? a.lsched : a.usched;
     t.ntiles = sc.tiles();
     const DevLayout &d = h->d;
-    t.tile_row = lower ? d.l_tile : d.u_tile;
-    t.tile_lev = lower ? d.l_tlev : d.u_tlev;
-    t.lev_ptr = lower ? d.l_lev : d.u_lev;
-    t.lev_lg = lower ? d.l_lg : d.u_lg;
+    t.tile_seg = lower ? d.l_tseg : d.u_tseg;
+    t.seg_row = lower ? d.l_seg : d.u_seg;
+    t.seg_lg = lower ? d.l_slg : d.u_slg;
     t.rows = lower ? d.l_rows : d.u_rows;
-    t.ref = lower ? d.l_ref : d.u_ref;
+    t.row_ent = lower ? d.l_rent : d.u_rent;
+    t.ent_ref = lower ? d.l_ref : d.u_ref;
+    t.tile_ext = lower ? d.l_text : d.u_text;
+    t.ext_src = lower ? d.l_esrc : d.u_esrc;
+    t.tile_lds = lower ? d.l_tlds : d.u_tlds;
     const T *base = (const T *)(is64 ? (void *)d.T64 : (void *)d.T32);
     if (lower) {
-        t.rp = d.lrp;
         t.val = base;
         t.rhs64 = rhs64;
         t.prow = d.prow;
     } else {
-        t.rp = d.urp;
         t.val = base + a.lrp[a.n];
         t.diag = base + a.lrp[a.n] + a.urp[a.n];
         t.rhs_step = rhs_step;
@@ -1206,6 +1279,11 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
     return KKT_OK;
 }
 
+void launch_resid(kkt_handle_t h, const KrylovArgs &ka, const double *b, const double *x, double *r, hipStream_t s) {
+    if (h->opts.residual == KKT_RESID_DD) k_resid<true><<<h->grid_stream, kStreamBlock, 0, s>>>(ka, b, x, r);
+    else k_resid<false><<<h->grid_stream, kStreamBlock, 0, s>>>(ka, b, x, r);
+}
+
 kkt_status_t read_ctl(kkt_handle_t h, hipStream_t s) {
     KKT_HIP(h, hipMemcpyAsync(h->host_ctl, h->d.ctl, sizeof(ControlSummary), hipMemcpyDeviceToHost, s));
     KKT_HIP(h, hipStreamSynchronize(s));
@@ -1219,8 +1297,9 @@ kkt_status_t read_ctl(kkt_handle_t h, hipStream_t s) {
 
 // One FGMRES-IR solve with the factors currently in the workspace (Section 2.1): x0 from
 // the direct solve, the refine test of Section 2.3, then restart cycles whose solution is
-// formed only at the end of the cycle.  The host reads the stop flag after every Arnoldi
-// step, so no kernel is launched past the end of a cycle.
+// formed only at the end of the cycle.  The host reads each Arnoldi step's stop flag while
+// the next step runs; at most one step is enqueued past the end of a cycle, and its kernels
+// return at once.
 // require_nrbe = false runs FGMRES as an inner solver (acceptance on its estimate only).
 template <typename T>
 kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, kkt_solve_info_t *info,
@@ -1238,7 +1317,7 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     rearm<T>(h, s);
     KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
     e0 = prof_begin(h, s);
-    k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+    launch_resid(h, ka, b, x, d.r, s);
     k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G);
     prof_end(h, KKT_K_RESID, e0, s);
     KKT_HIP(h, hipGetLastError());
@@ -1282,33 +1361,50 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         e0 = prof_begin(h, s);
         k_cycle_start<T><<<G, kStreamBlock, 0, s>>>(ka, d.r, inner, y, z);
         prof_end(h, KKT_K_OTHER, e0, s);
+        // Step j+1 is enqueued before the host reads step j's record, so the device never
+        // waits for the host; kernels of a step enqueued after the stop return at once.
         for (int j = 0; j < R; ++j) {
+            const size_t step_mark = h->ev_pending.size();
             KKT_HIP(h, precond<T>(h, d.V + (int64_t)j * a.n, d.Z + (int64_t)j * a.n, d.ctl, s));
-            inf.precond_applications += 1;
             e0 = prof_begin(h, s);
             k_spmv_dots<<<G, kStreamBlock, 0, s>>>(ka, j);
             prof_end(h, KKT_K_SPMV, e0, s);
             e0 = prof_begin(h, s);
             k_cgs_pass2<<<G, kStreamBlock, 0, s>>>(ka, j);
             k_cgs_finish<<<G, kStreamBlock, 0, s>>>(ka, j);
-            k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, R, y, z);
+            k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, R, y, z, h->dev_rec);
             prof_end(h, KKT_K_CGS, e0, s);
             KKT_HIP(h, hipGetLastError());
-            st = read_ctl(h, s);
-            if (st != KKT_OK) return st;
-            if (h->host_ctl->stop) break;
+            KKT_HIP(h, hipEventRecord(h->step_ev[j & 1], s));
+            if (j == 0) continue;
+            KKT_HIP(h, hipEventSynchronize(h->step_ev[(j - 1) & 1]));
+            const StepRecord &rec = h->host_rec[j - 1];
+            if (rec.hang) {
+                h->device_failed = true;
+                return fail(h, KKT_EDEVICE, "a dependency wait exceeded its spin limit");
+            }
+            if (rec.stop) {
+                // step j does no work: its timing records are not kept
+                for (size_t q = step_mark; q < h->ev_pending.size(); ++q) {
+                    h->ev_pool.push_back(h->ev_pending[q].a);
+                    h->ev_pool.push_back(h->ev_pending[q].b);
+                }
+                h->ev_pending.resize(step_mark);
+                break;
+            }
         }
         e0 = prof_begin(h, s);
         k_xupdate<<<G, kStreamBlock, 0, s>>>(ka, x);
         prof_end(h, KKT_K_OTHER, e0, s);
         e0 = prof_begin(h, s);
-        k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+        launch_resid(h, ka, b, x, d.r, s);
         k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G);
         prof_end(h, KKT_K_RESID, e0, s);
         KKT_HIP(h, hipGetLastError());
         st = read_ctl(h, s);
         if (st != KKT_OK) return st;
         iters += h->host_ctl->jdone;
+        inf.precond_applications += h->host_ctl->jdone;
         est = h->host_ctl->est;
         rn = std::sqrt(h->host_ctl->rnorm2);
         nrbe = rn / (knorm * std::sqrt(h->host_ctl->xnorm2) + bn);
@@ -1345,7 +1441,7 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
     KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
     auto residual = [&]() -> kkt_status_t {
         hipEvent_t r0 = prof_begin(h, s);
-        k_resid<<<G, kStreamBlock, 0, s>>>(ka, b, x, d.r);
+        launch_resid(h, ka, b, x, d.r, s);
         k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G);
         prof_end(h, KKT_K_RESID, r0, s);
         KKT_HIP(h, hipGetLastError());
@@ -1448,6 +1544,7 @@ void kkt_opts_default(kkt_opts_t *o) {
     o->richardson_max_it = 50;
     o->ratio_stop = 0.5;
     o->inner_tol = 1e-2;
+    o->residual = KKT_RESID_FP64;
 }
 
 kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowptr, const int32_t *colidx,
@@ -1462,12 +1559,17 @@ kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowpt
         delete h;
         return fail(nullptr, KKT_EINVAL, "restart must be in 1..64");
     }
+    if (h->opts.residual != KKT_RESID_FP64 && h->opts.residual != KKT_RESID_DD) {
+        delete h;
+        return fail(nullptr, KKT_EINVAL, "residual must be KKT_RESID_FP64 or KKT_RESID_DD");
+    }
     AnalysisOptions ao;
     ao.ordering = h->opts.ordering == KKT_ORDER_ND ? ORDER_ND : ORDER_MD;
     ao.nd_leaf = h->opts.nd_leaf;
     ao.pivot_tau = h->opts.pivot_tau;
     ao.tile_threads = kTileThreads;
     ao.tile_rows = kTileRows;
+    ao.tile_lds = kTileLds;
     std::string msg;
     int rc = analyze(ao, n, rowptr, colidx, values_first, h->an, &msg);
     if (rc != AN_OK) {
@@ -1534,6 +1636,13 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     hipStream_t s = (hipStream_t)stream;
     KKT_HIP(h, hipGetDevice(&h->device));
     if (!h->host_ctl) KKT_HIP(h, hipHostMalloc((void **)&h->host_ctl, sizeof(ControlSummary), hipHostMallocDefault));
+    if (!h->host_rec) {
+        KKT_HIP(h, hipHostMalloc((void **)&h->host_rec, sizeof(StepRecord) * kRestartMax,
+                                 hipHostMallocMapped | hipHostMallocCoherent));
+        KKT_HIP(h, hipHostGetDevicePointer((void **)&h->dev_rec, h->host_rec, 0));
+    }
+    for (int e = 0; e < 2; ++e)
+        if (!h->step_ev[e]) KKT_HIP(h, hipEventCreateWithFlags(&h->step_ev[e], hipEventDisableTiming));
     char *b = (char *)dev_ptr;
     DevLayout &d = h->d;
     const Analysis &a = h->an;
@@ -1545,22 +1654,26 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.relptr = (int64_t *)(b + o.relptr);
     d.fsrc = (int64_t *)(b + o.fsrc);
     d.relpos = (int32_t *)(b + o.relpos);
-    d.lrp = (int64_t *)(b + o.lrp);
-    d.urp = (int64_t *)(b + o.urp);
     d.krp = (int64_t *)(b + o.krp);
     d.kci = (int32_t *)(b + o.kci);
     d.l_rows = (int32_t *)(b + o.l_rows);
-    d.l_lev = (int32_t *)(b + o.l_lev);
-    d.l_tile = (int32_t *)(b + o.l_tile);
-    d.l_tlev = (int32_t *)(b + o.l_tlev);
+    d.l_seg = (int32_t *)(b + o.l_seg);
+    d.l_tseg = (int32_t *)(b + o.l_tseg);
     d.l_ref = (int32_t *)(b + o.l_ref);
-    d.l_lg = (int8_t *)(b + o.l_lg);
+    d.l_text = (int32_t *)(b + o.l_text);
+    d.l_esrc = (int32_t *)(b + o.l_esrc);
+    d.l_rent = (int64_t *)(b + o.l_rent);
+    d.l_tlds = (uint8_t *)(b + o.l_tlds);
+    d.l_slg = (int32_t *)(b + o.l_slg);
     d.u_rows = (int32_t *)(b + o.u_rows);
-    d.u_lev = (int32_t *)(b + o.u_lev);
-    d.u_tile = (int32_t *)(b + o.u_tile);
-    d.u_tlev = (int32_t *)(b + o.u_tlev);
+    d.u_seg = (int32_t *)(b + o.u_seg);
+    d.u_tseg = (int32_t *)(b + o.u_tseg);
     d.u_ref = (int32_t *)(b + o.u_ref);
-    d.u_lg = (int8_t *)(b + o.u_lg);
+    d.u_text = (int32_t *)(b + o.u_text);
+    d.u_esrc = (int32_t *)(b + o.u_esrc);
+    d.u_rent = (int64_t *)(b + o.u_rent);
+    d.u_tlds = (uint8_t *)(b + o.u_tlds);
+    d.u_slg = (int32_t *)(b + o.u_slg);
     d.prow = (int32_t *)(b + o.prow);
     d.q = (int32_t *)(b + o.q);
     d.kval = (double *)(b + o.kval);
@@ -1590,22 +1703,26 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.relptr, a.relptr, s));
     KKT_HIP(h, up(b, o.fsrc, a.fsrc, s));
     KKT_HIP(h, up(b, o.relpos, a.relpos, s));
-    KKT_HIP(h, up(b, o.lrp, a.lrp, s));
-    KKT_HIP(h, up(b, o.urp, a.urp, s));
     KKT_HIP(h, up(b, o.krp, a.rowptr, s));
     KKT_HIP(h, up(b, o.kci, a.colidx, s));
     KKT_HIP(h, up(b, o.l_rows, a.lsched.rows, s));
-    KKT_HIP(h, up(b, o.l_lev, a.lsched.lev_ptr, s));
-    KKT_HIP(h, up(b, o.l_tile, a.lsched.tile_row, s));
-    KKT_HIP(h, up(b, o.l_tlev, a.lsched.tile_lev, s));
-    KKT_HIP(h, up(b, o.l_ref, a.lsched.ref, s));
-    KKT_HIP(h, up(b, o.l_lg, a.lsched.lev_lg, s));
+    KKT_HIP(h, up(b, o.l_seg, a.lsched.seg_row, s));
+    KKT_HIP(h, up(b, o.l_tseg, a.lsched.tile_seg, s));
+    KKT_HIP(h, up(b, o.l_ref, a.lsched.ent_ref, s));
+    KKT_HIP(h, up(b, o.l_text, a.lsched.tile_ext, s));
+    KKT_HIP(h, up(b, o.l_esrc, a.lsched.ext_src, s));
+    KKT_HIP(h, up(b, o.l_rent, a.lsched.row_ent, s));
+    KKT_HIP(h, up(b, o.l_tlds, a.lsched.tile_lds, s));
+    KKT_HIP(h, up(b, o.l_slg, a.lsched.seg_lg, s));
     KKT_HIP(h, up(b, o.u_rows, a.usched.rows, s));
-    KKT_HIP(h, up(b, o.u_lev, a.usched.lev_ptr, s));
-    KKT_HIP(h, up(b, o.u_tile, a.usched.tile_row, s));
-    KKT_HIP(h, up(b, o.u_tlev, a.usched.tile_lev, s));
-    KKT_HIP(h, up(b, o.u_ref, a.usched.ref, s));
-    KKT_HIP(h, up(b, o.u_lg, a.usched.lev_lg, s));
+    KKT_HIP(h, up(b, o.u_seg, a.usched.seg_row, s));
+    KKT_HIP(h, up(b, o.u_tseg, a.usched.tile_seg, s));
+    KKT_HIP(h, up(b, o.u_ref, a.usched.ent_ref, s));
+    KKT_HIP(h, up(b, o.u_text, a.usched.tile_ext, s));
+    KKT_HIP(h, up(b, o.u_esrc, a.usched.ext_src, s));
+    KKT_HIP(h, up(b, o.u_rent, a.usched.row_ent, s));
+    KKT_HIP(h, up(b, o.u_tlds, a.usched.tile_lds, s));
+    KKT_HIP(h, up(b, o.u_slg, a.usched.seg_lg, s));
     KKT_HIP(h, up(b, o.prow, a.prow, s));
     KKT_HIP(h, up(b, o.q, a.q, s));
     KKT_HIP(h, hipMemsetAsync(d.ctl, 0, sizeof(Control), s));
@@ -1680,6 +1797,18 @@ kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x
     return KKT_OK;
 }
 
+kkt_status_t kkt_residual(kkt_handle_t h, const double *dev_b, const double *dev_x, double *dev_r, void *stream) {
+    if (!h || !dev_b || !dev_x || !dev_r) return fail(h, KKT_EINVAL, "null argument");
+    if (h->device_failed) return fail(h, KKT_EDEVICE, "handle unusable after a device error");
+    if (!h->bound || !h->have_factors) return fail(h, KKT_ESTATE, "refactor before the residual");
+    if (dev_r == dev_b || dev_r == dev_x) return fail(h, KKT_EINVAL, "dev_r must be distinct from dev_b and dev_x");
+    hipStream_t s = (hipStream_t)stream;
+    const KrylovArgs ka = kargs<double>(h);
+    launch_resid(h, ka, dev_b, dev_x, dev_r, s);
+    KKT_HIP(h, hipGetLastError());
+    return KKT_OK;
+}
+
 kkt_status_t kkt_get_factor_values(kkt_handle_t h, int32_t precision, double *lx, double *ux, void *stream) {
     if (!h) return fail(h, KKT_EINVAL, "null handle");
     if (!h->bound || !h->have_factors) return fail(h, KKT_ESTATE, "no factors");
@@ -1728,6 +1857,9 @@ kkt_status_t kkt_release(kkt_handle_t h) {
     }
     for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->host_ctl) (void)hipHostFree(h->host_ctl);
+    if (h->host_rec) (void)hipHostFree(h->host_rec);
+    for (auto e : h->step_ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     return KKT_OK;
 }

@@ -22,11 +22,12 @@ GUARD_PERTURB, GUARD_FAIL = 0, 1
 STOP_PAPER, STOP_NRBE = 0, 1
 ORDER_MD, ORDER_ND = 0, 1
 IR_FGMRES, IR_RICHARDSON, IR_ERROR_FGMRES = 0, 1, 2
+RESID_FP64, RESID_DD = 0, 1
 
 #: every entry point declared in include/kkt.h
 EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
            "kkt_get_factor_pattern", "kkt_get_analysis_values", "kkt_workspace_size",
-           "kkt_bind_workspace", "kkt_refactor", "kkt_solve", "kkt_direct_solve",
+           "kkt_bind_workspace", "kkt_refactor", "kkt_solve", "kkt_direct_solve", "kkt_residual",
            "kkt_get_factor_values", "kkt_set_profiling", "kkt_get_kernel_times", "kkt_release",
            "kkt_last_error"]
 
@@ -38,7 +39,8 @@ class Opts(C.Structure):
                 ("max_restarts", C.c_int32), ("delta_tol", C.c_double), ("nrbe_target", C.c_double),
                 ("precision", C.c_int32), ("guard_policy", C.c_int32), ("stop_mode", C.c_int32),
                 ("mixed_fallback", C.c_int32), ("mixed_max_cycles", C.c_int32), ("ir_method", C.c_int32),
-                ("richardson_max_it", C.c_int32), ("ratio_stop", C.c_double), ("inner_tol", C.c_double)]
+                ("richardson_max_it", C.c_int32), ("ratio_stop", C.c_double), ("inner_tol", C.c_double),
+                ("residual", C.c_int32)]
 
 
 class AnalysisInfo(C.Structure):
@@ -92,6 +94,7 @@ def lib():
         L.kkt_refactor.argtypes = [vp, vp, vp]
         L.kkt_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(SolveInfo), vp]
         L.kkt_direct_solve.argtypes = [vp, vp, vp, vp]
+        L.kkt_residual.argtypes = [vp, vp, vp, vp, vp]
         L.kkt_get_factor_values.argtypes = [vp, C.c_int32, f64p, f64p, vp]
         L.kkt_set_profiling.argtypes = [vp, C.c_int32]
         L.kkt_get_kernel_times.argtypes = [vp, C.POINTER(KernelTimes), vp]
@@ -231,6 +234,17 @@ class Solver:
         self._check(lib().kkt_direct_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                                            _stream_ptr(stream)))
         return x
+
+    def residual(self, b, x, r=None, stream=None):
+        """r = b - K x for the last refactored K (kkt_residual; precision per opts.residual)."""
+        import torch
+        for t in (b, x):
+            assert t.is_cuda and t.dtype == torch.float64 and t.numel() == self.n
+        if r is None:
+            r = torch.empty_like(b)
+        self._check(lib().kkt_residual(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                       C.c_void_p(r.data_ptr()), _stream_ptr(stream)))
+        return r
 
     def factor_values(self, precision=0, stream=None):
         inf = self.info()

@@ -31,3 +31,19 @@ def test_algorithmic_bytes_counts():
 def test_percentile():
     assert bench.percentile([1, 2, 3, 4], 50) == 2.5
     assert bench.percentile([5], 99) == 5
+
+
+def test_cpu_baseline_compares_solutions():
+    import numpy as np
+    import kkt_synth as ks
+    import oracle
+    p = ks.make_pattern(1)
+    systems = [p.system(k) for k in (1, 2)]
+    Q = oracle.order(p.rowptr, p.colidx)
+    xs = [oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=Q)[0] for v, b in systems]
+    done, el, cmp = bench.cpu_baseline(p, systems, 0.0, gpu_xs=xs)
+    assert done == 1 and el > 0 and len(cmp) == 1
+    assert cmp[0][0] == 0.0 and cmp[0][1] > 1.0
+    bad = [xs[0] * (1 + 1e-3), xs[1]]
+    _, _, cmp = bench.cpu_baseline(p, systems[:1], 0.0, gpu_xs=bad)
+    assert abs(cmp[0][0] - 1e-3) < 1e-9

@@ -275,3 +275,49 @@ def test_fgmres_counts_preconditioner_applications(dev):
     s.refactor(cuda(v, dev))
     _, info = s.solve(cuda(b, dev))
     assert info["precond_applications"] == 1 + info["iterations"]
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("resid", ["fp64", "dd"])
+def test_residual_bit_exact(dev, cfg, resid):
+    # rho = b - K x through kkt_residual, in working precision and in double-double, against
+    # the oracle's residual of the same kind: same summation order, so bit-identical
+    say("residual", resid, "config", cfg)
+    p, s, _ = make(cfg, dev, residual=P.RESID_DD if resid == "dd" else P.RESID_FP64)
+    v, b = p.system(2)
+    s.refactor(cuda(v, dev))
+    rng = np.random.default_rng(cfg)
+    x = rng.standard_normal(p.N) * 10.0 ** rng.uniform(-6, 6, p.N)
+    r = s.residual(cuda(b, dev), cuda(x, dev))
+    torch.cuda.synchronize()
+    ro = oracle.residual(p.rowptr, p.colidx, v, x, b, resid)
+    assert np.array_equal(r.cpu().numpy(), ro)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_solve_dd_residual_reaches_working_accuracy(dev, seed):
+    # FGMRES-IR with double-double residuals: componentwise error against the exact rational
+    # solution of the stored system within 2u (the working-precision residual stalls near
+    # cond * u on these systems)
+    from exact import exact_solve, max_componentwise_error
+    say("dd residual solve seed", seed)
+    p = ks.small_kkt(24, 16, seed)
+    v, b = p.system(1)
+    s = P.Solver(p.rowptr, p.colidx, v, residual=P.RESID_DD).bind(dev)
+    s.refactor(cuda(v, dev))
+    x, info = s.solve(cuda(b, dev))
+    assert info["converged"] == 1 and info["nrbe"] <= 1e-12
+    xe = exact_solve(ks.to_dense(p.rowptr, p.colidx, v, p.N), b)
+    assert max_componentwise_error(x.cpu().numpy(), xe) <= 2.0 ** -52
+
+
+def test_solve_dd_residual_sequence(dev):
+    say("dd residual 60k sequence")
+    p, s, _ = make(2, dev, residual=P.RESID_DD)
+    for step in (2, 3):
+        v, b = p.system(step)
+        s.refactor(cuda(v, dev))
+        x, info = s.solve(cuda(b, dev))
+        assert info["converged"] == 1 and info["nrbe"] <= 1e-12
+        m = oracle.metrics(p.rowptr, p.colidx, v, x.cpu().numpy(), b)
+        assert m["nrbe"] <= 1e-12

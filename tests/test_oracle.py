@@ -490,3 +490,58 @@ def test_md_fill_below_nested_dissection(cfg):
     f_md = oracle.LU(p.rowptr, p.colidx, v, Q=oracle.order(p.rowptr, p.colidx))
     f_nd = oracle.LU(p.rowptr, p.colidx, v, Q=oracle.order(p.rowptr, p.colidx, method="nd"))
     assert f_md.lnz + f_md.unz < 0.5 * (f_nd.lnz + f_nd.unz)
+
+
+# ---------------------------------------------------------------------------------------
+# extended-precision (double-double) residual
+# ---------------------------------------------------------------------------------------
+
+def test_residual_dd_hand_cancellation():
+    # 3 * fl(1/3) = 1 - 2^-54 exactly; in binary64 it rounds to 1 (tie to even), so the
+    # working-precision residual of b = 0 against x = (fl(1/3), -1) is 0 while the exact
+    # residual is 2^-54.
+    rp = np.array([0, 2], np.int64)
+    ci = np.array([0, 1], np.int32)
+    v = np.array([3.0, 1.0])
+    x = np.array([1.0 / 3.0, -1.0])
+    b = np.array([0.0])
+    assert oracle.residual(rp, ci, v, x, b)[0] == 0.0
+    assert oracle.residual(rp, ci, v, x, b, "dd")[0] == 2.0 ** -54
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_residual_dd_matches_exact_rounding(seed):
+    from fractions import Fraction
+    from exact import exact_residual
+    p = ks.small_kkt(30, 20, seed)
+    v, b = p.system(1)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(p.N) * 10.0 ** rng.uniform(-6, 6, p.N)
+    ex = exact_residual(p.rowptr, p.colidx, v, x, b)
+    r = oracle.residual(p.rowptr, p.colidx, v, x, b, "dd")
+    for i in range(p.N):
+        mag = abs(b[i]) + sum(abs(v[q] * x[p.colidx[q]]) for q in range(p.rowptr[i], p.rowptr[i + 1]))
+        rounded = float(ex[i])  # correctly rounded exact value
+        bound = 0.5 * np.spacing(abs(rounded)) + 2.0 ** -103 * mag
+        assert abs(Fraction(float(r[i])) - ex[i]) <= Fraction(bound), i
+    # the double-double rows are the correctly rounded exact residual far more often than
+    # the working-precision ones
+    r64 = oracle.residual(p.rowptr, p.colidx, v, x, b)
+    exact_dd = sum(float(r[i]) == float(ex[i]) for i in range(p.N))
+    exact_64 = sum(float(r64[i]) == float(ex[i]) for i in range(p.N))
+    assert exact_dd >= p.N - 1 and exact_dd > exact_64
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_fgmres_dd_residual_reaches_working_accuracy(seed):
+    # With residuals in double-double, refinement converges to the exact solution of the
+    # stored system to about the unit roundoff componentwise (three-precision IR), where the
+    # working-precision residual stalls near cond * u; exact solution by rational elimination.
+    from exact import exact_solve, max_componentwise_error
+    p = ks.small_kkt(24, 16, seed)
+    v, b = p.system(1)
+    xe = exact_solve(ks.to_dense(p.rowptr, p.colidx, v, p.N), b)
+    f = oracle.LU(p.rowptr, p.colidx, v)
+    x, info = f.fgmres_ir(p.rowptr, p.colidx, v, b, mode=1, eta=1e-14, residual="dd")
+    assert info["converged"]
+    assert max_componentwise_error(x, xe) <= 2.0 ** -52
