@@ -15,6 +15,7 @@ bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -46,6 +47,39 @@ def algorithmic_bytes(cls: str, ai: dict) -> float:
     if cls == "spmv":
         return nnz * 12 + (n + 1) * 8 + n * 8 * 3
     raise KeyError(cls)
+
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kkt_sequence_60k_hbm_counters.txt")
+KERNEL_NAMES = {"trsv_l": "kkt::k_trsv<double,true>", "trsv_u": "kkt::k_trsv<double,false>",
+                "refactor": "kkt::k_refactor<double>", "spmv": "kkt::k_spmv_dots"}
+
+
+def source_digest() -> str:
+    """sha256 over the library's kernel and analysis sources (names and contents)."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2401_13926_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        if fn.endswith((".hip", ".cpp", ".hpp")):
+            h.update(fn.encode())
+            with open(os.path.join(d, fn), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cls: str):
+    """HBM bytes (read + written) per launch of a kernel class, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of the 60k workload; None when the sources changed since."""
+    name = KERNEL_NAMES.get(cls)
+    if not name or not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest = source_digest()
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 5 and parts[0] == "traffic" and parts[1] == name and parts[4] == digest:
+                return float(parts[2]) + float(parts[3])
+    return None
 
 
 def percentile(xs, q):
@@ -143,6 +177,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 256 MiB device buffer 4 times (reference kernel for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path "
@@ -161,6 +198,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
+                          "launches": 4}), flush=True)
+        return
 
     cfg = args.config
     pattern = ks.make_pattern(cfg)
@@ -222,8 +269,9 @@ def main():
         avg_s = ms / n_l / 1e3
         bytes_per = algorithmic_bytes(dom, ai)
         achieved = bytes_per / avg_s / 1e9
+        traffic = measured_traffic(dom) if cfg == 2 else None
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per}
     if not args.no_cpu:
         done, el, cmp = cpu_baseline(pattern, systems, args.cpu_seconds, r64["xs"])
