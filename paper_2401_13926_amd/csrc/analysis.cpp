@@ -588,8 +588,12 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
                         if (level[i] == l) sc.rows.push_back(i);
                 int lg = 0;  // about four entries per lane, at most 64 lanes ...
                 while (lg < 6 && ((int64_t)1 << lg) * 4 < tmax[l - w0]) ++lg;
-                while (lg > 0 && ((int64_t)cnt << lg) > threads) --lg;  // ... one pass per segment
-                sc.seg_lg.push_back(lg);
+                // ... one pass per segment: of one wavefront when it covers the segment with
+                // these lanes (no block barrier needed), else of the block, with fewer lanes
+                // per row if needed
+                const bool narrow = ((int64_t)cnt << lg) <= 64;
+                while (lg > 0 && ((int64_t)cnt << lg) > threads) --lg;
+                sc.seg_lg.push_back(lg | (narrow ? kSegWave : 0));
                 sc.seg_row.push_back((int32_t)sc.rows.size());
                 tcount[l - w0] = 0;
                 tmax[l - w0] = 0;

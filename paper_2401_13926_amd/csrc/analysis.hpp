@@ -21,6 +21,9 @@ struct AnalysisOptions {
                                  // handed out one column at a time
 };
 
+// Flag in TriSchedule::seg_lg: the segment's rows fit one wavefront.
+constexpr int32_t kSegWave = 0x40;
+
 // Schedule of one triangular solve.  A tile is a contiguous run of rows solved by one block;
 // it is cut into segments, each a set of mutually independent rows covered by one pass of the
 // block (2^lg lanes per row), with a block barrier between segments.  Tiles are handed out in
@@ -36,7 +39,8 @@ struct TriSchedule {
     std::vector<int32_t> rows;      // solve order
     std::vector<int32_t> tile_seg;  // first segment of each tile (tiles + 1)
     std::vector<int32_t> seg_row;   // start of each segment in rows (segments + 1)
-    std::vector<int32_t> seg_lg;    // log2 of the lanes per row of each segment
+    std::vector<int32_t> seg_lg;    // log2 of the lanes per row of each segment, | kSegWave when
+                                    // the segment fits one wavefront (solved by wavefront 0)
     std::vector<int64_t> row_ent;   // first packed entry of each position of rows (n + 1)
     std::vector<int32_t> ent_ref;   // per packed entry: LDS slot (staged tile) or source row
     std::vector<int32_t> tile_ext;  // first external of each tile (tiles + 1)

@@ -413,6 +413,31 @@ template <typename T> struct TrsvArgs {
 // the following segments and to the global solution with one coherent store each (every
 // solution entry is its own ready flag).  An unstaged tile (one long row) is solved by one
 // wavefront reading its entries and sources from global memory.
+// Value of another lane selected by a DPP control (row shifts fill 0 past the row edge; rows
+// outside kRowMask return 0), applied to each 32-bit half of a double.
+template <int kCtrl, int kRowMask> __device__ __forceinline__ double dpp_get(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, kRowMask, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, kRowMask, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+template <int kCtrl, int kRowMask> __device__ __forceinline__ float dpp_get(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xF, true));
+}
+
+// Sum over aligned groups of 2^lg lanes (lg <= 6), complete in each group's last lane: an
+// inclusive shift-add scan within rows of 16 lanes (row_shr 1, 2, 4, 8), then the row
+// broadcasts of lane 15 into rows 1 and 3 and of lane 31 into rows 2 and 3.  Register-only.
+template <typename T> __device__ __forceinline__ T group_sum_last(T v, int lg) {
+    if (lg >= 1) v = v + dpp_get<0x111, 0xF>(v);
+    if (lg >= 2) v = v + dpp_get<0x112, 0xF>(v);
+    if (lg >= 3) v = v + dpp_get<0x114, 0xF>(v);
+    if (lg >= 4) v = v + dpp_get<0x118, 0xF>(v);
+    if (lg >= 5) v = v + dpp_get<0x142, 0xA>(v);
+    if (lg >= 6) v = v + dpp_get<0x143, 0xC>(v);
+    return v;
+}
+
 // Read-only schedule data seen through the constant address space: with a uniform index the
 // compiler loads it through the scalar cache, so waiting for it never waits for the
 // kernel's outstanding vector stores.
@@ -476,9 +501,24 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
         int32_t *qid = rid + nr;                   // nr (upper)
         int32_t *roff = qid + nr;                  // nr + 1
         uint16_t *refs = reinterpret_cast<uint16_t *>(roff + nr + 1);  // ne
-        for (int k = tid; k < ne; k += kTileThreads) {
-            vals[k] = a.val[eb + k];
-            refs[k] = (uint16_t)a.ent_ref[eb + k];
+        // four loads in flight per thread before the LDS writes
+        for (int k0 = tid; k0 < ne; k0 += 4 * kTileThreads) {
+            T v[4];
+            int c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + u * kTileThreads;
+                v[u] = k < ne ? a.val[eb + k] : T(0);
+                c[u] = k < ne ? a.ent_ref[eb + k] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + u * kTileThreads;
+                if (k < ne) {
+                    vals[k] = v[u];
+                    refs[k] = (uint16_t)c[u];
+                }
+            }
         }
         for (int r = tid; r < nr; r += kTileThreads) {
             const int i = a.rows[rb + r];
@@ -488,7 +528,7 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
                 rhs[r] = (T)a.rhs64[a.prow[i]];
             } else {
                 rhs[r] = a.rhs_step[i];
-                dg[r] = a.diag[i];
+                dg[r] = T(1) / a.diag[i];  // reciprocal: one multiply per row in the segments
                 qid[r] = a.q[i];
             }
         }
@@ -500,30 +540,48 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
             xs[nr + k] = v;
         }
         __syncthreads();
+        // A wavefront segment is solved by wavefront 0 alone: between two such segments no
+        // block barrier is needed (a wavefront's LDS accesses complete in order).
+        bool prev_wave = false;
         for (int sg = s0; sg < s1; ++sg) {
             const int lb = seg_row[sg] - rb, le = seg_row[sg + 1] - rb;
-            const int lg = seg_lg[sg];
+            const int code = seg_lg[sg];
+            const bool wave = (code & kSegWave) != 0;
+            const int lg = code & 0xF;
             const int g = 1 << lg;
+            if (sg > s0 && !(wave && prev_wave)) __syncthreads();
+            prev_wave = wave;
+            if (wave && tid >= 64) continue;
             const int r = lb + (tid >> lg);
             T acc = 0;
             if (r < le) {
                 const int e1 = roff[r + 1];
-                for (int e = roff[r] + (tid & (g - 1)); e < e1; e += g) {
+                int e = roff[r] + (tid & (g - 1));
+                for (; e + 3 * g < e1; e += 4 * g) {  // operands of four entries in flight
+                    const int c0 = refs[e], c1 = refs[e + g], c2 = refs[e + 2 * g], c3 = refs[e + 3 * g];
+                    const T v0 = vals[e], v1 = vals[e + g], v2 = vals[e + 2 * g], v3 = vals[e + 3 * g];
+                    const T p0 = v0 * xs[c0], p1 = v1 * xs[c1], p2 = v2 * xs[c2], p3 = v3 * xs[c3];
+                    acc = acc + p0;
+                    acc = acc + p1;
+                    acc = acc + p2;
+                    acc = acc + p3;
+                }
+                for (; e < e1; e += g) {
                     const T prod = vals[e] * xs[refs[e]];
                     acc = acc + prod;
                 }
             }
-            for (int o = 1; o < g; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
-            if (r < le && (tid & (g - 1)) == 0) {
+            acc = group_sum_last(acc, lg);
+            if (r < le && (tid & (g - 1)) == g - 1) {
                 T res;
                 if (kLower) res = rhs[r] - acc;
-                else res = (rhs[r] - acc) / dg[r];
+                else res = (rhs[r] - acc) * dg[r];
                 xs[r] = res;
                 store_ready(a.out + rid[r], res);
                 if (!kLower) a.xout[qid[r]] = (double)res;
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
 }
 
