@@ -427,7 +427,8 @@ int pivoted_lu(int64_t n, const int64_t *rp, const int32_t *ci, const double *va
 // Tiles are numbered window by window, so every reference of a tile is to a row of an
 // earlier tile or of the same tile at an earlier segment.
 bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64_t> &rp,
-                  const std::vector<int32_t> &ci, bool lower, TriSchedule &sc, std::string *msg) {
+                  const std::vector<int32_t> &ci, bool lower, int64_t dense_reserve, TriSchedule &sc,
+                  std::string *msg) {
     constexpr int64_t kSerial = 16;  // entries per lane allowed when rows share a pass
     const int threads = opt.tile_threads;
     std::vector<int32_t> level(n, 0);
@@ -474,8 +475,10 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
     struct Size {
         int64_t rows = 0, ent = 0, ext = 0;  // ext: references to earlier windows (upper bound)
     };
+    // tiles are formed within a smaller budget, so that dense blocks fit in what remains
+    const int64_t stage_budget = opt.tile_lds - dense_reserve;
     auto stageable = [&](const Size &z) {
-        return z.rows <= opt.tile_rows && tile_lds_bytes(z.rows, z.ext, z.ent) <= opt.tile_lds;
+        return z.rows <= opt.tile_rows && tile_lds_bytes(z.rows, z.ext, z.ent) <= stage_budget;
     };
     std::vector<int32_t> parent(n, -1);
     std::vector<Size> size(n);
@@ -552,6 +555,8 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
     sc.seg_row.assign(1, 0);
     sc.seg_lg.clear();
     sc.tile_lds.clear();
+    sc.seg_dofs.clear();
+    std::vector<int64_t> tile_dvals;  // dense-block values of each tile
     sc.windows = 0;
     std::vector<int32_t> tcount, comp_of_root(n, -1);
     std::vector<int64_t> tmax;
@@ -578,28 +583,71 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
         tmax.assign(nl, 0);
         Size tsize;
         std::vector<int32_t> members;
+        auto lane_log = [&](int64_t cnt, int64_t maxlen, int64_t pass) {
+            int lg = 0;  // about four entries per lane, at most 64 lanes, one pass
+            while (lg < 6 && ((int64_t)1 << lg) * 4 < maxlen) ++lg;
+            while (lg > 0 && (cnt << lg) > pass) --lg;
+            return lg;
+        };
         auto close_tile = [&](bool staged) {
             if (members.empty()) return;
+            // the tile's levels: rows in order, counts and longest rows
+            std::vector<int32_t> lcnt;
+            std::vector<int64_t> lmax;
             for (int32_t l = w0; l <= w1; ++l) {
                 const int32_t cnt = tcount[l - w0];
                 if (!cnt) continue;
                 for (int32_t c : members)
                     for (int32_t i : crows[c])
                         if (level[i] == l) sc.rows.push_back(i);
-                int lg = 0;  // about four entries per lane, at most 64 lanes ...
-                while (lg < 6 && ((int64_t)1 << lg) * 4 < tmax[l - w0]) ++lg;
-                // ... one pass per segment: of one wavefront when it covers the segment with
-                // these lanes (no block barrier needed), else of the block, with fewer lanes
-                // per row if needed
-                const bool narrow = ((int64_t)cnt << lg) <= 64;
-                while (lg > 0 && ((int64_t)cnt << lg) > threads) --lg;
-                sc.seg_lg.push_back(lg | (narrow ? kSegWave : 0));
-                sc.seg_row.push_back((int32_t)sc.rows.size());
+                lcnt.push_back(cnt);
+                lmax.push_back(tmax[l - w0]);
                 tcount[l - w0] = 0;
                 tmax[l - w0] = 0;
             }
+            // consecutive small levels are fused into dense segments while the LDS left over
+            // by the tile's entries holds their blocks
+            int64_t room = staged && dense_reserve > 0
+                               ? opt.tile_lds - tile_lds_bytes(tsize.rows, tsize.ext, tsize.ent)
+                               : 0;
+            int64_t dvals = 0;
+            int32_t row = sc.seg_row.back();
+            for (size_t k = 0; k < lcnt.size();) {
+                size_t k1 = k + 1;
+                int64_t m = lcnt[k], mx = lmax[k];
+                while (k1 < lcnt.size() && m + lcnt[k1] <= kDenseRows &&
+                       8 * dense_block_values(m + lcnt[k1]) <= room) {
+                    m += lcnt[k1];
+                    mx = std::max(mx, lmax[k1]);
+                    ++k1;
+                }
+                // worth it only when the levels it replaces cost more than its sweep: about
+                // one segment per level against 1.5 segments plus m / 32 for the sweep
+                if (k1 - k >= 2 && 32 * (int64_t)(k1 - k) < 48 + m) {
+                    k1 = k + 1;
+                    m = lcnt[k];
+                    mx = lmax[k];
+                }
+                row += (int32_t)m;
+                sc.seg_row.push_back(row);
+                if (k1 - k >= 2) {  // dense segment: phase A is a block pass over its rows
+                    sc.seg_lg.push_back(lane_log(m, mx, threads) | kSegDense);
+                    sc.seg_dofs.push_back((int32_t)dvals);
+                    dvals += dense_block_values(m);
+                    room -= 8 * dense_block_values(m);
+                } else {
+                    // a wavefront pass when it covers the level with these lanes (no block
+                    // barrier needed), else a block pass with fewer lanes per row if needed
+                    const int lgw = lane_log(m, mx, 64 * 64);
+                    const bool wave = (m << lgw) <= 64;
+                    sc.seg_lg.push_back(lane_log(m, mx, threads) | (wave ? kSegWave : 0));
+                    sc.seg_dofs.push_back(-1);
+                }
+                k = k1;
+            }
             sc.tile_seg.push_back((int32_t)sc.seg_lg.size());
             sc.tile_lds.push_back(staged ? 1 : 0);
+            tile_dvals.push_back(dvals);
             members.clear();
             tsize = Size();
         };
@@ -666,9 +714,23 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
                 tile_of[r] = (int32_t)t;
                 seg_of[r] = g;
             }
+    // dense segments: local index of each position, and whether a reference stays inside
+    std::vector<int32_t> dloc(n, -1);
+    for (int64_t g = 0; g < sc.segments(); ++g)
+        if (sc.seg_lg[g] & kSegDense)
+            for (int32_t r = sc.seg_row[g]; r < sc.seg_row[g + 1]; ++r) dloc[r] = r - sc.seg_row[g];
+    auto inside = [&](int32_t r, int32_t pk) { return dloc[r] >= 0 && seg_of[pk] == seg_of[r]; };
     sc.row_ent.assign(n + 1, 0);
-    for (int64_t r = 0; r < n; ++r) sc.row_ent[r + 1] = sc.row_ent[r] + len(sc.rows[r]);
-    sc.ent_ref.assign(ci.size(), 0);
+    for (int64_t r = 0; r < n; ++r) {
+        const int32_t i = sc.rows[r];
+        int64_t cnt = 0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) cnt += !inside((int32_t)r, pos[ci[p]]);
+        sc.row_ent[r + 1] = sc.row_ent[r] + cnt;
+    }
+    sc.packed = sc.row_ent[n];
+    sc.tile_dense.assign(1, sc.packed);
+    for (int64_t t = 0; t < sc.tiles(); ++t) sc.tile_dense.push_back(sc.tile_dense.back() + tile_dvals[t]);
+    sc.ent_ref.assign(sc.packed, 0);
     sc.csr2ent.assign(ci.size(), 0);
     sc.tile_ext.assign(1, 0);
     sc.ext_src.clear();
@@ -679,12 +741,19 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
         for (int32_t r = rb; r < re; ++r) {
             const int32_t i = sc.rows[r];
             int64_t e = sc.row_ent[r];
-            for (int64_t p = rp[i]; p < rp[i + 1]; ++p, ++e) {
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
                 const int32_t k = ci[p];
                 const int32_t pk = pos[k];
-                if (tile_of[pk] > t || seg_of[pk] >= seg_of[r]) {
+                if (tile_of[pk] > t || (seg_of[pk] >= seg_of[r] && !(inside(r, pk) && pk < r))) {
                     *msg = "internal: triangular schedule order";
                     return false;
+                }
+                if (inside(r, pk)) {  // column-major strictly lower dense block, local (r, c)
+                    const int64_t g = seg_of[r];
+                    const int64_t m = sc.seg_row[g + 1] - sc.seg_row[g];
+                    const int64_t lr = dloc[r], lc = dloc[pk];
+                    sc.csr2ent[p] = sc.tile_dense[t] + sc.seg_dofs[g] + lc * m - lc * (lc + 1) / 2 + (lr - lc - 1);
+                    continue;
                 }
                 sc.csr2ent[p] = e;
                 if (!sc.tile_lds[t]) {
@@ -698,12 +767,14 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
                     }
                     sc.ent_ref[e] = (re - rb) + ext_slot[k];
                 }
+                ++e;
             }
         }
         for (size_t k = x0; k < sc.ext_src.size(); ++k) ext_slot[sc.ext_src[k]] = -1;
         sc.tile_ext.push_back((int32_t)sc.ext_src.size());
         if (sc.tile_lds[t] &&
-            tile_lds_bytes(re - rb, (int64_t)(sc.ext_src.size() - x0), sc.row_ent[re] - sc.row_ent[rb]) > opt.tile_lds) {
+            tile_lds_bytes(re - rb, (int64_t)(sc.ext_src.size() - x0), sc.row_ent[re] - sc.row_ent[rb],
+                           tile_dvals[t]) > opt.tile_lds) {
             *msg = "internal: staged tile exceeds its LDS budget";
             return false;
         }
@@ -867,16 +938,19 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
     }
     // --- triangular-solve schedules; T then holds each triangle's entries packed in solve
     // order (L, then strict U), followed by the diagonal of U in step order
-    if (!tri_schedule(opt, n, a.lrp, a.lci, true, a.lsched, msg) ||
-        !tri_schedule(opt, n, a.urp, a.uci, false, a.usched, msg))
+    if (!tri_schedule(opt, n, a.lrp, a.lci, true, opt.dense_reserve_l, a.lsched, msg) ||
+        !tri_schedule(opt, n, a.urp, a.uci, false, opt.dense_reserve_u, a.usched, msg))
         return AN_EINVAL;
     {
         const int64_t ubase = a.lrp[n], dbase = a.lrp[n] + a.urp[n];
+        const int64_t tu = a.lsched.values(), td = tu + a.usched.values();
         for (int64_t t = 0; t < f; ++t) {
             const int64_t d = a.f2t[t];
             if (d < ubase) a.f2t[t] = (int32_t)a.lsched.csr2ent[d];
-            else if (d < dbase) a.f2t[t] = (int32_t)(ubase + a.usched.csr2ent[d - ubase]);
+            else if (d < dbase) a.f2t[t] = (int32_t)(tu + a.usched.csr2ent[d - ubase]);
+            else a.f2t[t] = (int32_t)(td + (d - dbase));
         }
+        a.t_size = td + n;
     }
     return AN_OK;
 }

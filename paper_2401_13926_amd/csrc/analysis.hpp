@@ -17,12 +17,23 @@ struct AnalysisOptions {
     int tile_threads = 256;      // threads of a triangular-solve block
     int tile_rows = 2048;        // rows of a tile at most
     int64_t tile_lds = 65536;    // LDS bytes of a staged tile at most (tile_lds_bytes)
+    // LDS that tiles keep free for dense blocks (0: no dense segments), per triangle.  The top
+    // of L's DAG is many levels of few long rows, where fusing pays; measured on the 60k
+    // sequence, fusing in U (shorter rows, wider levels) cost more than it saved.
+    int64_t dense_reserve_l = 16384;
+    int64_t dense_reserve_u = 0;
     int narrow_columns = 1024;   // refactorization levels with at most this many columns are
                                  // handed out one column at a time
 };
 
-// Flag in TriSchedule::seg_lg: the segment's rows fit one wavefront.
+// Flags in TriSchedule::seg_lg: the segment's rows fit one wavefront; the segment is a
+// *dense* one (several consecutive levels, at most kDenseRows rows, whose references to each
+// other are kept as a dense strictly lower triangle in solve order and resolved by a
+// wavefront-level column sweep; the packed entries of its rows hold only the references to
+// earlier segments and tiles).
 constexpr int32_t kSegWave = 0x40;
+constexpr int32_t kSegDense = 0x80;
+constexpr int kDenseRows = 64;
 
 // Schedule of one triangular solve.  A tile is a contiguous run of rows solved by one block;
 // it is cut into segments, each a set of mutually independent rows covered by one pass of the
@@ -46,7 +57,14 @@ struct TriSchedule {
     std::vector<int32_t> tile_ext;  // first external of each tile (tiles + 1)
     std::vector<int32_t> ext_src;   // source row of each external
     std::vector<uint8_t> tile_lds;  // 1: staged in LDS, 0: entries read from global memory
-    std::vector<int64_t> csr2ent;   // CSR entry (row-wise layout of the triangle) -> packed entry
+    std::vector<int64_t> csr2ent;   // CSR entry (row-wise layout of the triangle) -> index in the
+                                    // triangle's values: [packed entries | dense blocks]
+    std::vector<int64_t> tile_dense;  // first dense-block value of each tile (tiles + 1), index in
+                                      // the triangle's values
+    std::vector<int32_t> seg_dofs;  // dense segment: offset of its block within the tile's dense
+                                    // values (column-major strictly lower triangle), else -1
+    int64_t packed = 0;             // number of packed entries
+    int64_t values() const { return tile_dense.empty() ? packed : tile_dense.back(); }
     int64_t levels = 0;             // depth of the dependency DAG
     int64_t windows = 0;            // groups of levels whose tiles are mutually independent
     int64_t tiles() const { return (int64_t)tile_seg.size() - 1; }
@@ -54,10 +72,12 @@ struct TriSchedule {
 };
 
 // LDS bytes a staged tile needs with FP64 values (the kernel's layout: solution slots, rhs,
-// diagonal, entry values; row ids, column-permutation ids, row offsets; 16-bit references).
-inline int64_t tile_lds_bytes(int64_t rows, int64_t ext, int64_t ent) {
-    return 8 * (rows + ext) + 36 * rows + 10 * ent + 32;
+// diagonal, entry values, dense-block values; row ids, column-permutation ids, row offsets;
+// 16-bit references).
+inline int64_t tile_lds_bytes(int64_t rows, int64_t ext, int64_t ent, int64_t dense = 0) {
+    return 8 * (rows + ext) + 36 * rows + 10 * ent + 8 * dense + 32;
 }
+inline int64_t dense_block_values(int64_t m) { return m * (m - 1) / 2; }
 
 // Everything derived from the pattern and the first system's values.
 //
@@ -100,12 +120,13 @@ struct Analysis {
     int64_t refactor_split = 0;
 
     // Row-wise triangles in step space (strict L, strict U), from which the solve schedules
-    // are built.  Solve layout T = [L packed (nnz_l) | strict U packed (nnz_u - n) | U
-    // diagonal (n, step order)], the packed orders being those of lsched / usched; f2t maps
+    // are built.  Solve layout T = [L values | strict U values | U diagonal (n, step order)],
+    // each triangle's values being its schedule's [packed entries | dense blocks]; f2t maps
     // each F entry to its T index.
     std::vector<int64_t> lrp, urp;  // n+1 each
     std::vector<int32_t> lci, uci;  // column indices (steps), ascending per row
     std::vector<int32_t> f2t;
+    int64_t t_size = 0;  // values in T (dense blocks include explicit zeros)
 
     // Triangular-solve schedules (L forward, U backward).
     TriSchedule lsched, usched;

@@ -387,7 +387,9 @@ template <typename T> struct TrsvArgs {
     const int32_t *tile_ext;  // first external of each tile
     const int32_t *ext_src;   // source row of each external
     const uint8_t *tile_lds;  // 1: staged tile
-    const T *val;             // packed entry values
+    const int64_t *tile_dense;  // first dense-block value of each tile (index into val)
+    const int32_t *seg_dofs;  // dense segment: its block's offset in the tile's dense values
+    const T *val;             // packed entry values, then dense blocks
     const T *diag;            // upper only: diagonal of U in step order
     const double *rhs64;      // lower: right-hand side in original order (gathered by prow)
     const int32_t *prow;      // lower: pivot rows
@@ -438,6 +440,17 @@ template <typename T> __device__ __forceinline__ T group_sum_last(T v, int lg) {
     return v;
 }
 
+// Value of lane l (uniform) of v.
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // Read-only schedule data seen through the constant address space: with a uniform index the
 // compiler loads it through the scalar cache, so waiting for it never waits for the
 // kernel's outstanding vector stores.
@@ -445,9 +458,10 @@ template <typename P> __device__ __forceinline__ const __attribute__((address_sp
     return (const __attribute__((address_space(4))) P *)p;
 }
 
-template <typename T, bool kLower>
+template <typename T, bool kLower, bool kDense>
 __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
     __shared__ __align__(16) unsigned char smem[kTileLds];
+    __shared__ T ys[kDenseRows];  // dense segment: rows' right-hand sides minus earlier terms
     __shared__ unsigned int tile_sh;
     if (a.stopflag && a.stopflag->stop) return;
     const int tid = threadIdx.x;
@@ -492,12 +506,16 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
         }
         const int xb = uniform_ro(a.tile_ext)[t];
         const int nx = uniform_ro(a.tile_ext)[t + 1] - xb;
+        const int64_t db = uniform_ro(a.tile_dense)[t];
+        const int nd = (int)(uniform_ro(a.tile_dense)[t + 1] - db);
+        const auto seg_dofs = uniform_ro(a.seg_dofs);
         // LDS carve-up: 8-byte arrays first, then 4-byte, then 2-byte
         T *xs = reinterpret_cast<T *>(smem);       // nr + nx solution slots
         T *rhs = xs + nr + nx;                     // nr
         T *dg = rhs + nr;                          // nr (upper)
         T *vals = dg + nr;                         // ne
-        int32_t *rid = reinterpret_cast<int32_t *>(vals + ne);  // nr
+        T *dvs = vals + ne;                        // nd: dense blocks
+        int32_t *rid = reinterpret_cast<int32_t *>(dvs + nd);  // nr
         int32_t *qid = rid + nr;                   // nr (upper)
         int32_t *roff = qid + nr;                  // nr + 1
         uint16_t *refs = reinterpret_cast<uint16_t *>(roff + nr + 1);  // ne
@@ -520,6 +538,7 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
                 }
             }
         }
+        for (int k = tid; k < nd; k += kTileThreads) dvs[k] = a.val[db + k];
         for (int r = tid; r < nr; r += kTileThreads) {
             const int i = a.rows[rb + r];
             rid[r] = i;
@@ -550,6 +569,62 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
             const int lg = code & 0xF;
             const int g = 1 << lg;
             if (sg > s0 && !(wave && prev_wave)) __syncthreads();
+            if (kDense && (code & kSegDense)) {
+                // phase A (block pass): each row's terms from earlier segments and tiles
+                const int r = lb + (tid >> lg);
+                T acc = 0;
+                if (r < le) {
+                    const int e1 = roff[r + 1];
+                    for (int e = roff[r] + (tid & (g - 1)); e < e1; e += g) {
+                        const T prod = vals[e] * xs[refs[e]];
+                        acc = acc + prod;
+                    }
+                }
+                acc = group_sum_last(acc, lg);
+                if (r < le && (tid & (g - 1)) == g - 1) ys[r - lb] = rhs[r] - acc;
+                __syncthreads();
+                // phase B (wavefront 0): column sweep over the dense strictly lower block,
+                // lane l owns row l; x_c is broadcast from lane c once its row is final
+                if (tid < 64) {
+                    const int m = le - lb, l = tid;
+                    const T *D = dvs + seg_dofs[sg];
+                    T y = l < m ? ys[l] : T(0);
+                    const T inv = (!kLower && l < m) ? dg[lb + l] : T(1);
+                    // lane l's coefficient of column c (0 above the diagonal), read four
+                    // columns ahead of its use
+                    auto coef = [&](int c) -> T {
+                        return (l > c && l < m) ? D[c * m - c * (c + 1) / 2 + (l - c - 1)] : T(0);
+                    };
+                    T q0 = coef(0), q1 = coef(1), q2 = coef(2), q3 = coef(3);
+                    for (int c = 0; c < m; c += 4) {
+                        const T n0 = coef(c + 4), n1 = coef(c + 5), n2 = coef(c + 6), n3 = coef(c + 7);
+                        const T qs[4] = {q0, q1, q2, q3};
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (c + u < m) {
+                                const T xc = lane_value(kLower ? y : y * inv, c + u);
+                                if (l > c + u) {
+                                    const T prod = qs[u] * xc;
+                                    y = y - prod;
+                                }
+                            }
+                        }
+                        q0 = n0;
+                        q1 = n1;
+                        q2 = n2;
+                        q3 = n3;
+                    }
+                    if (l < m) {
+                        const T res = kLower ? y : y * inv;
+                        const int r2 = lb + l;
+                        xs[r2] = res;
+                        store_ready(a.out + rid[r2], res);
+                        if (!kLower) a.xout[qid[r2]] = (double)res;
+                    }
+                }
+                prev_wave = true;  // the last writer is wavefront 0
+                continue;
+            }
             prev_wave = wave;
             if (wave && tid >= 64) continue;
             const int r = lb + (tid >> lg);
@@ -1002,7 +1077,8 @@ struct DevLayout {
     // triangular-solve schedules (L, U): rows, level starts, lanes, tiles, references
     int32_t *l_rows, *l_seg, *l_tseg, *l_ref, *l_text, *l_esrc;
     int32_t *u_rows, *u_seg, *u_tseg, *u_ref, *u_text, *u_esrc;
-    int64_t *l_rent, *u_rent;
+    int64_t *l_rent, *u_rent, *l_tden, *u_tden;
+    int32_t *l_sdof, *u_sdof;
     int32_t *l_slg, *u_slg;
     uint8_t *l_tlds, *u_tlds;
     // values
@@ -1135,8 +1211,8 @@ struct Planner {
 // Offsets of every array inside the workspace (also gives the total size).
 struct Offsets {
     size_t fp, fi, fdiag, order, f2t, relptr, fsrc, relpos, krp, kci, l_rows, l_seg, l_tseg,
-        l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
-        u_rent, u_tlds, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
+        l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, l_tden, l_sdof, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
+        u_rent, u_tlds, u_tden, u_sdof, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
         z32, dv, rr, part, ctl, total;
 };
 
@@ -1164,6 +1240,8 @@ Offsets plan(const kkt_handle_t h) {
     o.l_esrc = p.take<int32_t>(a.lsched.ext_src.size());
     o.l_rent = p.take<int64_t>(a.lsched.row_ent.size());
     o.l_tlds = p.take<uint8_t>(a.lsched.tile_lds.size());
+    o.l_tden = p.take<int64_t>(a.lsched.tile_dense.size());
+    o.l_sdof = p.take<int32_t>(a.lsched.seg_dofs.size());
     o.l_slg = p.take<int32_t>(a.lsched.seg_lg.size());
     o.u_rows = p.take<int32_t>(n);
     o.u_seg = p.take<int32_t>(a.usched.seg_row.size());
@@ -1173,14 +1251,16 @@ Offsets plan(const kkt_handle_t h) {
     o.u_esrc = p.take<int32_t>(a.usched.ext_src.size());
     o.u_rent = p.take<int64_t>(a.usched.row_ent.size());
     o.u_tlds = p.take<uint8_t>(a.usched.tile_lds.size());
+    o.u_tden = p.take<int64_t>(a.usched.tile_dense.size());
+    o.u_sdof = p.take<int32_t>(a.usched.seg_dofs.size());
     o.u_slg = p.take<int32_t>(a.usched.seg_lg.size());
     o.prow = p.take<int32_t>(n);
     o.q = p.take<int32_t>(n);
     o.kval = p.take<double>(a.nnz);
     o.F64 = p.take<double>(f);
-    o.T64 = p.take<double>(f);
+    o.T64 = p.take<double>(a.t_size);
     o.F32 = p.take<float>(f);
-    o.T32 = p.take<float>(f);
+    o.T32 = p.take<float>(a.t_size);
     o.Ld64 = p.take<double>(f);
     o.Ld32 = p.take<float>(f);
     o.V = p.take<double>((size_t)(R + 1) * n);
@@ -1255,14 +1335,16 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     t.tile_ext = lower ? d.l_text : d.u_text;
     t.ext_src = lower ? d.l_esrc : d.u_esrc;
     t.tile_lds = lower ? d.l_tlds : d.u_tlds;
+    t.tile_dense = lower ? d.l_tden : d.u_tden;
+    t.seg_dofs = lower ? d.l_sdof : d.u_sdof;
     const T *base = (const T *)(is64 ? (void *)d.T64 : (void *)d.T32);
     if (lower) {
         t.val = base;
         t.rhs64 = rhs64;
         t.prow = d.prow;
     } else {
-        t.val = base + a.lrp[a.n];
-        t.diag = base + a.lrp[a.n] + a.urp[a.n];
+        t.val = base + a.lsched.values();
+        t.diag = base + a.lsched.values() + a.usched.values();
         t.rhs_step = rhs_step;
         t.xout = xout;
         t.q = d.q;
@@ -1272,8 +1354,12 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     t.work = lower ? &d.ctl->work_lower : &d.ctl->work_upper;
     t.hang = &d.ctl->hang;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(is64 ? h->grid_trsv64 : h->grid_trsv32, t.ntiles));
-    if (lower) k_trsv<T, true><<<grid, kTileThreads, 0, s>>>(t);
-    else k_trsv<T, false><<<grid, kTileThreads, 0, s>>>(t);
+    // the variant without the dense-segment path when the schedule has none
+    const bool dense = sc.values() > sc.packed;
+    if (lower && dense) k_trsv<T, true, true><<<grid, kTileThreads, 0, s>>>(t);
+    else if (lower) k_trsv<T, true, false><<<grid, kTileThreads, 0, s>>>(t);
+    else if (dense) k_trsv<T, false, true><<<grid, kTileThreads, 0, s>>>(t);
+    else k_trsv<T, false, false><<<grid, kTileThreads, 0, s>>>(t);
     return hipGetLastError();
 }
 
@@ -1722,6 +1808,8 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.l_esrc = (int32_t *)(b + o.l_esrc);
     d.l_rent = (int64_t *)(b + o.l_rent);
     d.l_tlds = (uint8_t *)(b + o.l_tlds);
+    d.l_tden = (int64_t *)(b + o.l_tden);
+    d.l_sdof = (int32_t *)(b + o.l_sdof);
     d.l_slg = (int32_t *)(b + o.l_slg);
     d.u_rows = (int32_t *)(b + o.u_rows);
     d.u_seg = (int32_t *)(b + o.u_seg);
@@ -1731,6 +1819,8 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.u_esrc = (int32_t *)(b + o.u_esrc);
     d.u_rent = (int64_t *)(b + o.u_rent);
     d.u_tlds = (uint8_t *)(b + o.u_tlds);
+    d.u_tden = (int64_t *)(b + o.u_tden);
+    d.u_sdof = (int32_t *)(b + o.u_sdof);
     d.u_slg = (int32_t *)(b + o.u_slg);
     d.prow = (int32_t *)(b + o.prow);
     d.q = (int32_t *)(b + o.q);
@@ -1771,6 +1861,8 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.l_esrc, a.lsched.ext_src, s));
     KKT_HIP(h, up(b, o.l_rent, a.lsched.row_ent, s));
     KKT_HIP(h, up(b, o.l_tlds, a.lsched.tile_lds, s));
+    KKT_HIP(h, up(b, o.l_tden, a.lsched.tile_dense, s));
+    KKT_HIP(h, up(b, o.l_sdof, a.lsched.seg_dofs, s));
     KKT_HIP(h, up(b, o.l_slg, a.lsched.seg_lg, s));
     KKT_HIP(h, up(b, o.u_rows, a.usched.rows, s));
     KKT_HIP(h, up(b, o.u_seg, a.usched.seg_row, s));
@@ -1780,18 +1872,27 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.u_esrc, a.usched.ext_src, s));
     KKT_HIP(h, up(b, o.u_rent, a.usched.row_ent, s));
     KKT_HIP(h, up(b, o.u_tlds, a.usched.tile_lds, s));
+    KKT_HIP(h, up(b, o.u_tden, a.usched.tile_dense, s));
+    KKT_HIP(h, up(b, o.u_sdof, a.usched.seg_dofs, s));
     KKT_HIP(h, up(b, o.u_slg, a.usched.seg_lg, s));
     KKT_HIP(h, up(b, o.prow, a.prow, s));
     KKT_HIP(h, up(b, o.q, a.q, s));
     KKT_HIP(h, hipMemsetAsync(d.ctl, 0, sizeof(Control), s));
+    // dense blocks of the solve layout hold explicit zeros that the refactorization never writes
+    KKT_HIP(h, hipMemsetAsync(d.T64, 0, a.t_size * sizeof(double), s));
+    KKT_HIP(h, hipMemsetAsync(d.T32, 0, a.t_size * sizeof(float), s));
     KKT_HIP(h, hipMemsetAsync(d.part, 0, (size_t)3 * kStreamGridMax * kPartStride * sizeof(double), s));
     KKT_HIP(h, hipStreamSynchronize(s));
     h->grid_refactor64 = coop_grid((const void *)k_refactor<double>, h->device);
     h->grid_refactor32 = coop_grid((const void *)k_refactor<float>, h->device);
-    h->grid_trsv64 = std::min(coop_grid((const void *)k_trsv<double, true>, h->device),
-                              coop_grid((const void *)k_trsv<double, false>, h->device));
-    h->grid_trsv32 = std::min(coop_grid((const void *)k_trsv<float, true>, h->device),
-                              coop_grid((const void *)k_trsv<float, false>, h->device));
+    h->grid_trsv64 = std::min(std::min(coop_grid((const void *)k_trsv<double, true, true>, h->device),
+                                       coop_grid((const void *)k_trsv<double, false, true>, h->device)),
+                              std::min(coop_grid((const void *)k_trsv<double, true, false>, h->device),
+                                       coop_grid((const void *)k_trsv<double, false, false>, h->device)));
+    h->grid_trsv32 = std::min(std::min(coop_grid((const void *)k_trsv<float, true, true>, h->device),
+                                       coop_grid((const void *)k_trsv<float, false, true>, h->device)),
+                              std::min(coop_grid((const void *)k_trsv<float, true, false>, h->device),
+                                       coop_grid((const void *)k_trsv<float, false, false>, h->device)));
     if (h->grid_refactor64 <= 0 || h->grid_refactor32 <= 0 || h->grid_trsv64 <= 0 || h->grid_trsv32 <= 0)
         return fail(h, KKT_EDEVICE, "occupancy query failed");
     h->grid_stream = stream_blocks(a.n);

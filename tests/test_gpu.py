@@ -321,3 +321,37 @@ def test_solve_dd_residual_sequence(dev):
         assert info["converged"] == 1 and info["nrbe"] <= 1e-12
         m = oracle.metrics(p.rowptr, p.colidx, v, x.cpu().numpy(), b)
         assert m["nrbe"] <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["1x1", "2x2", "3x3-dense"])
+def test_tiny_systems(dev, case):
+    # degenerate sizes: one row, a 2x2 KKT block, a dense 3x3 (every schedule is one tile)
+    say("tiny system", case)
+    if case == "1x1":
+        rp, ci, v = np.array([0, 1]), np.array([0], np.int32), np.array([4.0])
+    elif case == "2x2":
+        rp, ci, v = np.array([0, 2, 4]), np.array([0, 1, 0, 1], np.int32), np.array([1e-3, 1.0, 1.0, -1e-8])
+    else:
+        rp = np.array([0, 3, 6, 9])
+        ci = np.array([0, 1, 2] * 3, np.int32)
+        v = np.array([2.0, -1.0, 0.5, -1.0, 3.0, 1.0, 0.5, 1.0, -4.0])
+    n = len(rp) - 1
+    b = np.arange(1.0, n + 1.0)
+    s = P.Solver(rp, ci, v, restart=1).bind(dev)
+    s.refactor(cuda(v, dev))
+    x, info = s.solve(cuda(b, dev))
+    A = ks.to_dense(rp, ci, v, n)
+    xe = np.linalg.solve(A, b)
+    assert info["converged"] == 1
+    assert np.allclose(x.cpu().numpy(), xe, rtol=1e-12, atol=0)
+
+
+def test_restart_one_on_60k(dev):
+    # FGMRES(1): every cycle is one Arnoldi step; still converges under the same control
+    say("restart 1 on 60k")
+    p, s, _ = make(2, dev, restart=1)
+    v, b = p.system(2)
+    s.refactor(cuda(v, dev))
+    x, info = s.solve(cuda(b, dev))
+    assert info["converged"] == 1 and info["nrbe"] <= 1e-12
+    assert info["cycles"] == info["iterations"]
