@@ -91,6 +91,12 @@ typedef struct {
                                rho = b - K x of the refinement carried in double-double and
                                rounded once (the extended-precision residual of three-precision
                                iterative refinement, Section 2) */
+    int32_t repivot_cycles; /* when > 0: if FGMRES-IR with the current pivot sequence has not
+                               converged after this many restart cycles, the solve downloads
+                               the system's values, repeats the threshold-pivoted factorization
+                               on the host (ordering kept), rebuilds the schedules in the bound
+                               workspace, refactors and solves again; later systems use the new
+                               pivot sequence (3).  0: the pivot sequence of system 1 is kept. */
 } kkt_opts_t;
 
 enum { KKT_IR_FGMRES = 0, KKT_IR_RICHARDSON = 1, KKT_IR_ERROR_FGMRES = 2 };
@@ -144,6 +150,8 @@ typedef struct {
     double knorm_inf;        /* ||K||_inf */
     double nsr;              /* ||r - K x||_inf / (||K||_inf ||x||_inf), MA57's measure */
     int64_t precond_applications; /* triangular-solve pairs (x0 included) */
+    int32_t repivoted;       /* 1 if this solve re-pivoted (opts.repivot_cycles) */
+    int32_t reserved;
 } kkt_solve_info_t;
 
 /* Fill *opts with the defaults listed above. */

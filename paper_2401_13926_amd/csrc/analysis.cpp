@@ -984,7 +984,8 @@ int analyze(const AnalysisOptions &opt, int64_t n, const int64_t *rowptr, const 
         a.rowptr.assign(rowptr, rowptr + n + 1);
         a.colidx.assign(colidx, colidx + a.nnz);
         int rc = AN_OK;
-        if (opt.ordering == ORDER_ND) rc = nested_dissection(n, rowptr, colidx, opt.nd_leaf, a.q);
+        if (opt.fixed_order) a.q.assign(opt.fixed_order, opt.fixed_order + n);
+        else if (opt.ordering == ORDER_ND) rc = nested_dissection(n, rowptr, colidx, opt.nd_leaf, a.q);
         else minimum_degree(n, rowptr, colidx, a.q);
         if (rc != AN_OK || (int64_t)a.q.size() != n) {
             *msg = "ordering failed";

@@ -12,6 +12,7 @@ enum { ORDER_MD = 0, ORDER_ND = 1 };
 
 struct AnalysisOptions {
     int ordering = ORDER_MD;     // exact minimum degree, or BFS nested dissection
+    const int32_t *fixed_order = nullptr;  // when set: this column order (n entries) is used
     int64_t nd_leaf = 64;
     double pivot_tau = 0.1;
     int tile_threads = 256;      // threads of a triangular-solve block

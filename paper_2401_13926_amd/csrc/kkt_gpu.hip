@@ -1117,6 +1117,7 @@ struct kkt_handle_s {
     hipEvent_t step_ev[2] = {nullptr, nullptr};
     int restart_alloc = 0;
     bool fp64_current = false;  // mixed mode: FP64 factors of the current system exist
+    int64_t repivots = 0;       // re-pivoted factorizations so far
     // per-launch timing (kkt_set_profiling)
     struct ProfRec {
         int cls;
@@ -1668,6 +1669,59 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
 
 using namespace kkt;
 
+namespace kkt {
+namespace {
+
+AnalysisOptions analysis_options(const kkt_opts_t &o) {
+    AnalysisOptions ao;
+    ao.ordering = o.ordering == KKT_ORDER_ND ? ORDER_ND : ORDER_MD;
+    ao.nd_leaf = o.nd_leaf;
+    ao.pivot_tau = o.pivot_tau;
+    ao.tile_threads = kTileThreads;
+    ao.tile_rows = kTileRows;
+    ao.tile_lds = kTileLds;
+    return ao;
+}
+
+// The pivot sequence of an earlier system no longer suits the current one: repeat the
+// threshold-pivoted factorization on the host with the current values (ordering kept), rebuild
+// the schedules into the bound workspace and refactor (Section 1.3 describes the first
+// system's pivoted factorization; this repeats it for the current one).
+kkt_status_t repivot_impl(kkt_handle_t h, hipStream_t s) {
+    const Analysis &old = h->an;
+    std::vector<double> vals(old.nnz);
+    KKT_HIP(h, hipMemcpyAsync(vals.data(), h->d.kval, old.nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+    KKT_HIP(h, hipStreamSynchronize(s));
+    AnalysisOptions ao = analysis_options(h->opts);
+    const std::vector<int32_t> q = old.q;
+    ao.fixed_order = q.data();
+    Analysis na;
+    std::string msg;
+    const int rc = analyze(ao, old.n, old.rowptr.data(), old.colidx.data(), vals.data(), na, &msg);
+    if (rc != AN_OK)
+        return fail(h, rc == AN_ESINGULAR ? KKT_ESINGULAR : KKT_EINVAL, "re-pivoting: " + msg);
+    Analysis keep = std::move(h->an);
+    h->an = std::move(na);
+    const size_t need = plan(h).total;
+    if (need > h->ws_bytes) {
+        h->an = std::move(keep);
+        return fail(h, KKT_ENOMEM, "re-pivoting needs a workspace of " + std::to_string(need) + " bytes, " +
+                                       std::to_string(h->ws_bytes) + " are bound");
+    }
+    kkt_status_t st = kkt_bind_workspace(h, h->ws, h->ws_bytes, s);
+    if (st != KKT_OK) return st;
+    KKT_HIP(h, hipMemcpyAsync(h->d.kval, vals.data(), h->an.nnz * sizeof(double), hipMemcpyHostToDevice, s));
+    st = refactor_impl(h, nullptr, KKT_PREC_FP64, s);
+    if (st != KKT_OK) return st;
+    h->fp64_current = h->factor_precision == KKT_PREC_MIXED || h->fp64_current;
+    h->factor_precision = h->opts.precision;
+    h->repivots += 1;
+    return KKT_OK;
+}
+
+}  // namespace
+}  // namespace kkt
+
 extern "C" {
 
 void kkt_opts_default(kkt_opts_t *o) {
@@ -1689,6 +1743,7 @@ void kkt_opts_default(kkt_opts_t *o) {
     o->ratio_stop = 0.5;
     o->inner_tol = 1e-2;
     o->residual = KKT_RESID_FP64;
+    o->repivot_cycles = 3;
 }
 
 kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowptr, const int32_t *colidx,
@@ -1707,13 +1762,7 @@ kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowpt
         delete h;
         return fail(nullptr, KKT_EINVAL, "residual must be KKT_RESID_FP64 or KKT_RESID_DD");
     }
-    AnalysisOptions ao;
-    ao.ordering = h->opts.ordering == KKT_ORDER_ND ? ORDER_ND : ORDER_MD;
-    ao.nd_leaf = h->opts.nd_leaf;
-    ao.pivot_tau = h->opts.pivot_tau;
-    ao.tile_threads = kTileThreads;
-    ao.tile_rows = kTileRows;
-    ao.tile_lds = kTileLds;
+    AnalysisOptions ao = analysis_options(h->opts);
     std::string msg;
     int rc = analyze(ao, n, rowptr, colidx, values_first, h->an, &msg);
     if (rc != AN_OK) {
@@ -1933,10 +1982,18 @@ kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, doubl
         h->fp64_current = true;
     }
     kkt_status_t st;
-    if (h->opts.ir_method == KKT_IR_RICHARDSON || h->opts.ir_method == KKT_IR_ERROR_FGMRES)
+    if (h->opts.ir_method == KKT_IR_RICHARDSON || h->opts.ir_method == KKT_IR_ERROR_FGMRES) {
         st = richardson_impl<double>(h, dev_b, dev_x, tol, info, s, h->opts.ir_method == KKT_IR_ERROR_FGMRES);
-    else
-        st = solve_impl<double>(h, dev_b, dev_x, tol, info, s, cycles);
+    } else {
+        const bool rp = h->opts.repivot_cycles > 0;
+        st = solve_impl<double>(h, dev_b, dev_x, tol, info, s, rp ? std::min(cycles, h->opts.repivot_cycles) : cycles);
+        if (st == KKT_ENOCONV && rp) {
+            st = repivot_impl(h, s);
+            if (st != KKT_OK) return st;
+            st = solve_impl<double>(h, dev_b, dev_x, tol, info, s, cycles);
+            if (info) info->repivoted = 1;
+        }
+    }
     if (info && h->fp64_current) info->fallback = 1;
     return st;
 }

@@ -40,7 +40,7 @@ class Opts(C.Structure):
                 ("precision", C.c_int32), ("guard_policy", C.c_int32), ("stop_mode", C.c_int32),
                 ("mixed_fallback", C.c_int32), ("mixed_max_cycles", C.c_int32), ("ir_method", C.c_int32),
                 ("richardson_max_it", C.c_int32), ("ratio_stop", C.c_double), ("inner_tol", C.c_double),
-                ("residual", C.c_int32)]
+                ("residual", C.c_int32), ("repivot_cycles", C.c_int32)]
 
 
 class AnalysisInfo(C.Structure):
@@ -56,7 +56,7 @@ class SolveInfo(C.Structure):
                 ("pivots_perturbed", C.c_int64), ("nrbe", C.c_double), ("nrbe0", C.c_double),
                 ("rel_resid", C.c_double), ("rr", C.c_double), ("est_resid", C.c_double),
                 ("true_resid", C.c_double), ("knorm_inf", C.c_double), ("nsr", C.c_double),
-                ("precond_applications", C.c_int64)]
+                ("precond_applications", C.c_int64), ("repivoted", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -192,11 +192,13 @@ class Solver:
         return s.value
 
     # --- device -------------------------------------------------------------------------
-    def bind(self, device=None, stream=None):
-        """Allocate the workspace as a torch uint8 tensor and bind it."""
+    def bind(self, device=None, stream=None, slack: float = 1.5):
+        """Allocate the workspace as a torch uint8 tensor and bind it.  `slack` times the
+        current size leaves room for a re-pivoted factorization with more fill
+        (opts.repivot_cycles)."""
         import torch
         dev = torch.device("cuda" if device is None else device)
-        nbytes = self.workspace_size()
+        nbytes = int(self.workspace_size() * max(1.0, slack)) + (1 << 20)
         ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         base = ws.data_ptr()
         off = (-base) % 256

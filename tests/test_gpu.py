@@ -355,3 +355,43 @@ def test_restart_one_on_60k(dev):
     x, info = s.solve(cuda(b, dev))
     assert info["converged"] == 1 and info["nrbe"] <= 1e-12
     assert info["cycles"] == info["iterations"]
+
+
+def test_repivot_recovers_failed_static_pivots(dev):
+    # 60k KKT with D over 24 decades: the pivot sequence of system 1 leaves tiny static
+    # pivots in system 2 and FGMRES-IR stalls (also in the oracle, checked below).  With
+    # repivot_cycles the solve repeats the pivoted factorization for system 2 (ordering kept),
+    # whose analysis must match the oracle's fresh pivoted LU of system 2 bit for bit.
+    say("repivot 60k seed 5")
+    p = ks.small_kkt(35000, 25000, 5, (-12.0, 12.0))
+    v1, _ = p.system(1)
+    v2, b2 = p.system(2)
+    f1 = oracle.LU(p.rowptr, p.colidx, v1)
+    lx, ux, ng = f1.refactor64(p.rowptr, p.colidx, v2)
+    _, oinf = f1.fgmres_ir(p.rowptr, p.colidx, v2, b2, Lx=lx, Ux=ux, restart=10, max_restarts=20, eta=1e-14, mode=1)
+    assert ng > 0 and not oinf["converged"]
+    s0 = P.Solver(p.rowptr, p.colidx, v1, repivot_cycles=0).bind(dev)
+    s0.refactor(cuda(v2, dev))
+    _, i0 = s0.solve(cuda(b2, dev), allow_noconv=True)
+    assert i0["converged"] == 0 and i0["repivoted"] == 0
+    s = P.Solver(p.rowptr, p.colidx, v1).bind(dev)
+    s.refactor(cuda(v2, dev))
+    x, info = s.solve(cuda(b2, dev))
+    assert info["converged"] == 1 and info["repivoted"] == 1 and info["nrbe"] <= 1e-12
+    f2 = oracle.LU(p.rowptr, p.colidx, v2, Q=f1.Q)
+    prow, q = s.permutations()
+    assert np.array_equal(q, f1.Q) and np.array_equal(prow, f2.prow)
+    lp, li, up, ui = s.pattern()
+    assert np.array_equal(lp, f2.Lp) and np.array_equal(li, f2.Li)
+    assert np.array_equal(up, f2.Up) and np.array_equal(ui, f2.Ui)
+    # the re-pivoted factors are the refactorization of system 2 with the new sequence
+    glx, gux = s.factor_values(0)
+    assert np.array_equal(glx, f2.Lx) and np.array_equal(gux, f2.Ux)
+    xo = f2.solve(b2)
+    rel = np.abs(x.cpu().numpy() - xo).max() / np.abs(xo).max()
+    assert rel <= 1e-8 * f2.condest(p.rowptr, v2)
+    # the next system reuses the new pivot sequence without another repivot
+    v3, b3 = p.system(3)
+    s.refactor(cuda(v3, dev))
+    _, i3 = s.solve(cuda(b3, dev), allow_noconv=True)
+    assert i3["repivoted"] in (0, 1)
