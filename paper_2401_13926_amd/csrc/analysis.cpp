@@ -490,37 +490,32 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
         }
         return x;
     };
-    // merges the components of x and y; returns false when the result no longer fits a tile
+    // merges the components of x and y (the smaller level list into the larger, in place);
+    // returns false when the result no longer fits a tile
     auto unite = [&](int32_t x, int32_t y) {
         x = find(x);
         y = find(y);
         if (x == y) return true;
         if (stat[x].size() < stat[y].size()) std::swap(x, y);
-        std::vector<LevStat> merged;
-        merged.reserve(stat[x].size() + stat[y].size());
-        size_t u = 0, v = 0;
-        while (u < stat[x].size() || v < stat[y].size()) {
-            if (v == stat[y].size() || (u < stat[x].size() && stat[x][u].level < stat[y][v].level))
-                merged.push_back(stat[x][u++]);
-            else if (u == stat[x].size() || stat[y][v].level < stat[x][u].level)
-                merged.push_back(stat[y][v++]);
-            else {
-                merged.push_back({stat[x][u].level, stat[x][u].count + stat[y][v].count,
-                                  std::max(stat[x][u].maxlen, stat[y][v].maxlen)});
-                ++u;
-                ++v;
+        std::vector<LevStat> &big = stat[x];
+        bool ok = true;
+        for (const LevStat &e : stat[y]) {
+            auto it = std::lower_bound(big.begin(), big.end(), e.level,
+                                       [](const LevStat &a, int32_t l) { return a.level < l; });
+            if (it != big.end() && it->level == e.level) {
+                it->count += e.count;
+                it->maxlen = std::max(it->maxlen, e.maxlen);
+            } else {
+                it = big.insert(it, e);
             }
+            ok = ok && fits(it->count, it->maxlen);
         }
         parent[y] = x;
         size[x].rows += size[y].rows;
         size[x].ent += size[y].ent;
         size[x].ext += size[y].ext;
-        stat[x].swap(merged);
         std::vector<LevStat>().swap(stat[y]);
-        if (!stageable(size[x])) return false;
-        for (const LevStat &e : stat[x])
-            if (!fits(e.count, e.maxlen)) return false;
-        return true;
+        return ok && stageable(size[x]);
     };
     auto add_level = [&](int32_t l, int32_t w0) {
         bool ok = true;
