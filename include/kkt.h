@@ -237,12 +237,76 @@ kkt_status_t kkt_set_profiling(kkt_handle_t h, int32_t on);
  * Synchronizes `stream` (the stream the work was issued on). */
 kkt_status_t kkt_get_kernel_times(kkt_handle_t h, kkt_kernel_times_t *times, void *stream);
 
+/* New unbound handle with a copy of src's options and analysis (no host re-analysis): for
+ * several solvers of one pattern running at once (each needs its own workspace).  Errors:
+ * KKT_ENOMEM. */
+kkt_status_t kkt_clone(kkt_handle_t src, kkt_handle_t *out);
+
 /* Free the handle and its host memory (the workspace stays owned by the caller). */
 kkt_status_t kkt_release(kkt_handle_t h);
 
 /* Message for the last failing call on h ("" if none; h may be NULL for kkt_analyze
  * failures, which keep a per-thread message). */
 const char *kkt_last_error(kkt_handle_t h);
+
+/* ------------------------------------------------------------------------------------------
+ * Serving: KKT solves of several patterns arriving from concurrent optimizer instances.
+ *
+ * The server keeps one host analysis per registered pattern and a set of resident solver
+ * *slots* (a cloned handle with its own workspace).  Slot workspaces are carved first-fit
+ * from one caller-owned device pool, so admission is by HBM footprint: a request starts when
+ * a free slot of its pattern exists or a new slot fits in the pool (idle slots of other
+ * patterns are evicted, least recently used first, to make room); otherwise it waits while
+ * later requests that fit go ahead.  `workers` host threads, each with its own HIP stream
+ * (default priority), run admitted requests concurrently, so their kernels overlap on the
+ * device; each request is one refactorization plus one FGMRES-IR solve, exactly as
+ * kkt_refactor + kkt_solve on a handle of that pattern (the same kernels and schedules, hence
+ * the same result bit for bit, alone or in a mix).
+ * ---------------------------------------------------------------------------------------- */
+typedef struct kkt_server_s *kkt_server_t;
+
+typedef struct {
+    double queued_ms;   /* submit -> start of service */
+    double service_ms;  /* start of service -> solution ready (stream synchronized) */
+    double latency_ms;  /* submit -> solution ready */
+    int32_t slot;       /* slot that served the request */
+    int32_t new_slot;   /* 1 if the slot was created (workspace carved and bound) for it */
+} kkt_request_times_t;
+
+/* Create a server on the current HIP device.  dev_pool: DEVICE memory of pool_bytes
+ * (256-byte aligned, caller-owned, outlives the server).  workers >= 1.  Errors:
+ * KKT_EINVAL, KKT_ENOMEM, KKT_EDEVICE. */
+kkt_status_t kkt_server_create(void *dev_pool, size_t pool_bytes, int32_t workers, kkt_server_t *out);
+
+/* Register a pattern: host analysis as kkt_analyze (HOST arrays, copied).  *pattern_id
+ * receives its id (0, 1, ...).  Errors: those of kkt_analyze; KKT_ENOMEM when one slot of
+ * this pattern cannot fit in the pool at all. */
+kkt_status_t kkt_server_add_pattern(kkt_server_t srv, const kkt_opts_t *opts, int64_t n, const int64_t *rowptr,
+                                    const int32_t *colidx, const double *values_first, int32_t *pattern_id);
+
+/* Queue one solve of pattern_id: DEVICE arrays dev_values (nnz, CSR order of the pattern),
+ * dev_b and dev_x (n float64), which must stay valid (and b, values unchanged) until the
+ * request completes; tol <= 0 uses the pattern's delta_tol.  *ticket identifies it.
+ * Never blocks.  Errors: KKT_EINVAL (unknown pattern, null pointers). */
+kkt_status_t kkt_server_submit(kkt_server_t srv, int32_t pattern_id, const double *dev_values,
+                               const double *dev_b, double *dev_x, double tol, int64_t *ticket);
+
+/* Block until the request completes; fill *info and *times (either may be NULL) and forget
+ * the ticket.  Returns the request's status (that of kkt_refactor / kkt_solve; KKT_ENOCONV
+ * with x and info filled as for kkt_solve).  KKT_EINVAL for an unknown ticket. */
+kkt_status_t kkt_server_wait(kkt_server_t srv, int64_t ticket, kkt_solve_info_t *info,
+                             kkt_request_times_t *times);
+
+/* Non-blocking: *done = 1 when the request has completed (then kkt_server_wait returns at
+ * once), else 0.  KKT_EINVAL for an unknown ticket. */
+kkt_status_t kkt_server_poll(kkt_server_t srv, int64_t ticket, int32_t *done);
+
+/* Counters: requests completed, slots created, slots evicted, pool bytes in use. */
+kkt_status_t kkt_server_stats(kkt_server_t srv, int64_t *completed, int64_t *slots_created,
+                              int64_t *slots_evicted, int64_t *pool_in_use);
+
+/* Finish every queued request, stop the workers, release all slots and patterns. */
+kkt_status_t kkt_server_destroy(kkt_server_t srv);
 
 #ifdef __cplusplus
 }

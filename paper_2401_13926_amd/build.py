@@ -9,7 +9,7 @@ import sys
 PKG = pathlib.Path(__file__).resolve().parent
 ROOT = PKG.parent
 LIB = PKG / "libkkt.so"
-SOURCES = [PKG / "csrc" / "kkt_gpu.hip", PKG / "csrc" / "analysis.cpp"]
+SOURCES = [PKG / "csrc" / "kkt_gpu.hip", PKG / "csrc" / "analysis.cpp", PKG / "csrc" / "server.cpp"]
 HEADERS = [PKG / "csrc" / "analysis.hpp", PKG / "csrc" / "kernels.hpp", ROOT / "include" / "kkt.h"]
 ARCH = os.environ.get("KKT_OFFLOAD_ARCH", "gfx950")
 
@@ -25,7 +25,7 @@ def command(out: pathlib.Path) -> list[str]:
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
             "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function", "-I", str(ROOT / "include"),
-            "-o", str(out)] + [str(s) for s in SOURCES]
+            "-o", str(out)] + [str(s) for s in SOURCES] + ["-lpthread"]
 
 
 def build(force: bool = True) -> pathlib.Path:

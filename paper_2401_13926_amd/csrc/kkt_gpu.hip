@@ -2065,6 +2065,22 @@ kkt_status_t kkt_get_kernel_times(kkt_handle_t h, kkt_kernel_times_t *t, void *s
     return KKT_OK;
 }
 
+kkt_status_t kkt_clone(kkt_handle_t src, kkt_handle_t *out) {
+    if (!src || !out) return fail(src, KKT_EINVAL, "null argument");
+    *out = nullptr;
+    kkt_handle_t h = new (std::nothrow) kkt_handle_s();
+    if (!h) return fail(src, KKT_ENOMEM, "out of host memory");
+    try {
+        h->opts = src->opts;
+        h->an = src->an;
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return fail(src, KKT_ENOMEM, "out of host memory");
+    }
+    *out = h;
+    return KKT_OK;
+}
+
 kkt_status_t kkt_release(kkt_handle_t h) {
     if (!h) return KKT_OK;
     for (auto &r : h->ev_pending) {

@@ -29,7 +29,9 @@ EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_
            "kkt_get_factor_pattern", "kkt_get_analysis_values", "kkt_workspace_size",
            "kkt_bind_workspace", "kkt_refactor", "kkt_solve", "kkt_direct_solve", "kkt_residual",
            "kkt_get_factor_values", "kkt_set_profiling", "kkt_get_kernel_times", "kkt_release",
-           "kkt_last_error"]
+           "kkt_last_error",
+           "kkt_clone", "kkt_server_create", "kkt_server_add_pattern", "kkt_server_submit",
+           "kkt_server_wait", "kkt_server_poll", "kkt_server_stats", "kkt_server_destroy"]
 
 KERNEL_CLASSES = ["ingest", "refactor", "trsv_l", "trsv_u", "spmv", "cgs", "resid", "other"]
 
@@ -48,6 +50,14 @@ class AnalysisInfo(C.Structure):
                 ("offdiag_pivots", C.c_int64), ("levels_refactor", C.c_int64),
                 ("levels_l", C.c_int64), ("levels_u", C.c_int64), ("updates", C.c_int64),
                 ("analysis_seconds", C.c_double)]
+
+
+class RequestTimes(C.Structure):
+    _fields_ = [("queued_ms", C.c_double), ("service_ms", C.c_double), ("latency_ms", C.c_double),
+                ("slot", C.c_int32), ("new_slot", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SolveInfo(C.Structure):
@@ -99,6 +109,14 @@ def lib():
         L.kkt_set_profiling.argtypes = [vp, C.c_int32]
         L.kkt_get_kernel_times.argtypes = [vp, C.POINTER(KernelTimes), vp]
         L.kkt_release.argtypes = [vp]
+        L.kkt_clone.argtypes = [vp, C.POINTER(vp)]
+        L.kkt_server_create.argtypes = [vp, C.c_size_t, C.c_int32, C.POINTER(vp)]
+        L.kkt_server_add_pattern.argtypes = [vp, C.POINTER(Opts), i64, i64p, i32p, f64p, i32p]
+        L.kkt_server_submit.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_double, i64p]
+        L.kkt_server_wait.argtypes = [vp, i64, C.POINTER(SolveInfo), C.POINTER(RequestTimes)]
+        L.kkt_server_poll.argtypes = [vp, i64, i32p]
+        L.kkt_server_stats.argtypes = [vp, i64p, i64p, i64p, i64p]
+        L.kkt_server_destroy.argtypes = [vp]
         L.kkt_last_error.argtypes = [vp]
         L.kkt_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -265,3 +283,80 @@ class Solver:
         t = KernelTimes()
         self._check(lib().kkt_get_kernel_times(self._h, C.byref(t), _stream_ptr(stream)))
         return {name: (int(t.launches[i]), float(t.ms[i])) for i, name in enumerate(KERNEL_CLASSES)}
+
+
+class Server:
+    """Serving loop (kkt_server_*): patterns are registered once; requests (device values, b,
+    x) are queued and solved by `workers` concurrent host threads on their own streams, with
+    solver slots carved from one device pool (a torch tensor of pool_bytes)."""
+
+    def __init__(self, pool_bytes: int, workers: int = 4, device=None):
+        import torch
+        dev = torch.device("cuda" if device is None else device)
+        self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=dev)
+        base = self.pool.data_ptr()
+        off = (-base) % 256
+        h = C.c_void_p()
+        rc = lib().kkt_server_create(C.c_void_p(base + off), int(pool_bytes), int(workers), C.byref(h))
+        if rc != KKT_OK:
+            raise KKTError(rc, "kkt_server_create failed")
+        self._h = h
+        self._keep = {}  # ticket -> tensors that must outlive the request
+
+    def add_pattern(self, rowptr, colidx, values_first, **opts) -> int:
+        o = default_opts(**opts)
+        rp = np.ascontiguousarray(rowptr, np.int64)
+        ci = np.ascontiguousarray(colidx, np.int32)
+        v = np.ascontiguousarray(values_first, np.float64)
+        pid = C.c_int32()
+        rc = lib().kkt_server_add_pattern(self._h, C.byref(o), rp.size - 1, _p(rp, C.c_int64), _p(ci, C.c_int32),
+                                          _p(v, C.c_double), C.byref(pid))
+        if rc != KKT_OK:
+            raise KKTError(rc, lib().kkt_last_error(None).decode())
+        return pid.value
+
+    def submit(self, pattern_id: int, values, b, x, tol: float = 0.0) -> int:
+        for t in (values, b, x):
+            assert t.is_cuda and t.element_size() == 8 and t.is_contiguous()
+        tk = C.c_int64()
+        rc = lib().kkt_server_submit(self._h, int(pattern_id), C.c_void_p(values.data_ptr()),
+                                     C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol), C.byref(tk))
+        if rc != KKT_OK:
+            raise KKTError(rc, "kkt_server_submit failed")
+        self._keep[tk.value] = (values, b, x)
+        return tk.value
+
+    def poll(self, ticket: int) -> bool:
+        d = C.c_int32()
+        rc = lib().kkt_server_poll(self._h, int(ticket), C.byref(d))
+        if rc != KKT_OK:
+            raise KKTError(rc, "kkt_server_poll: unknown ticket")
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        """(status, info dict, times dict); the request's tensors are released."""
+        info = SolveInfo()
+        times = RequestTimes()
+        rc = lib().kkt_server_wait(self._h, int(ticket), C.byref(info), C.byref(times))
+        if rc == KKT_EINVAL and int(ticket) not in self._keep:
+            raise KKTError(rc, "kkt_server_wait: unknown ticket")
+        self._keep.pop(int(ticket), None)
+        return rc, info.as_dict(), times.as_dict()
+
+    def stats(self) -> dict:
+        v = [C.c_int64() for _ in range(4)]
+        lib().kkt_server_stats(self._h, *[C.byref(x) for x in v])
+        return dict(completed=v[0].value, slots_created=v[1].value, slots_evicted=v[2].value,
+                    pool_in_use=v[3].value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kkt_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

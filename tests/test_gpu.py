@@ -395,3 +395,54 @@ def test_repivot_recovers_failed_static_pivots(dev):
     s.refactor(cuda(v3, dev))
     _, i3 = s.solve(cuda(b3, dev), allow_noconv=True)
     assert i3["repivoted"] in (0, 1)
+
+
+def _serving_patterns():
+    return [ks.make_pattern(1), ks.small_kkt(6000, 4000, 3)]
+
+
+def _alone(p, steps, dev):
+    s = P.Solver(p.rowptr, p.colidx, p.system(1)[0]).bind(dev)
+    out = []
+    for k in steps:
+        v, b = p.system(k)
+        s.refactor(cuda(v, dev))
+        x, info = s.solve(cuda(b, dev))
+        out.append((x.cpu().numpy(), info))
+    return out
+
+
+@pytest.mark.parametrize("pool_slots", [4.0, 1.2])
+def test_server_results_match_alone(dev, pool_slots):
+    # a mix of two patterns through the serving loop (3 workers): every result equals the
+    # standalone solve of the same system bit for bit; with a pool that holds about one slot
+    # of the larger pattern, requests wait for room and idle slots are evicted
+    say("server mix, pool slots", pool_slots)
+    pats = _serving_patterns()
+    steps = [1, 2, 3, 4]
+    alone = [_alone(p, steps, dev) for p in pats]
+    sizes = []
+    for p in pats:
+        s = P.Solver(p.rowptr, p.colidx, p.system(1)[0])
+        sizes.append(int(s.workspace_size() * 1.5) + (1 << 20))
+    srv = P.Server(int(max(sizes) * pool_slots), workers=3, device=dev)
+    pids = [srv.add_pattern(p.rowptr, p.colidx, p.system(1)[0]) for p in pats]
+    reqs = []
+    for k_i, k in enumerate(steps):
+        for pi, p in enumerate(pats):
+            v, b = p.system(k)
+            vv, bb = cuda(v, dev), cuda(b, dev)
+            x = torch.empty_like(bb)
+            reqs.append((pi, k_i, x, srv.submit(pids[pi], vv, bb, x)))
+    for pi, k_i, x, t in reqs:
+        rc, info, times = srv.wait(t)
+        assert rc == P.KKT_OK and info["converged"] == 1
+        xa, ia = alone[pi][k_i]
+        assert np.array_equal(x.cpu().numpy(), xa)
+        assert info["iterations"] == ia["iterations"]
+        assert times["latency_ms"] >= times["service_ms"] >= 0.0
+    st = srv.stats()
+    assert st["completed"] == len(reqs)
+    if pool_slots < 2:
+        assert st["slots_evicted"] > 0
+    srv.close()

@@ -114,10 +114,11 @@ def test_abi_struct_sizes_match_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     src = tmp_path / "sz.c"
-    src.write_text('#include "kkt.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu %zu %zu\\n",'
+    src.write_text('#include "kkt.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu %zu %zu %zu\\n",'
                    'sizeof(kkt_opts_t), sizeof(kkt_solve_info_t), sizeof(kkt_analysis_info_t),'
-                   'sizeof(kkt_kernel_times_t)); return 0;}\n')
+                   'sizeof(kkt_kernel_times_t), sizeof(kkt_request_times_t)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run([cc, "-I", str(ROOT / "include"), "-o", str(exe), str(src)], check=True)
     sizes = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
-    assert sizes == [C.sizeof(K.Opts), C.sizeof(K.SolveInfo), C.sizeof(K.AnalysisInfo), C.sizeof(K.KernelTimes)]
+    assert sizes == [C.sizeof(K.Opts), C.sizeof(K.SolveInfo), C.sizeof(K.AnalysisInfo), C.sizeof(K.KernelTimes),
+                     C.sizeof(K.RequestTimes)]
