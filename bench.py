@@ -166,6 +166,89 @@ def cpu_baseline(pattern, systems, budget_s, gpu_xs=None):
     return done, el, cmp
 
 
+def run_serving(P, torch, args):
+    """Serving workload: requests of 8 patterns (dims 7,000..500,000) arrive as a Poisson
+    process; each is the next system of its pattern (refactor + FGMRES-IR).  Then the same
+    requests all at once (saturation).  Latency = completion - arrival, from the library."""
+    import threading
+    import kkt_synth as ks
+    dev = torch.device("cuda:0")
+    npat = len(ks.SERVING_DIMS)
+    steps = max(1, args.serve_steps)
+    pats, vals, rhs = [], [], []
+    t0 = time.perf_counter()
+    for k in range(npat):
+        p = ks.make_pattern(4, k)
+        pats.append(p)
+        sys_k = [p.system(s) for s in range(1, steps + 1)]
+        vals.append([torch.as_tensor(v, device=dev) for v, _ in sys_k])
+        rhs.append([torch.as_tensor(b, device=dev) for _, b in sys_k])
+    gen_s = time.perf_counter() - t0
+    srv = P.Server(int(args.pool_gb * (1 << 30)), workers=args.workers, device=dev)
+    t0 = time.perf_counter()
+    pids = [srv.add_pattern(p.rowptr, p.colidx, p.system(1)[0]) for p in pats]
+    analysis_s = time.perf_counter() - t0
+    print("serving: %d patterns analysed in %.1f s (inputs %.1f s)" % (npat, analysis_s, gen_s),
+          file=sys.stderr, flush=True)
+    rng = np.random.default_rng([2401, 4])
+    pat_of = rng.integers(0, npat, size=args.requests)
+    gaps = rng.exponential(1.0 / args.rate, size=args.requests)
+
+    def one_run(saturate):
+        nxt = [0] * npat
+        res = [None] * args.requests
+        tickets = [None] * args.requests
+        ready = threading.Semaphore(0)
+
+        def collector():
+            for i in range(args.requests):
+                ready.acquire()
+                res[i] = srv.wait(tickets[i])
+        th = threading.Thread(target=collector)
+        th.start()
+        start = time.perf_counter()
+        t_arr = start
+        for i in range(args.requests):
+            if not saturate:
+                t_arr += gaps[i]
+                dt = t_arr - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            k = int(pat_of[i])
+            j = nxt[k] % steps
+            nxt[k] += 1
+            x = torch.empty_like(rhs[k][j])
+            tickets[i] = srv.submit(pids[k], vals[k][j], rhs[k][j], x)
+            ready.release()
+        th.join()
+        wall = time.perf_counter() - start
+        lat = [r[2]["latency_ms"] for r in res]
+        svc = [r[2]["service_ms"] for r in res]
+        conv = [r[1]["converged"] == 1 for r in res]
+        return {"solves_per_s": args.requests / wall, "wall_s": wall,
+                "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                "service_p50_ms": percentile(svc, 50), "service_p99_ms": percentile(svc, 99),
+                "all_converged": all(conv), "repivots": int(sum(r[1]["repivoted"] for r in res)),
+                "max_nrbe": max(r[1]["nrbe"] for r in res)}
+
+    poisson = one_run(False)
+    print("poisson run done", file=sys.stderr, flush=True)
+    sat = one_run(True)
+    st = srv.stats()
+    srv.close()
+    out = {
+        "metric": "KKT solves/s served (refactor+FGMRES-IR to NRBE<=1e-12), p50/p99 latency ms",
+        "value": poisson["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.requests,
+        "warmup": 0, "ms_per_step": 1e3 * poisson["wall_s"] / args.requests, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded KKT generator, %d systems per pattern cycled)" % steps,
+        "config": {"workload": "kkt_serving_8_patterns", "dims": list(ks.SERVING_DIMS), "requests": args.requests,
+                   "rate_per_s": args.rate, "workers": args.workers, "pool_gb": args.pool_gb},
+        "poisson": poisson, "saturation": sat, "server": st, "analysis_s": analysis_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +260,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving workload: Poisson arrivals over 8 patterns, then saturation")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--pool-gb", type=float, default=32.0)
+    ap.add_argument("--serve-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB device buffer 4 times (reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -198,6 +288,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.serve:
+        run_serving(P, torch, args)
+        return
     if args.calibrate_copy:
         nbytes = 256 << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
