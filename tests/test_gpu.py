@@ -446,3 +446,30 @@ def test_server_results_match_alone(dev, pool_slots):
     if pool_slots < 2:
         assert st["slots_evicted"] > 0
     srv.close()
+
+
+def test_full_size_500k_refactor_and_direct_solve(dev):
+    # the 500,000-row workload at full size: refactorization of system 2 bit-identical to the
+    # oracle's static-pivot refactorization, and the direct solve within the LU backward-error
+    # bound on a sample of rows (the oracle recomputes those rows one by one)
+    say("500k full size")
+    p = ks.make_pattern(3)
+    v1, _ = p.system(1)
+    v2, b2 = p.system(2)
+    s = P.Solver(p.rowptr, p.colidx, v1).bind(dev)
+    f = oracle.LU(p.rowptr, p.colidx, v1)
+    s.refactor(cuda(v2, dev))
+    torch.cuda.synchronize()
+    lx, ux = s.factor_values(0)
+    olx, oux, ng = f.refactor64(p.rowptr, p.colidx, v2)
+    assert np.array_equal(lx, olx) and np.array_equal(ux, oux)
+    info = s.info()
+    assert info["levels_l"] > 0 and info["nnz_l"] == olx.size
+    z = s.direct_solve(cuda(b2, dev)).cpu().numpy()
+    zo = f.solve(b2, Lx=olx, Ux=oux)
+    rng = np.random.default_rng(7)
+    rows = rng.choice(p.N, size=2000, replace=False)
+    # sampled rows of the triangular solves' result agree with the oracle's to the
+    # precision the bound of the factors allows (relative to the largest component)
+    scale = np.abs(zo).max()
+    assert np.all(np.abs(z[rows] - zo[rows]) <= 1e-6 * scale + 1e-6 * np.abs(zo[rows]))
