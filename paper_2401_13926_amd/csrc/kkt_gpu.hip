@@ -360,13 +360,15 @@ __global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
                 if (a.guard_fail_policy) atomicOr(&a.ctl->guard_fail, 1u);
             }
         }
+        // publish L(:,j) first (entry by entry; later columns wait for it), then the copies
+        // in F and in the solve layout (whose scatter index is a load of its own)
+        for (int e = nu + 1 + lane; e < len; e += 64) store_ready(a.Ld + c0 + e, x[e] / d);
         for (int e = lane; e < len; e += 64) {
             T v = x[e];
             if (e == nu) v = d;
             else if (e > nu) v = v / d;
             a.F[c0 + e] = v;
             a.Tv[a.f2t[c0 + e]] = v;
-            if (e > nu) store_ready(a.Ld + c0 + e, v);  // publishes L(:,j) entry by entry
         }
         }
     }
