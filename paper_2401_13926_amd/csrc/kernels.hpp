@@ -40,7 +40,10 @@ struct Control {
     double rinf, xinf;              // max |rho_i|, max |x_i| from the residual kernel
     double h1[kRestartMax + 1];     // first CGS pass coefficients
     double h2[kRestartMax + 1];     // second CGS pass coefficients
-    double g[kRestartMax + 1];      // rotated right-hand side of the least-squares problem
+    double g[kRestartMax + 1];      // g[j]: right-hand side entry j before rotation j is applied
+    double gr[kRestartMax];         // gr[j]: entry j after rotation j (the least-squares rhs); kept
+                                    // apart from g so that no block of the normalization kernel
+                                    // reads a value block 0 rewrites in the same launch
     double cs[kRestartMax], sn[kRestartMax];
     double y[kRestartMax];          // least-squares solution of the cycle
     double H[(kRestartMax + 1) * kRestartMax];  // rotated Hessenberg (upper triangular), column-major
@@ -58,6 +61,7 @@ struct StepRecord {
     int jdone;
     int pad;
     double est;
+    unsigned long long token;  // written last (release): identifies the step the record is for
 };
 
 // Host-visible summary copied back once per cycle.

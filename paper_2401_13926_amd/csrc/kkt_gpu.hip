@@ -81,18 +81,34 @@ template <typename T> __device__ __forceinline__ T load_ready(const T *p, unsign
     using U = typename Bits<T>::U;
     T v = *p;
     if (!is_sentinel(v)) return v;
-    U b;
+    // Four coherent loads in flight, one issued per check: a store is seen about a quarter of
+    // a memory round trip after it lands instead of up to a whole one.
+    const U *q = reinterpret_cast<const U *>(p);
+    U b0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __builtin_amdgcn_s_sleep(1);
+    U b1 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __builtin_amdgcn_s_sleep(1);
+    U b2 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __builtin_amdgcn_s_sleep(1);
+    U b3 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     unsigned int spins = 0;
-    do {
-        __builtin_amdgcn_s_sleep(1);
-        b = __hip_atomic_load(reinterpret_cast<const U *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        if (++spins >= kSpinLimit ||
+    for (;;) {
+        if (b0 != Bits<T>::sent) return __builtin_bit_cast(T, b0);
+        b0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (b1 != Bits<T>::sent) return __builtin_bit_cast(T, b1);
+        b1 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (b2 != Bits<T>::sent) return __builtin_bit_cast(T, b2);
+        b2 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (b3 != Bits<T>::sent) return __builtin_bit_cast(T, b3);
+        b3 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        spins += 4;
+        if (spins >= kSpinLimit ||
             ((spins & 1023u) == 0 && __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
             __hip_atomic_store(hang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return T(0);
         }
-    } while (b == Bits<T>::sent);
-    return __builtin_bit_cast(T, b);
+        __builtin_amdgcn_s_sleep(1);
+    }
 }
 
 // Wave-uniform: lane 0 takes `chunk` consecutive work items from *counter.
@@ -824,7 +840,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j
 // also writes the step's record (stop, hang, estimate) to host memory.
 template <typename T>
 __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j, int restart, T *s1, T *s2,
-                                                            StepRecord *rec) {
+                                                            StepRecord *rec, unsigned long long token) {
     __shared__ double sh[3];
     __shared__ double red[kStreamBlock / 64];
     __shared__ double hsq[1];
@@ -860,7 +876,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j,
             c->cs[j] = cs;
             c->sn[j] = sn;
             c->g[j + 1] = gj1;
-            c->g[j] = cs * gj;
+            c->gr[j] = cs * gj;
             for (int t = 0; t <= j; ++t) c->H[j * (kRestartMax + 1) + t] = col[t];
             c->hn = hn;
             c->est = est;
@@ -876,6 +892,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j,
             __hip_atomic_store(&r->jdone, j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             __hip_atomic_store(&r->hang, c->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             __hip_atomic_store(&r->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&r->token, token, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
     __syncthreads();
@@ -1022,7 +1039,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_xupdate(KrylovArgs a, double *
     const int m = c->jdone;
     if (threadIdx.x == 0) {
         for (int t = m - 1; t >= 0; --t) {
-            double s = c->g[t];
+            double s = c->gr[t];
             for (int u = t + 1; u < m; ++u) {
                 const double prod = c->H[u * (kRestartMax + 1) + t] * y[u];
                 s = s - prod;
@@ -1120,6 +1137,7 @@ struct kkt_handle_s {
     int restart_alloc = 0;
     bool fp64_current = false;  // mixed mode: FP64 factors of the current system exist
     int64_t repivots = 0;       // re-pivoted factorizations so far
+    unsigned long long step_token = 0;  // tag of the last Arnoldi step launched
     // per-launch timing (kkt_set_profiling)
     struct ProfRec {
         int cls;
@@ -1519,13 +1537,29 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
             e0 = prof_begin(h, s);
             k_cgs_pass2<<<G, kStreamBlock, 0, s>>>(ka, j);
             k_cgs_finish<<<G, kStreamBlock, 0, s>>>(ka, j);
-            k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, R, y, z, h->dev_rec);
+            const unsigned long long token = ++h->step_token;
+            k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, R, y, z, h->dev_rec, token);
             prof_end(h, KKT_K_CGS, e0, s);
             KKT_HIP(h, hipGetLastError());
             KKT_HIP(h, hipEventRecord(h->step_ev[j & 1], s));
             if (j == 0) continue;
             KKT_HIP(h, hipEventSynchronize(h->step_ev[(j - 1) & 1]));
-            const StepRecord &rec = h->host_rec[j - 1];
+            // the record of step j - 1 carries the token it was launched with; until it shows,
+            // the slot may still hold an older step's record, so wait for it (bounded, then
+            // fall back to a full synchronization)
+            StepRecord &rec = h->host_rec[j - 1];
+            const unsigned long long want = h->step_token - 1;
+            bool seen = false;
+            for (int spin = 0; spin < (1 << 20) && !seen; ++spin)
+                seen = __atomic_load_n(&rec.token, __ATOMIC_ACQUIRE) == want;
+            if (!seen) {
+                KKT_HIP(h, hipStreamSynchronize(s));
+                seen = __atomic_load_n(&rec.token, __ATOMIC_ACQUIRE) == want;
+                if (!seen) {
+                    h->device_failed = true;
+                    return fail(h, KKT_EDEVICE, "an Arnoldi step record did not arrive");
+                }
+            }
             if (rec.hang) {
                 h->device_failed = true;
                 return fail(h, KKT_EDEVICE, "a dependency wait exceeded its spin limit");

@@ -373,7 +373,7 @@ def test_repivot_recovers_failed_static_pivots(dev):
     s0 = P.Solver(p.rowptr, p.colidx, v1, repivot_cycles=0).bind(dev)
     s0.refactor(cuda(v2, dev))
     _, i0 = s0.solve(cuda(b2, dev), allow_noconv=True)
-    assert i0["converged"] == 0 and i0["repivoted"] == 0
+    assert i0["converged"] == 0 and i0["repivoted"] == 0 and i0["cycles"] == 21
     s = P.Solver(p.rowptr, p.colidx, v1).bind(dev)
     s.refactor(cuda(v2, dev))
     x, info = s.solve(cuda(b2, dev))
@@ -473,3 +473,22 @@ def test_full_size_500k_refactor_and_direct_solve(dev):
     # precision the bound of the factors allows (relative to the largest component)
     scale = np.abs(zo).max()
     assert np.all(np.abs(z[rows] - zo[rows]) <= 1e-6 * scale + 1e-6 * np.abs(zo[rows]))
+
+
+def test_long_refinement_repeatable_bitwise(dev):
+    # 21 restart cycles of FGMRES(10) on a system whose inherited pivots stall the refinement:
+    # every Arnoldi step's stop decision and every sentinel re-arm must agree across blocks, or
+    # repeated solves drift apart (regression test for a race on the rotated right-hand side)
+    say("long refinement repeatable")
+    p = ks.small_kkt(35000, 25000, 5, (-12.0, 12.0))
+    v1, _ = p.system(1)
+    v2, b2 = p.system(2)
+    s = P.Solver(p.rowptr, p.colidx, v1, repivot_cycles=0).bind(dev)
+    out = []
+    for _ in range(3):
+        s.refactor(cuda(v2, dev))
+        x, info = s.solve(cuda(b2, dev), allow_noconv=True)
+        out.append((x.cpu().numpy(), info["iterations"], info["est_resid"]))
+    assert out[0][1] > 100
+    for x, it, est in out[1:]:
+        assert np.array_equal(x, out[0][0]) and it == out[0][1] and est == out[0][2]
