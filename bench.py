@@ -96,11 +96,12 @@ WORKLOADS = {1: ("kkt_single_7k", 10), 2: ("kkt_sequence_60k", 10), 3: ("kkt_seq
              5: ("kkt_sequence_2m", 50)}
 
 
-def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, restart=10):
+def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, restart=10, gram_schmidt=0):
     dev = torch.device("cuda:0")
     v1, _ = systems[0]
     t0 = time.perf_counter()
-    s = P.Solver(pattern.rowptr, pattern.colidx, v1, precision=precision, restart=restart)
+    s = P.Solver(pattern.rowptr, pattern.colidx, v1, precision=precision, restart=restart,
+                 gram_schmidt=gram_schmidt)
     analysis_s = time.perf_counter() - t0
     s.bind(dev)
     vals = [torch.as_tensor(v, device=dev) for v, _ in systems]
@@ -257,6 +258,8 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS),
                     help="workload: 1 (7k, one system), 2 (60k x 20), 3 (500k x 10), 5 (2M x 5)")
     ap.add_argument("--mixed-steps", type=int, default=10)
+    ap.add_argument("--gram-schmidt", choices=["cgs2", "dcgs2"], default="cgs2",
+                    help="Arnoldi orthogonalization: CGS2 (default) or delayed CGS2 (one reduction per step)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -310,12 +313,13 @@ def main():
           file=sys.stderr, flush=True)
 
     wname, restart = WORKLOADS[cfg]
-    r64 = run_gpu(P, torch, pattern, systems, args.steps, args.warmup, P.PREC_FP64, not args.no_profile, restart)
+    gs = P.GS_DCGS2 if args.gram_schmidt == "dcgs2" else P.GS_CGS2
+    r64 = run_gpu(P, torch, pattern, systems, args.steps, args.warmup, P.PREC_FP64, not args.no_profile, restart, gs)
     ai = r64["solver"].info()
     print("fp64 done: %.1f ms/step" % (1e3 * r64["wall"] / args.steps), file=sys.stderr, flush=True)
     rmx = None
     if args.mixed_steps > 0:
-        rmx = run_gpu(P, torch, pattern, systems, args.mixed_steps, 1, P.PREC_MIXED, False, restart)
+        rmx = run_gpu(P, torch, pattern, systems, args.mixed_steps, 1, P.PREC_MIXED, False, restart, gs)
         print("mixed done: %.1f ms/step" % (1e3 * rmx["wall"] / args.mixed_steps), file=sys.stderr, flush=True)
 
     infos = r64["infos"]
@@ -335,7 +339,7 @@ def main():
         "data": "synthetic (seeded KKT generator; the paper's ACTIVSg sequences are not available)",
         "config": {"workload": wname, "N": pattern.N,
                    "nnz": pattern.nnz, "systems": nsys, "restart": restart, "delta_tol": 1e-14,
-                   "nrbe_target": 1e-12, "precision": "fp64"},
+                   "nrbe_target": 1e-12, "precision": "fp64", "gram_schmidt": args.gram_schmidt},
         "p50_ms": percentile(r64["lat"], 50),
         "p99_ms": percentile(r64["lat"], 99),
         "max_nrbe": max(i["nrbe"] for i in infos),

@@ -97,10 +97,20 @@ typedef struct {
                                on the host (ordering kept), rebuilds the schedules in the bound
                                workspace, refactors and solves again; later systems use the new
                                pivot sequence (3).  0: the pivot sequence of system 1 is kept. */
+    int32_t gram_schmidt;   /* KKT_GS_CGS2: two classical Gram-Schmidt passes per Arnoldi step
+                               (Section 2.1, default).  KKT_GS_DCGS2: delayed CGS2, one of the
+                               low-synchronization FGMRES variants Section 2.1 cites (Bielich et
+                               al. 2022): one reduction per step, the second pass and the
+                               normalization of each vector deferred to the next step's
+                               reduction; 2 kernels per step after the triangular solves
+                               instead of 4, the same Krylov basis, and one preconditioner
+                               application more per cycle that converges before its restart */
+    int32_t reserved;
 } kkt_opts_t;
 
 enum { KKT_IR_FGMRES = 0, KKT_IR_RICHARDSON = 1, KKT_IR_ERROR_FGMRES = 2 };
 enum { KKT_RESID_FP64 = 0, KKT_RESID_DD = 1 };
+enum { KKT_GS_CGS2 = 0, KKT_GS_DCGS2 = 1 };
 
 /* Kernel classes reported by kkt_get_kernel_times. */
 enum {

@@ -56,6 +56,8 @@ def lib():
         L.or_refactor64.argtypes = [C.c_void_p, i64p, i32p, f64p, C.c_int, f64p, f64p, i64p, i64p]
         L.or_refactor32.argtypes = [C.c_void_p, i64p, i32p, f64p, C.c_int, f32p, f32p, i64p, i64p]
         L.or_solve_with.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p]
+        L.or_arnoldi.argtypes = [C.c_void_p, f64p, f64p, i64p, i32p, f64p, f64p, C.c_int, C.c_int, f64p,
+                                 f64p, f64p]
         L.or_solve_with32.argtypes = [C.c_void_p, f32p, f32p, f64p, f64p]
         L.or_residual.argtypes = [i64, i64p, i32p, f64p, f64p, f64p, f64p]
         L.or_residual_dd.argtypes = [i64, i64p, i32p, f64p, f64p, f64p, f64p]
@@ -206,13 +208,19 @@ class LU:
         return lib().or_condest(self._h, _p(rp, C.c_int64), _p(v, C.c_double))
 
     def fgmres_ir(self, rowptr, colidx, values, b, Lx=None, Ux=None, Lx32=None, Ux32=None,
-                  restart=10, max_restarts=20, eta=1e-12, mode=0, hist_cap=4096, residual="fp64"):
+                  restart=10, max_restarts=20, eta=1e-12, mode=0, hist_cap=4096, residual="fp64",
+                  gs="cgs2"):
         """FGMRES-IR with these factors as right preconditioner (see or_fgmres_ir);
-        residual="dd" forms every residual in extended precision (or_residual_dd)."""
+        residual="dd" forms every residual in extended precision (or_residual_dd);
+        gs="dcgs2" runs the Arnoldi steps with delayed CGS2 (one reduction per step)."""
         if residual not in ("fp64", "dd"):
             raise ValueError("residual must be 'fp64' or 'dd'")
         if residual == "dd":
             mode = int(mode) | 2
+        if gs not in ("cgs2", "dcgs2"):
+            raise ValueError("gs must be 'cgs2' or 'dcgs2'")
+        if gs == "dcgs2":
+            mode = int(mode) | 4
         rp, ci, v = _csr(rowptr, colidx, values)
         b = np.ascontiguousarray(b, np.float64)
         prec = 1 if Lx32 is not None else 0
@@ -221,7 +229,7 @@ class LU:
         l32 = np.zeros(1, np.float32) if Lx32 is None else np.ascontiguousarray(Lx32, np.float32)
         u32 = np.zeros(1, np.float32) if Ux32 is None else np.ascontiguousarray(Ux32, np.float32)
         x = np.empty(self.n)
-        info = np.zeros(8)
+        info = np.zeros(9)
         hist = np.zeros(hist_cap)
         lib().or_fgmres_ir(self._h, _p(Lx, C.c_double), _p(Ux, C.c_double), _p(l32, C.c_float),
                            _p(u32, C.c_float), prec, _p(rp, C.c_int64), _p(ci, C.c_int32),
@@ -231,7 +239,28 @@ class LU:
         it = int(info[0])
         return x, dict(iters=it, cycles=int(info[1]), nrbe=info[2], rr=info[3],
                        converged=bool(info[4]), nrbe0=info[5], est=info[6], true_resid=info[7],
-                       hist=hist[:min(it, hist_cap)].copy())
+                       applications=int(info[8]), hist=hist[:min(it, hist_cap)].copy())
+
+    def arnoldi(self, rowptr, colidx, values, r0, restart, gs="cgs2", Lx=None, Ux=None):
+        """One FGMRES Arnoldi cycle from r0 run to `restart` steps (see or_arnoldi).
+        Returns (V, Z, Hbar, k): columns of V and Z are basis vectors, Hbar is unrotated."""
+        if gs not in ("cgs2", "dcgs2"):
+            raise ValueError("gs must be 'cgs2' or 'dcgs2'")
+        rp, ci, v = _csr(rowptr, colidx, values)
+        Lx = self.Lx if Lx is None else np.ascontiguousarray(Lx, np.float64)
+        Ux = self.Ux if Ux is None else np.ascontiguousarray(Ux, np.float64)
+        r0 = np.ascontiguousarray(r0, np.float64)
+        R = int(restart)
+        V = np.zeros((R + 1, self.n))
+        Z = np.zeros((R, self.n))
+        H = np.zeros((R, R + 1))
+        k = lib().or_arnoldi(self._h, _p(Lx, C.c_double), _p(Ux, C.c_double), _p(rp, C.c_int64),
+                             _p(ci, C.c_int32), _p(v, C.c_double), _p(r0, C.c_double), R,
+                             1 if gs == "dcgs2" else 0, _p(V, C.c_double), _p(Z, C.c_double),
+                             _p(H, C.c_double))
+        if k < 0:
+            raise MemoryError("or_arnoldi failed")
+        return V.T, Z.T, H.T, k
 
     # step-indexed views (rows of P K Q), used to compare layouts
     def L_step_csc(self):

@@ -20,7 +20,7 @@
  *   or_solve       x = Q U^-1 L^-1 P b (the direct solve, Section 1.3 step 3)
  *   or_residual, or_metrics   rho = b - K x, NRBE (eq. (nbre), Section 2.2), NSR (Section 1.3)
  *   or_condest     Hager/Higham 1-norm condition estimate (published method, Higham 1988)
- *   or_fgmres_ir   FGMRES-IR with the LU factors as right preconditioner, CGS2 Arnoldi,
+ *   or_fgmres_ir   FGMRES-IR with the LU factors as right preconditioner, CGS2 (or delayed CGS2) Arnoldi,
  *                  estimated residual, solution formed only at restart/convergence
  *                  (Section 2.1, stopping tests of Section 2.2, refine decision of 2.3)
  *
@@ -1092,9 +1092,16 @@ double or_condest(const or_lu_t *f, const int64_t *rp, const double *v) {
 /*  mode 1 (paper's test): inner test |g_{j+1}| < eta ||rho0||_2 (RR on the estimated      */
 /*          residual), refine iff ||rho0||/||b|| >= eta, accept when the estimate passes. */
 /*  mode | 2: residuals rho = b - K x in extended precision (or_residual_dd).             */
+/*  mode | 4: delayed CGS2 (DCGS2), one of the low-synchronization variants the paper     */
+/*          cites for FGMRES (Section 2.1; Bielich et al., Parallel Computing 2022): one    */
+/*          reduction per step, the second Gram-Schmidt pass of u_j and its normalization   */
+/*          deferred to step j + 1, where they share the reduction with K M^-1 u_j; the     */
+/*          Hessenberg column, the preconditioned vector and the next vector are corrected  */
+/*          for the deferred pass (see fgmres_cycle_dcgs2).                                  */
 /* precision 0: FP64 factors; 1: FP32 factors (Lx32/Ux32), preconditioner in binary32.    */
 /* info: [0] iterations, [1] cycles, [2] final NRBE, [3] RR (true), [4] converged flag,   */
-/*       [5] NRBE of x0, [6] final estimated residual, [7] final true residual norm       */
+/*       [5] NRBE of x0, [6] final estimated residual, [7] final true residual norm,      */
+/*       [8] preconditioner applications (x0 included)                                    */
 /* ------------------------------------------------------------------------------------ */
 
 static void apply_m(const or_lu_t *f, const double *Lx, const double *Ux, const float *Lx32,
@@ -1115,6 +1122,177 @@ static void matvec(int64_t n, const int64_t *rp, const int32_t *ci, const double
     }
 }
 
+/* Work arrays of one FGMRES(R) run. */
+typedef struct {
+    int64_t n;
+    int R;
+    double *V;   /* R + 1 basis vectors (slot j + 1 holds the next, not yet final, vector) */
+    double *Z;   /* R preconditioned vectors z_j = M^-1 v_j */
+    double *H;   /* rotated Hessenberg, column-major (R + 1) x R: upper triangular */
+    double *Hu;  /* the final Hessenberg columns before rotation, (R + 1) x R */
+    double *cs, *sn, *g, *h, *h2, *c, *sv, *e, *hs, *w;
+} fg_ws_t;
+
+/* Column j of the Hessenberg matrix, col[0..j+1], is complete: apply rotations 0..j-1,
+   choose rotation j to annihilate col[j+1], rotate g, store the column.  Returns the
+   estimated residual |g[j+1]|. */
+static double givens_close(fg_ws_t *ws, int j, double *col) {
+    double *cs = ws->cs, *sn = ws->sn, *g = ws->g;
+    for (int t = 0; t < j; t++) {
+        double a = col[t], bb = col[t + 1];
+        col[t] = cs[t] * a + sn[t] * bb;
+        col[t + 1] = -sn[t] * a + cs[t] * bb;
+    }
+    double a = col[j], bb = col[j + 1];
+    double rr = hypot(a, bb);
+    if (rr == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+    } else {
+        cs[j] = a / rr;
+        sn[j] = bb / rr;
+    }
+    col[j] = rr;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    for (int t = 0; t <= j; t++) ws->H[(size_t)j * (ws->R + 1) + t] = col[t];
+    return fabs(g[j + 1]);
+}
+
+static double dot(int64_t n, const double *a, const double *b) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) s += a[i] * b[i];
+    return s;
+}
+
+/* One FGMRES cycle with CGS2 (V[0] and g already set): for j = 0, 1, ...: z_j = M^-1 v_j,
+   w = K z_j, two classical Gram-Schmidt passes against v_0..v_j, h_{j+1,j} = ||w||, rotation,
+   estimate; stop on the inner tolerance, a breakdown (h_{j+1,j} <= 1e-14 ||K z_j||) or after
+   R steps.  Returns the number of Hessenberg columns (steps) completed. */
+static int fgmres_cycle_cgs2(fg_ws_t *ws, const or_lu_t *f, const double *Lx, const double *Ux,
+                             const float *Lx32, const float *Ux32, int precision, const int64_t *rp,
+                             const int32_t *ci, const double *v, double inner_tol, double *est,
+                             long *applications, double *hist, int64_t *nh, int64_t hist_cap) {
+    const int64_t n = ws->n;
+    const int R = ws->R;
+    double *V = ws->V, *Z = ws->Z, *h = ws->h, *h2 = ws->h2, *w = ws->w;
+    int jdone = 0;
+    for (int j = 0; j < R; j++) {
+        double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+        apply_m(f, Lx, Ux, Lx32, Ux32, precision, vj, zj);
+        (*applications)++;
+        matvec(n, rp, ci, v, zj, w);
+        double win = nrm2(n, w);
+        for (int t = 0; t <= j; t++) h[t] = 0.0;
+        for (int pass = 0; pass < 2; pass++) {
+            for (int t = 0; t <= j; t++) h2[t] = dot(n, V + (size_t)t * n, w);
+            for (int t = 0; t <= j; t++) {
+                const double *vt = V + (size_t)t * n;
+                for (int64_t i = 0; i < n; i++) w[i] -= h2[t] * vt[i];
+                h[t] += h2[t];
+            }
+        }
+        double hn = nrm2(n, w);
+        h[j + 1] = hn;
+        for (int t = 0; t <= j + 1; t++) ws->Hu[(size_t)j * (ws->R + 1) + t] = h[t];
+        *est = givens_close(ws, j, h);
+        jdone = j + 1;
+        if (hist && *nh < hist_cap) hist[(*nh)++] = *est;
+        int breakdown = !(hn > 1e-14 * win);
+        if (!breakdown)
+            for (int64_t i = 0; i < n; i++) V[(size_t)(j + 1) * n + i] = w[i] / hn;
+        if (*est <= inner_tol || breakdown) break;
+    }
+    return jdone;
+}
+
+/* One FGMRES cycle with delayed CGS2 (V[0] and g already set).  Step j works on u_j, the
+   vector after one Gram-Schmidt pass (u_0 = v_0, already final):
+     z~ = M^-1 u_j, w = K z~                               (none at j = R)
+     one reduction: s_t = v_t.u_j, c_t = v_t.w (t < j), alpha = u_j.u_j, d = u_j.w
+     j > 0: second pass of u_j: beta = sqrt(alpha - |s|^2), v_j = (u_j - V s) / beta, so
+            column j-1 becomes final: (p + s, beta) with p its one-pass part; rotation,
+            estimate, stop test (inner tolerance, breakdown beta <= 1e-14 |column|, j = R)
+     z_j = (z~ - Z s) / beta = M^-1 v_j  (M^-1 is linear)
+     K z_j = (w - K Z s) / beta = (w - V Hu s) / beta  (Arnoldi relation K Z = V Hu), so with
+     e = V_{0..j}^T w (e_t = c_t for t < j, e_j = (d - s.c) / beta) the one-pass column j is
+     p = (e - Hu s) / beta and u_{j+1} = K z_j - V p = (w - V e) / beta.
+   beta = 1 and s = () at j = 0.  In absolute size s_t beta and s.c / beta are of the order
+   of rounding (u ||K z||), like the second-pass coefficients of CGS2; the terms divided by
+   the small beta (V s, Z s, Hu s) are what keep V orthonormal and K Z = V Hu.
+   Returns the number of final columns. */
+static int fgmres_cycle_dcgs2(fg_ws_t *ws, const or_lu_t *f, const double *Lx, const double *Ux,
+                              const float *Lx32, const float *Ux32, int precision, const int64_t *rp,
+                              const int32_t *ci, const double *v, double inner_tol, double *est,
+                              long *applications, double *hist, int64_t *nh, int64_t hist_cap) {
+    const int64_t n = ws->n;
+    const int R = ws->R;
+    double *V = ws->V, *Z = ws->Z, *Hu = ws->Hu, *w = ws->w;
+    double *p = ws->h, *col = ws->h2, *c = ws->c, *sv = ws->sv, *e = ws->e, *hs = ws->hs;
+    int jdone = 0;
+    for (int j = 0; j <= R; j++) {
+        double *uj = V + (size_t)j * n;
+        double *zj = Z + (size_t)j * n;
+        const int have_w = j < R;
+        if (have_w) {
+            apply_m(f, Lx, Ux, Lx32, Ux32, precision, uj, zj);
+            (*applications)++;
+            matvec(n, rp, ci, v, zj, w);
+        }
+        for (int t = 0; t < j; t++) {
+            sv[t] = dot(n, V + (size_t)t * n, uj);
+            if (have_w) c[t] = dot(n, V + (size_t)t * n, w);
+        }
+        double alpha = dot(n, uj, uj);
+        double d = have_w ? dot(n, uj, w) : 0.0;
+        double beta = 1.0;
+        if (j > 0) {
+            double ss = 0.0;
+            for (int t = 0; t < j; t++) ss += sv[t] * sv[t];
+            beta = alpha - ss > 0.0 ? sqrt(alpha - ss) : 0.0;
+            for (int t = 0; t < j; t++) col[t] = p[t] + sv[t];
+            col[j] = beta;
+            double cn = 0.0;
+            for (int t = 0; t <= j; t++) cn += col[t] * col[t];
+            cn = sqrt(cn);
+            for (int t = 0; t <= j; t++) Hu[(size_t)(j - 1) * (R + 1) + t] = col[t];
+            *est = givens_close(ws, j - 1, col);
+            jdone = j;
+            if (hist && *nh < hist_cap) hist[(*nh)++] = *est;
+            int breakdown = !(beta > 1e-14 * cn);
+            if (*est <= inner_tol || breakdown || j == R) break;
+            for (int64_t i = 0; i < n; i++) {
+                double a = uj[i], b2 = zj[i];
+                for (int t = 0; t < j; t++) {
+                    a -= V[(size_t)t * n + i] * sv[t];
+                    b2 -= Z[(size_t)t * n + i] * sv[t];
+                }
+                uj[i] = a / beta;
+                zj[i] = b2 / beta;
+            }
+        }
+        double sc = 0.0;
+        for (int t = 0; t < j; t++) {
+            e[t] = c[t];
+            sc += sv[t] * c[t];
+        }
+        e[j] = (d - sc) / beta;
+        for (int t = 0; t <= j; t++) {
+            hs[t] = 0.0;
+            for (int k = 0; k < j; k++) hs[t] += Hu[(size_t)k * (R + 1) + t] * sv[k];
+            p[t] = (e[t] - hs[t]) / beta;
+        }
+        double *un = V + (size_t)(j + 1) * n;
+        for (int64_t i = 0; i < n; i++) {
+            double a = w[i];
+            for (int t = 0; t <= j; t++) a -= V[(size_t)t * n + i] * e[t];
+            un[i] = a / beta;
+        }
+    }
+    return jdone;
+}
+
 int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const float *Lx32,
                  const float *Ux32, int precision, const int64_t *rp, const int32_t *ci,
                  const double *v, const double *b, double *x, int restart, int max_restarts,
@@ -1122,126 +1300,148 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
     int64_t n = f->n;
     int R = restart;
     if (R < 1) return OR_EINVAL;
-    double *V = (double *)malloc((size_t)n * (R + 1) * sizeof(double));
-    double *Z = (double *)malloc((size_t)n * R * sizeof(double));
-    double *H = (double *)calloc((size_t)(R + 1) * R, sizeof(double)); /* column-major (R+1) x R */
-    double *cs = (double *)malloc((size_t)R * sizeof(double));
-    double *sn = (double *)malloc((size_t)R * sizeof(double));
-    double *g = (double *)malloc((size_t)(R + 1) * sizeof(double));
-    double *h = (double *)malloc((size_t)(R + 1) * sizeof(double));
-    double *h2 = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    fg_ws_t ws;
+    ws.n = n;
+    ws.R = R;
+    ws.V = (double *)malloc((size_t)n * (R + 1) * sizeof(double));
+    ws.Z = (double *)malloc((size_t)n * R * sizeof(double));
+    ws.H = (double *)calloc((size_t)(R + 1) * R, sizeof(double));
+    ws.Hu = (double *)calloc((size_t)(R + 1) * R, sizeof(double));
+    ws.cs = (double *)malloc((size_t)R * sizeof(double));
+    ws.sn = (double *)malloc((size_t)R * sizeof(double));
+    ws.g = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    ws.h = (double *)malloc((size_t)(R + 2) * sizeof(double));
+    ws.h2 = (double *)malloc((size_t)(R + 2) * sizeof(double));
+    ws.c = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    ws.sv = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    ws.e = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    ws.hs = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    ws.w = (double *)malloc((size_t)n * sizeof(double));
     double *yv = (double *)malloc((size_t)R * sizeof(double));
     double *r = (double *)malloc((size_t)n * sizeof(double));
-    double *w = (double *)malloc((size_t)n * sizeof(double));
-    if (!V || !Z || !H || !cs || !sn || !g || !h || !h2 || !yv || !r || !w) {
-        free(V); free(Z); free(H); free(cs); free(sn); free(g); free(h); free(h2); free(yv);
-        free(r); free(w);
-        return OR_ENOMEM;
-    }
-    int64_t nh = 0;
-    void (*resid)(int64_t, const int64_t *, const int32_t *, const double *, const double *, const double *,
-                  double *) = (mode & 2) ? or_residual_dd : or_residual;
-    mode &= 1;
-    double kn = or_norm_inf_mat(n, rp, v);
-    double bn = nrm2(n, b);
-    apply_m(f, Lx, Ux, Lx32, Ux32, precision, b, x);
-    resid(n, rp, ci, v, x, b, r);
-    double rho0 = nrm2(n, r);
-    double rn = rho0;
-    double nrbe = rn / (kn * nrm2(n, x) + bn);
-    info[5] = nrbe;
-    int iters = 0, cycles = 0, converged = 0;
-    double est = rn;
-    if (mode == 0 ? (nrbe <= eta) : (rn / bn < eta)) converged = 1;
-    while (!converged && cycles <= max_restarts) {
-        cycles++;
-        double beta = rn;
-        if (!(beta > 0.0)) {
-            converged = 1;
-            break;
-        }
-        double xn = nrm2(n, x);
-        double inner_tol = mode == 0 ? eta * (kn * xn + bn) : eta * rho0;
-        for (int64_t i = 0; i < n; i++) V[i] = r[i] / beta;
-        for (int t = 0; t <= R; t++) g[t] = 0.0;
-        g[0] = beta;
-        int jdone = 0;
-        for (int j = 0; j < R; j++) {
-            double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
-            apply_m(f, Lx, Ux, Lx32, Ux32, precision, vj, zj);
-            matvec(n, rp, ci, v, zj, w);
-            double win = nrm2(n, w);
-            /* CGS2: two classical Gram-Schmidt passes against v_0..v_j */
-            for (int t = 0; t <= j; t++) h[t] = 0.0;
-            for (int pass = 0; pass < 2; pass++) {
-                for (int t = 0; t <= j; t++) {
-                    const double *vt = V + (size_t)t * n;
-                    double s = 0.0;
-                    for (int64_t i = 0; i < n; i++) s += vt[i] * w[i];
-                    h2[t] = s;
-                }
-                for (int t = 0; t <= j; t++) {
-                    const double *vt = V + (size_t)t * n;
-                    for (int64_t i = 0; i < n; i++) w[i] -= h2[t] * vt[i];
-                    h[t] += h2[t];
-                }
-            }
-            double hn = nrm2(n, w);
-            h[j + 1] = hn;
-            /* previous rotations, then a new one annihilating h[j+1] */
-            for (int t = 0; t < j; t++) {
-                double a = h[t], bb = h[t + 1];
-                h[t] = cs[t] * a + sn[t] * bb;
-                h[t + 1] = -sn[t] * a + cs[t] * bb;
-            }
-            double a = h[j], bb = h[j + 1];
-            double rr = hypot(a, bb);
-            if (rr == 0.0) {
-                cs[j] = 1.0;
-                sn[j] = 0.0;
-            } else {
-                cs[j] = a / rr;
-                sn[j] = bb / rr;
-            }
-            h[j] = rr;
-            h[j + 1] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            for (int t = 0; t <= j; t++) H[(size_t)j * (R + 1) + t] = h[t];
-            iters++;
-            jdone = j + 1;
-            est = fabs(g[j + 1]);
-            if (hist && nh < hist_cap) hist[nh++] = est;
-            int breakdown = !(hn > 1e-14 * win);
-            if (!breakdown)
-                for (int64_t i = 0; i < n; i++) V[(size_t)(j + 1) * n + i] = w[i] / hn;
-            if (est <= inner_tol || breakdown) break;
-        }
-        /* y = H^-1 g (upper triangular, jdone x jdone), then x += Z y */
-        for (int t = jdone - 1; t >= 0; t--) {
-            double s = g[t];
-            for (int u = t + 1; u < jdone; u++) s -= H[(size_t)u * (R + 1) + t] * yv[u];
-            yv[t] = s / H[(size_t)t * (R + 1) + t];
-        }
-        for (int t = 0; t < jdone; t++) {
-            const double *zt = Z + (size_t)t * n;
-            for (int64_t i = 0; i < n; i++) x[i] += yv[t] * zt[i];
-        }
+    int ok = ws.V && ws.Z && ws.H && ws.Hu && ws.cs && ws.sn && ws.g && ws.h && ws.h2 && ws.c &&
+             ws.sv && ws.e && ws.hs && ws.w && yv && r;
+    int status = OR_ENOMEM;
+    if (ok) {
+        double *V = ws.V, *Z = ws.Z, *H = ws.H, *g = ws.g;
+        int64_t nh = 0;
+        long applications = 0;
+        void (*resid)(int64_t, const int64_t *, const int32_t *, const double *, const double *,
+                      const double *, double *) = (mode & 2) ? or_residual_dd : or_residual;
+        const int dcgs2 = (mode & 4) != 0;
+        mode &= 1;
+        double kn = or_norm_inf_mat(n, rp, v);
+        double bn = nrm2(n, b);
+        apply_m(f, Lx, Ux, Lx32, Ux32, precision, b, x);
+        applications++;
         resid(n, rp, ci, v, x, b, r);
-        rn = nrm2(n, r);
-        nrbe = rn / (kn * nrm2(n, x) + bn);
-        if (mode == 0 ? (nrbe <= eta) : (est < eta * rho0)) converged = 1;
+        double rho0 = nrm2(n, r);
+        double rn = rho0;
+        double nrbe = rn / (kn * nrm2(n, x) + bn);
+        info[5] = nrbe;
+        int iters = 0, cycles = 0, converged = 0;
+        double est = rn;
+        if (mode == 0 ? (nrbe <= eta) : (rn / bn < eta)) converged = 1;
+        while (!converged && cycles <= max_restarts) {
+            cycles++;
+            double beta = rn;
+            if (!(beta > 0.0)) {
+                converged = 1;
+                break;
+            }
+            double xn = nrm2(n, x);
+            double inner_tol = mode == 0 ? eta * (kn * xn + bn) : eta * rho0;
+            for (int64_t i = 0; i < n; i++) V[i] = r[i] / beta;
+            for (int t = 0; t <= R; t++) g[t] = 0.0;
+            g[0] = beta;
+            int jdone;
+            if (dcgs2)
+                jdone = fgmres_cycle_dcgs2(&ws, f, Lx, Ux, Lx32, Ux32, precision, rp, ci, v, inner_tol,
+                                           &est, &applications, hist, &nh, hist_cap);
+            else
+                jdone = fgmres_cycle_cgs2(&ws, f, Lx, Ux, Lx32, Ux32, precision, rp, ci, v, inner_tol,
+                                          &est, &applications, hist, &nh, hist_cap);
+            iters += jdone;
+            /* y = H^-1 g (upper triangular, jdone x jdone), then x += Z y */
+            for (int t = jdone - 1; t >= 0; t--) {
+                double s = g[t];
+                for (int u = t + 1; u < jdone; u++) s -= H[(size_t)u * (R + 1) + t] * yv[u];
+                yv[t] = s / H[(size_t)t * (R + 1) + t];
+            }
+            for (int t = 0; t < jdone; t++) {
+                const double *zt = Z + (size_t)t * n;
+                for (int64_t i = 0; i < n; i++) x[i] += yv[t] * zt[i];
+            }
+            resid(n, rp, ci, v, x, b, r);
+            rn = nrm2(n, r);
+            nrbe = rn / (kn * nrm2(n, x) + bn);
+            if (mode == 0 ? (nrbe <= eta) : (est < eta * rho0)) converged = 1;
+        }
+        info[0] = iters;
+        info[1] = cycles;
+        info[2] = nrbe;
+        info[3] = rho0 > 0.0 ? rn / rho0 : 0.0;
+        info[4] = converged;
+        info[6] = est;
+        info[7] = rn;
+        info[8] = (double)applications;
+        status = converged ? OR_OK : 4;
     }
-    info[0] = iters;
-    info[1] = cycles;
-    info[2] = nrbe;
-    info[3] = rho0 > 0.0 ? rn / rho0 : 0.0;
-    info[4] = converged;
-    info[6] = est;
-    info[7] = rn;
-    free(V); free(Z); free(H); free(cs); free(sn); free(g); free(h); free(h2); free(yv);
-    free(r); free(w);
-    return converged ? OR_OK : 4;
+    free(ws.V); free(ws.Z); free(ws.H); free(ws.Hu); free(ws.cs); free(ws.sn); free(ws.g);
+    free(ws.h); free(ws.h2); free(ws.c); free(ws.sv); free(ws.e); free(ws.hs); free(ws.w);
+    free(yv); free(r);
+    return status;
+}
+
+/* One Arnoldi cycle of FGMRES(R) from r0 with the preconditioner M = (Lx, Ux), run to R
+   steps (or a breakdown), returning the basis V (n x (R+1)), Z = M^-1 V (n x R) and the
+   Hessenberg matrix before rotation (column-major (R+1) x R) so that tests can check the
+   Arnoldi relation K Z_k = V_{k+1} Hbar_k and the orthonormality of V.  gs: 0 CGS2, 1 DCGS2
+   (whose last vector, v_k, is left after its first pass: the relation holds for k - 1
+   columns).  Returns k, the number of Hessenberg columns, or -1 on error. */
+int or_arnoldi(const or_lu_t *f, const double *Lx, const double *Ux, const int64_t *rp, const int32_t *ci,
+               const double *v, const double *r0, int R, int gs, double *Vout, double *Zout,
+               double *Hout) {
+    const int64_t n = f->n;
+    if (R < 1) return -1;
+    fg_ws_t ws;
+    ws.n = n;
+    ws.R = R;
+    ws.V = Vout;
+    ws.Z = Zout;
+    ws.Hu = Hout;
+    ws.H = (double *)calloc((size_t)(R + 1) * R, sizeof(double));
+    ws.cs = (double *)malloc((size_t)R * sizeof(double));
+    ws.sn = (double *)malloc((size_t)R * sizeof(double));
+    ws.g = (double *)calloc((size_t)(R + 1), sizeof(double));
+    ws.h = (double *)malloc((size_t)(R + 2) * sizeof(double));
+    ws.h2 = (double *)malloc((size_t)(R + 2) * sizeof(double));
+    ws.c = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    ws.sv = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    ws.e = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    ws.hs = (double *)malloc((size_t)(R + 1) * sizeof(double));
+    ws.w = (double *)malloc((size_t)n * sizeof(double));
+    int k = -1;
+    if (ws.H && ws.cs && ws.sn && ws.g && ws.h && ws.h2 && ws.c && ws.sv && ws.e && ws.hs && ws.w) {
+        memset(Vout, 0, (size_t)n * (R + 1) * sizeof(double));
+        memset(Zout, 0, (size_t)n * R * sizeof(double));
+        memset(Hout, 0, (size_t)(R + 1) * R * sizeof(double));
+        double beta = nrm2(n, r0);
+        for (int64_t i = 0; i < n; i++) Vout[i] = r0[i] / beta;
+        ws.g[0] = beta;
+        double est = beta;
+        long applications = 0;
+        int64_t nh = 0;
+        if (gs == 1)
+            k = fgmres_cycle_dcgs2(&ws, f, Lx, Ux, NULL, NULL, 0, rp, ci, v, 0.0, &est, &applications,
+                                   NULL, &nh, 0);
+        else
+            k = fgmres_cycle_cgs2(&ws, f, Lx, Ux, NULL, NULL, 0, rp, ci, v, 0.0, &est, &applications,
+                                  NULL, &nh, 0);
+    }
+    free(ws.H); free(ws.cs); free(ws.sn); free(ws.g); free(ws.h); free(ws.h2); free(ws.c);
+    free(ws.sv); free(ws.e); free(ws.hs); free(ws.w);
+    return k;
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -1279,10 +1479,10 @@ int or_richardson(const or_lu_t *f, const double *Lx, const double *Ux, const in
     int it = 0, converged = rn < tol * rho0;
     while (!converged && it < max_it) {
         if (inner_restart > 0) {
-            double inner[8];
+            double inner[9];
             or_fgmres_ir(f, Lx, Ux, NULL, NULL, 0, rp, ci, v, r, d, inner_restart, 0, inner_tol, 1, inner,
                          NULL, 0);
-            applications += 1 + (long)inner[0];
+            applications += (long)inner[8];
         } else {
             or_solve_with(f, Lx, Ux, r, d);
             applications += 1;

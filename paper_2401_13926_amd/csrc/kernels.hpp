@@ -47,6 +47,8 @@ struct Control {
     double cs[kRestartMax], sn[kRestartMax];
     double y[kRestartMax];          // least-squares solution of the cycle
     double H[(kRestartMax + 1) * kRestartMax];  // rotated Hessenberg (upper triangular), column-major
+    double Hbar[(kRestartMax + 1) * kRestartMax];  // DCGS2: final columns before rotation
+    double hp[2][kRestartMax + 1];  // DCGS2: one-pass column j in hp[j & 1] (read by step j + 1)
     unsigned int work_refactor;     // next column-order index to hand out (refactorization)
     unsigned int work_lower;        // next task index to hand out (L solve)
     unsigned int work_upper;        // next task index to hand out (U solve)

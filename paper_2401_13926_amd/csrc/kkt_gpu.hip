@@ -700,7 +700,7 @@ __global__ void k_fill_sentinel(int64_t n, T *a, T *b, Control *ctl) {
 // rotate so a kernel never overwrites the partials it is reading.
 // ---------------------------------------------------------------------------------------
 
-constexpr int kPartStride = kRestartMax + 4;
+constexpr int kPartStride = 2 * kRestartMax + 4;  // room for the 2 (j + 1) dots of a DCGS2 step
 
 struct KrylovArgs {
     int64_t n;
@@ -833,11 +833,61 @@ __global__ void __launch_bounds__(kStreamBlock) k_cgs_finish(KrylovArgs a, int j
     if (threadIdx.x == 0) partbuf(a, 2)[(int64_t)blockIdx.x * kPartStride] = ss;
 }
 
-// hn = ||w|| (reduce buffer 2); Hessenberg column h1 + h2, previous rotations, a new
-// Givens rotation, the estimated residual |g_{j+1}| and the stop test -- computed
-// identically in every block (only block 0 stores them); then v_{j+1} = w / hn unless the
-// step broke down, and the solve sentinels are re-armed when the cycle goes on.  Block 0
-// also writes the step's record (stop, hang, estimate) to host memory.
+// Closes Arnoldi column j (thread 0 of every block, identical results): col[0..j] are the
+// Gram-Schmidt coefficients, hn the new subdiagonal entry; applies the previous rotations
+// and a new Givens rotation, forms the estimated residual |g_{j+1}| and the stop test.
+// Block 0 stores the column, rotation, right-hand side and the host record r of the step.  Every
+// value another block reads here (g[j], cs, sn, inner_tol) is left untouched in this launch.
+// sh receives hn, breakdown, stop.
+__device__ void arnoldi_close(Control *c, int j, int restart, double hn, double wnorm_in, double *col,
+                              StepRecord *r, unsigned long long token, double *sh) {
+    col[j + 1] = hn;
+    for (int t = 0; t < j; ++t) {
+        const double x0 = col[t], x1 = col[t + 1];
+        col[t] = c->cs[t] * x0 + c->sn[t] * x1;
+        col[t + 1] = -c->sn[t] * x0 + c->cs[t] * x1;
+    }
+    const double rr = hypot(col[j], col[j + 1]);
+    double cs = 1.0, sn = 0.0;
+    if (rr != 0.0) {
+        cs = col[j] / rr;
+        sn = col[j + 1] / rr;
+    }
+    col[j] = rr;
+    const double gj = c->g[j];
+    const double gj1 = -sn * gj;
+    const double est = fabs(gj1);
+    const int brk = !(hn > 1e-14 * wnorm_in);
+    const int stop = est <= c->inner_tol || brk || j + 1 >= restart;
+    sh[0] = hn;
+    sh[1] = brk;
+    sh[2] = stop;
+    if (blockIdx.x == 0) {
+        c->cs[j] = cs;
+        c->sn[j] = sn;
+        c->g[j + 1] = gj1;
+        c->gr[j] = cs * gj;
+        for (int t = 0; t <= j; ++t) c->H[j * (kRestartMax + 1) + t] = col[t];
+        c->hn = hn;
+        c->est = est;
+        c->jdone = j + 1;
+        c->breakdown = brk;
+        c->stop = stop;
+        if (!stop) {
+            c->work_lower = 0;
+            c->work_upper = 0;
+        }
+        __hip_atomic_store(&r->est, est, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->jdone, j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->hang, c->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->token, token, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// hn = ||w|| (reduce buffer 2); Hessenberg column h1 + h2, rotation and stop test
+// (arnoldi_close); then v_{j+1} = w / hn unless the step broke down, and the solve
+// sentinels are re-armed when the cycle goes on.
 template <typename T>
 __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j, int restart, T *s1, T *s2,
                                                             StepRecord *rec, unsigned long long token) {
@@ -848,52 +898,9 @@ __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j,
     if (c->stop) return;
     reduce_cols(partbuf(a, 2), gridDim.x, 1, hsq, red);
     if (threadIdx.x == 0) {
-        const double hn = sqrt(hsq[0]);
         double col[kRestartMax + 1];
         for (int t = 0; t <= j; ++t) col[t] = c->h1[t] + c->h2[t];
-        col[j + 1] = hn;
-        for (int t = 0; t < j; ++t) {
-            const double x0 = col[t], x1 = col[t + 1];
-            col[t] = c->cs[t] * x0 + c->sn[t] * x1;
-            col[t + 1] = -c->sn[t] * x0 + c->cs[t] * x1;
-        }
-        const double rr = hypot(col[j], col[j + 1]);
-        double cs = 1.0, sn = 0.0;
-        if (rr != 0.0) {
-            cs = col[j] / rr;
-            sn = col[j + 1] / rr;
-        }
-        col[j] = rr;
-        const double gj = c->g[j];
-        const double gj1 = -sn * gj;
-        const double est = fabs(gj1);
-        const int brk = !(hn > 1e-14 * c->wnorm_in);
-        const int stop = est <= c->inner_tol || brk || j + 1 >= restart;
-        sh[0] = hn;
-        sh[1] = brk;
-        sh[2] = stop;
-        if (blockIdx.x == 0) {
-            c->cs[j] = cs;
-            c->sn[j] = sn;
-            c->g[j + 1] = gj1;
-            c->gr[j] = cs * gj;
-            for (int t = 0; t <= j; ++t) c->H[j * (kRestartMax + 1) + t] = col[t];
-            c->hn = hn;
-            c->est = est;
-            c->jdone = j + 1;
-            c->breakdown = brk;
-            c->stop = stop;
-            if (!stop) {
-                c->work_lower = 0;
-                c->work_upper = 0;
-            }
-            StepRecord *r = rec + j;
-            __hip_atomic_store(&r->est, est, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&r->jdone, j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&r->hang, c->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&r->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&r->token, token, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+        arnoldi_close(c, j, restart, sqrt(hsq[0]), c->wnorm_in, col, rec + j, token, sh);
     }
     __syncthreads();
     const double hn = sh[0];
@@ -907,6 +914,151 @@ __global__ void __launch_bounds__(kStreamBlock) k_normalize(KrylovArgs a, int j,
             s1[i] = sentinel<T>();
             s2[i] = sentinel<T>();
         }
+    }
+}
+
+// Delayed CGS2 (Bielich et al., Parallel Computing 2022), one of the low-synchronization
+// FGMRES variants of Section 2.1: one global reduction per Arnoldi step.  Step j works on u_j,
+// the vector left by one Gram-Schmidt pass (V slot j; u_0 = v_0 is final).  Its second pass
+// and normalization are deferred to step j and share the reduction with w = K M^-1 u_j:
+//   s_t = v_t.u_j, c_t = v_t.w (t < j), alpha = u_j.u_j, d = u_j.w
+//   beta = sqrt(alpha - |s|^2), v_j = (u_j - V s) / beta: column j - 1 becomes final,
+//     (p + s, beta) with p its one-pass part, and is rotated and tested (arnoldi_close)
+//   z_j = (M^-1 u_j - Z s) / beta = M^-1 v_j
+//   K z_j = (w - V Hbar s) / beta by the Arnoldi relation K Z = V Hbar, so with
+//     e = V^T w (e_t = c_t, e_j = (d - s.c) / beta) the next one-pass column is
+//     p = (e - Hbar s) / beta and u_{j+1} = (w - V e) / beta.
+// beta = 1 and s = () at j = 0; the closing step j = R only finishes column R - 1.
+// The estimate of column j - 1 is thus known one preconditioner application later than
+// with CGS2, so a cycle that converges spends one application more.
+
+// w = K z_j (when matvec); partials (buffer 0): V_t . w at t and V_t . u_j at j + 1 + t, t <= j
+__global__ void __launch_bounds__(kStreamBlock) k_dcgs2_dots(KrylovArgs a, int j, int matvec) {
+    __shared__ double red[(2 * kRestartMax + 4) * (kStreamBlock / 64)];
+    if (a.ctl->stop) return;
+    int64_t r0, r1;
+    block_rows(a.n, r0, r1);
+    if (matvec) {
+        const double *z = a.Z + (int64_t)j * a.n;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            double s = 0.0;
+            for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+                const double prod = a.kval[p] * z[a.ci[p]];
+                s = s + prod;
+            }
+            a.w[i] = s;
+        }
+    }
+    __syncthreads();
+    const double *u = a.V + (int64_t)j * a.n;
+    for (int t = 0; t <= j; ++t) {
+        const double *v = a.V + (int64_t)t * a.n;
+        double sw = 0.0, su = 0.0;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            const double vi = v[i];
+            if (matvec) sw += vi * a.w[i];
+            su += vi * u[i];
+        }
+        block_col_put(sw, t, red);
+        block_col_put(su, j + 1 + t, red);
+    }
+    __syncthreads();
+    double *out = partbuf(a, 0) + (int64_t)blockIdx.x * kPartStride;
+    for (int t = threadIdx.x; t < 2 * (j + 1); t += blockDim.x) out[t] = block_col_get(red, t);
+}
+
+// The rest of DCGS2 step j (see above): every block reduces the partials and forms the same
+// scalars in thread 0; block 0 stores the final column j - 1 (before rotation, in Hbar; and
+// rotated, in H), the one-pass column j (in hp[j & 1], read by the next step, so that no
+// block reads what block 0 writes in this launch) and the step's host record.  Then
+// v_j, z_j and u_{j+1} are formed in one pass over V and Z, and the solve sentinels re-armed.
+template <typename T>
+__global__ void __launch_bounds__(kStreamBlock) k_dcgs2(KrylovArgs a, int j, int restart, T *s1, T *s2,
+                                                        StepRecord *rec, unsigned long long token) {
+    __shared__ double red[(2 * kRestartMax + 4) * (kStreamBlock / 64)];
+    __shared__ double cw[2 * kRestartMax + 2];  // c_t (t < j), d at j; s_t at j + 1 + t, alpha at 2j + 1
+    __shared__ double sh[5];                    // hn, breakdown, stop (arnoldi_close); beta, e_j
+    Control *c = a.ctl;
+    if (c->stop) return;
+    reduce_cols(partbuf(a, 0), gridDim.x, 2 * (j + 1), cw, red);
+    if (threadIdx.x == 0) {
+        const double *sv = cw + j + 1;
+        double beta = 1.0;
+        sh[2] = 0.0;
+        double fin[kRestartMax + 2];  // final column j - 1 before rotation
+        if (j > 0) {
+            double ss = 0.0;
+            for (int t = 0; t < j; ++t) ss += sv[t] * sv[t];
+            const double d2 = sv[j] - ss;
+            beta = d2 > 0.0 ? sqrt(d2) : 0.0;
+            const double *p = c->hp[(j - 1) & 1];
+            double cn = 0.0;
+            for (int t = 0; t < j; ++t) fin[t] = p[t] + sv[t];
+            fin[j] = beta;
+            for (int t = 0; t <= j; ++t) cn += fin[t] * fin[t];
+            double col[kRestartMax + 2];
+            for (int t = 0; t <= j; ++t) col[t] = fin[t];
+            if (blockIdx.x == 0)
+                for (int t = 0; t <= j; ++t) c->Hbar[(j - 1) * (kRestartMax + 1) + t] = fin[t];
+            arnoldi_close(c, j - 1, restart, beta, sqrt(cn), col, rec + j, token, sh);
+        } else if (blockIdx.x == 0) {
+            c->work_lower = 0;
+            c->work_upper = 0;
+            StepRecord *r = rec;
+            __hip_atomic_store(&r->est, c->est, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&r->jdone, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&r->hang, c->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&r->stop, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&r->token, token, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        sh[3] = beta;
+        if (sh[2] == 0.0) {
+            // one-pass column j: p = (e - Hbar s) / beta, Hbar's columns 0..j-2 from earlier
+            // steps and column j - 1 from fin
+            double sc = 0.0;
+            for (int t = 0; t < j; ++t) sc += sv[t] * cw[t];
+            const double ej = (cw[j] - sc) / beta;
+            sh[4] = ej;
+            if (blockIdx.x == 0) {
+                double *pn = c->hp[j & 1];
+                for (int t = 0; t <= j; ++t) {
+                    double hs = 0.0;
+                    for (int k = 0; k < j; ++k) {
+                        const double hk = k == j - 1 ? fin[t] : (t <= k + 1 ? c->Hbar[k * (kRestartMax + 1) + t] : 0.0);
+                        hs += hk * sv[k];
+                    }
+                    const double et = t < j ? cw[t] : ej;
+                    pn[t] = (et - hs) / beta;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (sh[2] != 0.0) return;  // the cycle ends: no further vector is needed
+    const double beta = sh[3], ej = sh[4];
+    const double *sv = cw + j + 1;
+    double *vj = a.V + (int64_t)j * a.n;
+    double *zj = a.Z + (int64_t)j * a.n;
+    double *un = a.V + (int64_t)(j + 1) * a.n;
+    int64_t r0, r1;
+    block_rows(a.n, r0, r1);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        double vs = 0.0, vc = 0.0, zs = 0.0;
+        for (int t = 0; t < j; ++t) {
+            const double vt = a.V[(int64_t)t * a.n + i];
+            vs += vt * sv[t];
+            vc += vt * cw[t];
+            zs += a.Z[(int64_t)t * a.n + i] * sv[t];
+        }
+        double v = vj[i];
+        if (j > 0) {
+            v = (v - vs) / beta;
+            vj[i] = v;
+            zj[i] = (zj[i] - zs) / beta;
+        }
+        un[i] = (a.w[i] - vc - ej * v) / beta;
+        s1[i] = sentinel<T>();
+        s2[i] = sentinel<T>();
     }
 }
 
@@ -1131,7 +1283,7 @@ struct kkt_handle_s {
     int factor_precision = 0;
     int grid_refactor64 = 0, grid_refactor32 = 0, grid_trsv64 = 0, grid_trsv32 = 0, grid_stream = 0;
     kkt::ControlSummary *host_ctl = nullptr;  // pinned
-    kkt::StepRecord *host_rec = nullptr;      // pinned, kRestartMax records
+    kkt::StepRecord *host_rec = nullptr;      // pinned, kRestartMax + 1 records (one per step)
     kkt::StepRecord *dev_rec = nullptr;       // the same memory as seen by kernels
     hipEvent_t step_ev[2] = {nullptr, nullptr};
     int restart_alloc = 0;
@@ -1528,17 +1680,25 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         prof_end(h, KKT_K_OTHER, e0, s);
         // Step j+1 is enqueued before the host reads step j's record, so the device never
         // waits for the host; kernels of a step enqueued after the stop return at once.
-        for (int j = 0; j < R; ++j) {
+        // DCGS2 takes one step more: step R only finishes column R - 1.
+        const bool dcgs2 = h->opts.gram_schmidt == KKT_GS_DCGS2;
+        const int steps = dcgs2 ? R + 1 : R;
+        for (int j = 0; j < steps; ++j) {
             const size_t step_mark = h->ev_pending.size();
-            KKT_HIP(h, precond<T>(h, d.V + (int64_t)j * a.n, d.Z + (int64_t)j * a.n, d.ctl, s));
+            if (j < R) KKT_HIP(h, precond<T>(h, d.V + (int64_t)j * a.n, d.Z + (int64_t)j * a.n, d.ctl, s));
             e0 = prof_begin(h, s);
-            k_spmv_dots<<<G, kStreamBlock, 0, s>>>(ka, j);
+            if (dcgs2) k_dcgs2_dots<<<G, kStreamBlock, 0, s>>>(ka, j, j < R ? 1 : 0);
+            else k_spmv_dots<<<G, kStreamBlock, 0, s>>>(ka, j);
             prof_end(h, KKT_K_SPMV, e0, s);
             e0 = prof_begin(h, s);
-            k_cgs_pass2<<<G, kStreamBlock, 0, s>>>(ka, j);
-            k_cgs_finish<<<G, kStreamBlock, 0, s>>>(ka, j);
             const unsigned long long token = ++h->step_token;
-            k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, R, y, z, h->dev_rec, token);
+            if (dcgs2) {
+                k_dcgs2<T><<<G, kStreamBlock, 0, s>>>(ka, j, R, y, z, h->dev_rec, token);
+            } else {
+                k_cgs_pass2<<<G, kStreamBlock, 0, s>>>(ka, j);
+                k_cgs_finish<<<G, kStreamBlock, 0, s>>>(ka, j);
+                k_normalize<T><<<G, kStreamBlock, 0, s>>>(ka, j, R, y, z, h->dev_rec, token);
+            }
             prof_end(h, KKT_K_CGS, e0, s);
             KKT_HIP(h, hipGetLastError());
             KKT_HIP(h, hipEventRecord(h->step_ev[j & 1], s));
@@ -1585,7 +1745,8 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         st = read_ctl(h, s);
         if (st != KKT_OK) return st;
         iters += h->host_ctl->jdone;
-        inf.precond_applications += h->host_ctl->jdone;
+        // a DCGS2 cycle that stops before its last step has applied M^-1 once more
+        inf.precond_applications += h->host_ctl->jdone + (dcgs2 && h->host_ctl->jdone < R ? 1 : 0);
         est = h->host_ctl->est;
         rn = std::sqrt(h->host_ctl->rnorm2);
         nrbe = rn / (knorm * std::sqrt(h->host_ctl->xnorm2) + bn);
@@ -1780,6 +1941,7 @@ void kkt_opts_default(kkt_opts_t *o) {
     o->inner_tol = 1e-2;
     o->residual = KKT_RESID_FP64;
     o->repivot_cycles = 3;
+    o->gram_schmidt = KKT_GS_CGS2;
 }
 
 kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowptr, const int32_t *colidx,
@@ -1793,6 +1955,10 @@ kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowpt
     if (h->opts.restart < 1 || h->opts.restart > kRestartMax) {
         delete h;
         return fail(nullptr, KKT_EINVAL, "restart must be in 1..64");
+    }
+    if (h->opts.gram_schmidt != KKT_GS_CGS2 && h->opts.gram_schmidt != KKT_GS_DCGS2) {
+        delete h;
+        return fail(nullptr, KKT_EINVAL, "gram_schmidt must be KKT_GS_CGS2 or KKT_GS_DCGS2");
     }
     if (h->opts.residual != KKT_RESID_FP64 && h->opts.residual != KKT_RESID_DD) {
         delete h;
@@ -1866,7 +2032,7 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, hipGetDevice(&h->device));
     if (!h->host_ctl) KKT_HIP(h, hipHostMalloc((void **)&h->host_ctl, sizeof(ControlSummary), hipHostMallocDefault));
     if (!h->host_rec) {
-        KKT_HIP(h, hipHostMalloc((void **)&h->host_rec, sizeof(StepRecord) * kRestartMax,
+        KKT_HIP(h, hipHostMalloc((void **)&h->host_rec, sizeof(StepRecord) * (kRestartMax + 1),
                                  hipHostMallocMapped | hipHostMallocCoherent));
         KKT_HIP(h, hipHostGetDevicePointer((void **)&h->dev_rec, h->host_rec, 0));
     }

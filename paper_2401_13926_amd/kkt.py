@@ -23,6 +23,7 @@ STOP_PAPER, STOP_NRBE = 0, 1
 ORDER_MD, ORDER_ND = 0, 1
 IR_FGMRES, IR_RICHARDSON, IR_ERROR_FGMRES = 0, 1, 2
 RESID_FP64, RESID_DD = 0, 1
+GS_CGS2, GS_DCGS2 = 0, 1
 
 #: every entry point declared in include/kkt.h
 EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
@@ -42,7 +43,8 @@ class Opts(C.Structure):
                 ("precision", C.c_int32), ("guard_policy", C.c_int32), ("stop_mode", C.c_int32),
                 ("mixed_fallback", C.c_int32), ("mixed_max_cycles", C.c_int32), ("ir_method", C.c_int32),
                 ("richardson_max_it", C.c_int32), ("ratio_stop", C.c_double), ("inner_tol", C.c_double),
-                ("residual", C.c_int32), ("repivot_cycles", C.c_int32)]
+                ("residual", C.c_int32), ("repivot_cycles", C.c_int32), ("gram_schmidt", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class AnalysisInfo(C.Structure):

@@ -323,10 +323,11 @@ def test_solve_dd_residual_sequence(dev):
         assert m["nrbe"] <= 1e-12
 
 
+@pytest.mark.parametrize("gs", [P.GS_CGS2, P.GS_DCGS2])
 @pytest.mark.parametrize("case", ["1x1", "2x2", "3x3-dense"])
-def test_tiny_systems(dev, case):
+def test_tiny_systems(dev, case, gs):
     # degenerate sizes: one row, a 2x2 KKT block, a dense 3x3 (every schedule is one tile)
-    say("tiny system", case)
+    say("tiny system", case, "gs", gs)
     if case == "1x1":
         rp, ci, v = np.array([0, 1]), np.array([0], np.int32), np.array([4.0])
     elif case == "2x2":
@@ -337,7 +338,7 @@ def test_tiny_systems(dev, case):
         v = np.array([2.0, -1.0, 0.5, -1.0, 3.0, 1.0, 0.5, 1.0, -4.0])
     n = len(rp) - 1
     b = np.arange(1.0, n + 1.0)
-    s = P.Solver(rp, ci, v, restart=1).bind(dev)
+    s = P.Solver(rp, ci, v, restart=1, gram_schmidt=gs).bind(dev)
     s.refactor(cuda(v, dev))
     x, info = s.solve(cuda(b, dev))
     A = ks.to_dense(rp, ci, v, n)
@@ -346,10 +347,11 @@ def test_tiny_systems(dev, case):
     assert np.allclose(x.cpu().numpy(), xe, rtol=1e-12, atol=0)
 
 
-def test_restart_one_on_60k(dev):
+@pytest.mark.parametrize("gs", [P.GS_CGS2, P.GS_DCGS2])
+def test_restart_one_on_60k(dev, gs):
     # FGMRES(1): every cycle is one Arnoldi step; still converges under the same control
-    say("restart 1 on 60k")
-    p, s, _ = make(2, dev, restart=1)
+    say("restart 1 on 60k gs", gs)
+    p, s, _ = make(2, dev, restart=1, gram_schmidt=gs)
     v, b = p.system(2)
     s.refactor(cuda(v, dev))
     x, info = s.solve(cuda(b, dev))
@@ -492,3 +494,51 @@ def test_long_refinement_repeatable_bitwise(dev):
     assert out[0][1] > 100
     for x, it, est in out[1:]:
         assert np.array_equal(x, out[0][0]) and it == out[0][1] and est == out[0][2]
+
+
+def test_delayed_cgs2_sequence(dev):
+    # delayed CGS2 (gram_schmidt = DCGS2, one reduction per Arnoldi step) builds the same
+    # Krylov basis as CGS2: on the 60k sequence it takes CGS2's iteration counts and the
+    # oracle's DCGS2 counts, applies M^-1 once more per cycle that converges early, and
+    # agrees with a fresh pivoted direct solve like CGS2 does
+    say("delayed cgs2 60k sequence")
+    p, s2, f = make(2, dev)
+    s1 = P.Solver(p.rowptr, p.colidx, p.system(1)[0], gram_schmidt=P.GS_DCGS2).bind(dev)
+    for step in (2, 3, 4):
+        v, b = p.system(step)
+        s1.refactor(cuda(v, dev))
+        s2.refactor(cuda(v, dev))
+        x1, i1 = s1.solve(cuda(b, dev))
+        x2, i2 = s2.solve(cuda(b, dev))
+        assert i1["converged"] == 1 and i1["nrbe"] <= 1e-12
+        assert abs(i1["iterations"] - i2["iterations"]) <= 1
+        lx, ux, _ = f.refactor64(p.rowptr, p.colidx, v)
+        xo, io = f.fgmres_ir(p.rowptr, p.colidx, v, b, Lx=lx, Ux=ux, restart=10, max_restarts=20,
+                             eta=1e-14, mode=1, gs="dcgs2")
+        assert io["converged"] and abs(i1["iterations"] - io["iters"]) <= 1
+        early = int(i1["iterations"] < i1["cycles"] * 10)
+        assert i1["precond_applications"] == 1 + i1["iterations"] + early
+        xg = x1.cpu().numpy()
+        xd, _ = oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=f.Q)
+        rel = np.linalg.norm(xg - xd) / np.linalg.norm(xd)
+        reld = np.linalg.norm(xo - xd) / np.linalg.norm(xd)
+        assert rel <= max(1e3 * reld, 1e-10)
+
+
+@pytest.mark.parametrize("R", [2, 3])
+def test_delayed_cgs2_restarts_match_oracle(dev, R):
+    # short restart lengths on the 60k sequence: cycles end at their closing step (R = 2:
+    # 3 full cycles) or converge inside one (R = 3: 3 + 1 steps); counts as in the oracle
+    say("delayed cgs2 restart", R)
+    p, s, f = make(2, dev, restart=R, gram_schmidt=P.GS_DCGS2)
+    v, b = p.system(2)
+    s.refactor(cuda(v, dev))
+    x, info = s.solve(cuda(b, dev))
+    lx, ux, _ = f.refactor64(p.rowptr, p.colidx, v)
+    xo, io = f.fgmres_ir(p.rowptr, p.colidx, v, b, Lx=lx, Ux=ux, restart=R, max_restarts=20,
+                         eta=1e-14, mode=1, gs="dcgs2")
+    say("  gpu", info["iterations"], info["cycles"], info["precond_applications"],
+        "oracle", io["iters"], io["cycles"], io["applications"])
+    assert info["converged"] == 1 and io["converged"]
+    assert info["iterations"] == io["iters"] and info["cycles"] == io["cycles"]
+    assert info["precond_applications"] == io["applications"]

@@ -373,7 +373,8 @@ def identity_lu(n):
     return oracle.LU(rp, ci, np.ones(n), Q=np.arange(n, dtype=np.int32))
 
 
-def test_fgmres_identity_preconditioner_is_gmres():
+@pytest.mark.parametrize("gs", ["cgs2", "dcgs2"])
+def test_fgmres_identity_preconditioner_is_gmres(gs):
     n = 120
     rng = np.random.default_rng(3)
     A = sp.random(n, n, density=0.05, random_state=4, format="csr") + sp.eye(n) * 4.0
@@ -383,7 +384,7 @@ def test_fgmres_identity_preconditioner_is_gmres():
     b = rng.standard_normal(n)
     fI = identity_lu(n)
     R = 8
-    x, info = fI.fgmres_ir(rp, ci, v, b, restart=R, max_restarts=0, eta=1e-30, mode=1)
+    x, info = fI.fgmres_ir(rp, ci, v, b, restart=R, max_restarts=0, eta=1e-30, mode=1, gs=gs)
     # scipy GMRES from the same initial guess x0 = M^-1 b = b, one cycle of R steps
     hist = []
     r0 = np.linalg.norm(b - A @ b)
@@ -398,19 +399,21 @@ def test_fgmres_identity_preconditioner_is_gmres():
     assert np.linalg.norm(b - A @ x) == pytest.approx(np.linalg.norm(b - A @ xs), rel=1e-8)
 
 
-def test_fgmres_distinct_eigenvalues():
+@pytest.mark.parametrize("gs", ["cgs2", "dcgs2"])
+def test_fgmres_distinct_eigenvalues(gs):
     n = 90
     d = np.repeat([2.0, 3.0, 7.0], n // 3)   # x0 = b, so rho0 = (1 - d) b keeps all three
     rp = np.arange(n + 1, dtype=np.int64)
     ci = np.arange(n, dtype=np.int32)
     b = np.random.default_rng(5).standard_normal(n)
     fI = identity_lu(n)
-    x, info = fI.fgmres_ir(rp, ci, d, b, restart=10, max_restarts=0, eta=1e-13, mode=1)
+    x, info = fI.fgmres_ir(rp, ci, d, b, restart=10, max_restarts=0, eta=1e-13, mode=1, gs=gs)
     assert info["converged"] and info["iters"] == 3
     assert np.abs(d * x - b).max() < 1e-12
 
 
-def test_fgmres_estimate_equals_true_residual_at_restart():
+@pytest.mark.parametrize("gs", ["cgs2", "dcgs2"])
+def test_fgmres_estimate_equals_true_residual_at_restart(gs):
     n = 150
     A = sp.random(n, n, density=0.04, random_state=8, format="csr") + sp.eye(n) * 3.0
     A = sp.csr_matrix(A)
@@ -418,7 +421,7 @@ def test_fgmres_estimate_equals_true_residual_at_restart():
     rp, ci, v = A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data
     b = np.random.default_rng(9).standard_normal(n)
     fI = identity_lu(n)
-    x, info = fI.fgmres_ir(rp, ci, v, b, restart=5, max_restarts=0, eta=1e-30, mode=1)
+    x, info = fI.fgmres_ir(rp, ci, v, b, restart=5, max_restarts=0, eta=1e-30, mode=1, gs=gs)
     assert info["est"] == pytest.approx(info["true_resid"], rel=1e-6)
     assert np.all(np.diff(info["hist"]) <= 1e-12 * info["hist"][0])   # non-increasing
 
@@ -545,3 +548,106 @@ def test_fgmres_dd_residual_reaches_working_accuracy(seed):
     x, info = f.fgmres_ir(p.rowptr, p.colidx, v, b, mode=1, eta=1e-14, residual="dd")
     assert info["converged"]
     assert max_componentwise_error(x, xe) <= 2.0 ** -52
+
+
+def _spread_diag_system(n, lo, hi, seed):
+    """Diagonal-plus-upper-band matrix with eigenvalues spread over [10^lo, 10^hi]: the Krylov
+    vectors align fast, so one Gram-Schmidt pass leaves visible components along the basis."""
+    rng = np.random.default_rng(seed)
+    d = np.logspace(lo, hi, n)
+    A = sp.diags([d, 0.3 * d[:-1]], [0, 1], format="csr")
+    A.sort_indices()
+    return A, rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("R, eta, restarts", [(30, 1e-30, 1), (40, 1e-10, 3)])
+def test_dcgs2_equals_cgs2_on_a_fast_aligning_krylov_basis(R, eta, restarts):
+    # delayed CGS2 builds the same basis and Hessenberg matrix as CGS2 in exact arithmetic
+    # (Bielich et al. 2022); on a basis where one pass loses orthogonality the deferred
+    # corrections (second pass, Hessenberg and z_j updates) are what keeps them equal
+    A, b = _spread_diag_system(400, 0.0, 7.0, 17)
+    rp, ci, v = A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data
+    fI = identity_lu(A.shape[0])
+    x2, i2 = fI.fgmres_ir(rp, ci, v, b, restart=R, max_restarts=restarts, eta=eta, mode=1, gs="cgs2")
+    xd, id_ = fI.fgmres_ir(rp, ci, v, b, restart=R, max_restarts=restarts, eta=eta, mode=1, gs="dcgs2")
+    assert id_["iters"] == i2["iters"] and id_["cycles"] == i2["cycles"]
+    assert np.allclose(id_["hist"], i2["hist"], rtol=1e-7, atol=0.0)
+    assert np.linalg.norm(xd - x2) <= 1e-8 * np.linalg.norm(x2)
+    # one extra preconditioner application per cycle that ends before its restart length
+    early = int(i2["iters"] < i2["cycles"] * R)
+    assert id_["applications"] == i2["applications"] + early
+
+
+def test_dcgs2_inexact_lu_preconditioner():
+    # right preconditioning by LU factors of a nearby matrix (the refactorization setting)
+    p = ks.small_kkt(300, 200, 5, (-4.0, 4.0))
+    v1, b2 = p.system(1)
+    v2 = v1 * (1.0 + 0.02 * np.random.default_rng(11).standard_normal(v1.size))
+    f = oracle.LU(p.rowptr, p.colidx, v1)
+    x2, i2 = f.fgmres_ir(p.rowptr, p.colidx, v2, b2, restart=10, max_restarts=5, eta=1e-12, mode=1,
+                         gs="cgs2")
+    xd, id_ = f.fgmres_ir(p.rowptr, p.colidx, v2, b2, restart=10, max_restarts=5, eta=1e-12, mode=1,
+                          gs="dcgs2")
+    assert i2["converged"] and id_["converged"]
+    assert id_["iters"] == i2["iters"]
+    # equal to rounding: relative to each estimate, or to the initial residual once tiny
+    assert np.allclose(id_["hist"], i2["hist"], rtol=1e-6, atol=1e-13 * i2["hist"][0])
+    assert np.linalg.norm(xd - x2) <= 1e-9 * np.linalg.norm(x2)
+
+
+def test_dcgs2_breakdown_and_application_count():
+    # three distinct eigenvalues: the fourth vector vanishes (breakdown found when its delayed
+    # second pass gives beta = 0), after one preconditioner application more than CGS2
+    n = 90
+    d = np.repeat([2.0, 3.0, 7.0], n // 3)
+    rp = np.arange(n + 1, dtype=np.int64)
+    ci = np.arange(n, dtype=np.int32)
+    b = np.random.default_rng(5).standard_normal(n)
+    fI = identity_lu(n)
+    _, ic = fI.fgmres_ir(rp, ci, d, b, restart=10, max_restarts=0, eta=1e-30, mode=1, gs="cgs2")
+    _, idl = fI.fgmres_ir(rp, ci, d, b, restart=10, max_restarts=0, eta=1e-30, mode=1, gs="dcgs2")
+    assert ic["iters"] == idl["iters"] == 3
+    assert ic["applications"] == 1 + 3 and idl["applications"] == 1 + 4
+
+
+def _arnoldi_invariants(A, M, V, Z, H, k):
+    """Relative error of the Arnoldi relation A Z = V Hbar, loss of orthonormality of V and
+    error of Z = M^-1 V over the first k - 1 columns."""
+    m = k - 1
+    AZ = A @ Z[:, :m]
+    rel = np.linalg.norm(AZ - V[:, :m + 1] @ H[:m + 1, :m]) / np.linalg.norm(AZ)
+    orth = np.linalg.norm(V[:, :m + 1].T @ V[:, :m + 1] - np.eye(m + 1))
+    zr = np.linalg.norm(M @ Z[:, :m] - V[:, :m]) / np.sqrt(m)
+    return rel, orth, zr
+
+
+@pytest.mark.parametrize("gs", ["cgs2", "dcgs2"])
+def test_arnoldi_relation_and_orthonormal_basis(gs):
+    # Eight eigenvalue clusters of width 1e-9: Arnoldi nearly breaks down after eight steps,
+    # where one Gram-Schmidt pass leaves components of relative size ~1e-8 along the basis.
+    # The delayed corrections divided by the small norm (Hbar s / beta in the Hessenberg
+    # column, Z s / beta in z_j, V s in v_j) are what keeps K Z = V Hbar, Z = M^-1 V and
+    # V^T V = I at rounding level; dropping any one leaves errors >= 1e-9 here.
+    rng = np.random.default_rng(3)
+    n = 400
+    d = np.concatenate([c + 1e-9 * rng.standard_normal(n // 8) for c in np.arange(1, 9)])
+    A = sp.diags([d], [0], format="csr")
+    A.sort_indices()
+    b = rng.standard_normal(n)
+    fI = identity_lu(n)
+    V, Z, H, k = fI.arnoldi(A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, b, 20, gs)
+    assert k == 20
+    rel, orth, zr = _arnoldi_invariants(A, sp.eye(n), V, Z, H, k)
+    assert rel <= 1e-13 and orth <= 1e-13 and zr <= 1e-14
+    # right preconditioning by LU factors of a nearby KKT matrix
+    p = ks.small_kkt(300, 200, 5, (-4.0, 4.0))
+    v1, bk = p.system(1)
+    v2 = v1 * (1.0 + 1e-6 * np.random.default_rng(11).standard_normal(v1.size))
+    f = oracle.LU(p.rowptr, p.colidx, v1)
+    nk = p.rowptr.size - 1
+    K2 = sp.csr_matrix((v2, p.colidx, p.rowptr), shape=(nk, nk))
+    K1 = sp.csr_matrix((v1, p.colidx, p.rowptr), shape=(nk, nk))
+    V, Z, H, k = f.arnoldi(p.rowptr, p.colidx, v2, bk, 10, gs)
+    assert k == 10
+    rel, orth, zr = _arnoldi_invariants(K2, K1, V, Z, H, k)
+    assert rel <= 1e-12 and orth <= 1e-13 and zr <= 1e-11
