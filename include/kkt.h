@@ -105,7 +105,10 @@ typedef struct {
                                reduction; 2 kernels per step after the triangular solves
                                instead of 4, the same Krylov basis, and one preconditioner
                                application more per cycle that converges before its restart */
-    int32_t reserved;
+    int32_t tile_lds_kib;   /* LDS budget of one staged triangular-solve tile in KiB, 16..150
+                               (0: 64).  Larger tiles hold more levels of the elimination tree,
+                               so fewer cross-block hands-offs lie on a solve's critical path;
+                               above 80 KiB one solve block occupies a compute unit alone */
 } kkt_opts_t;
 
 enum { KKT_IR_FGMRES = 0, KKT_IR_RICHARDSON = 1, KKT_IR_ERROR_FGMRES = 2 };
@@ -242,6 +245,12 @@ kkt_status_t kkt_get_factor_values(kkt_handle_t h, int32_t precision, double *lx
 /* Enable (1) or disable (0) per-launch timing with HIP events on the work stream; enabling
  * clears the totals.  Timing adds two event records per kernel launch. */
 kkt_status_t kkt_set_profiling(kkt_handle_t h, int32_t on);
+
+/* Time only the kernel classes whose bits are set in class_mask (bit c: class c of
+ * kkt_kernel_class_t; 0 disables timing) and clear the totals.  Timing one class keeps the
+ * event records, and their cost on the host and the stream, to that class's launches.
+ * KKT_EINVAL for bits at or beyond KKT_K_CLASSES. */
+kkt_status_t kkt_set_profiling_mask(kkt_handle_t h, uint32_t class_mask);
 
 /* Totals since profiling was enabled: launches and device milliseconds per kernel class.
  * Synchronizes `stream` (the stream the work was issued on). */

@@ -13,7 +13,9 @@ constexpr int kStreamGridMax = 256;    // blocks of the streaming kernels (parti
 constexpr int kCoopBlock = 256;        // threads per block of the refactorization
 constexpr int kTileThreads = 256;      // threads per block of the triangular solves
 constexpr int kTileRows = 2048;        // rows of a multi-level solve tile (values in LDS)
-constexpr int kTileLds = 65536;        // LDS bytes of a staged solve tile
+constexpr int kTileLds = 65536;        // default LDS bytes of a staged solve tile
+constexpr int kTileLdsMin = 16 * 1024;  // smallest and largest tile budgets (gfx950: 160 KiB of LDS
+constexpr int kTileLdsMax = 150 * 1024; // per compute unit, the rest for the kernel's own arrays)
 constexpr int kRefactorLds = 1024;     // factor entries staged in LDS per wavefront
 // Spin limit of one dependency wait (iterations of a short sleep, a few seconds in all);
 // exceeding it marks Control::hang and lets every wave run to completion.

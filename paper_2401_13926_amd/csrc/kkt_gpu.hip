@@ -478,7 +478,7 @@ template <typename P> __device__ __forceinline__ const __attribute__((address_sp
 
 template <typename T, bool kLower, bool kDense>
 __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
-    __shared__ __align__(16) unsigned char smem[kTileLds];
+    extern __shared__ __align__(16) unsigned char smem[];  // the tile budget, sized at launch
     __shared__ T ys[kDenseRows];  // dense segment: rows' right-hand sides minus earlier terms
     __shared__ unsigned int tile_sh;
     if (a.stopflag && a.stopflag->stop) return;
@@ -1140,7 +1140,14 @@ __global__ void __launch_bounds__(kStreamBlock) k_resid(KrylovArgs a, const doub
 }
 
 // One block: sums of the residual kernel's partials into the control block.
-__global__ void __launch_bounds__(kStreamBlock) k_resid_reduce(KrylovArgs a, int G) {
+// The control block starts with the fields of ControlSummary, in the same layout.
+static_assert(sizeof(ControlSummary) % 8 == 0 && sizeof(ControlSummary) <= sizeof(Control),
+              "ControlSummary is copied as 64-bit words from the start of Control");
+
+// Reduces the residual kernel's partials into the control block, then copies the control
+// summary into pinned host memory (system-scope stores: visible to the host once the stream
+// has been synchronized), so reading it back needs no separate copy.
+__global__ void __launch_bounds__(kStreamBlock) k_resid_reduce(KrylovArgs a, int G, ControlSummary *pub) {
     __shared__ double h[4];
     __shared__ double red[4 * (kStreamBlock / 64)];
     reduce_cols(partbuf(a, 0), G, 4, h, red);
@@ -1155,6 +1162,10 @@ __global__ void __launch_bounds__(kStreamBlock) k_resid_reduce(KrylovArgs a, int
         a.ctl->xnorm2 = h[1];
         a.ctl->bnorm2 = h[2];
         if (h[3] != 0.0) a.ctl->nonfinite_b = 1;
+        const unsigned long long *src = reinterpret_cast<const unsigned long long *>(a.ctl);
+        unsigned long long *dst = reinterpret_cast<unsigned long long *>(pub);
+        for (size_t w = 0; w < sizeof(ControlSummary) / 8; ++w)
+            __hip_atomic_store(dst + w, src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -1269,6 +1280,7 @@ struct DevLayout {
 }  // namespace kkt
 
 struct kkt_handle_s {
+    size_t tile_lds = kkt::kTileLds;  // dynamic LDS bytes of a solve block (the tile budget)
     kkt_opts_t opts{};
     kkt::Analysis an;
     std::string err;
@@ -1282,7 +1294,8 @@ struct kkt_handle_s {
     bool have_factors = false;
     int factor_precision = 0;
     int grid_refactor64 = 0, grid_refactor32 = 0, grid_trsv64 = 0, grid_trsv32 = 0, grid_stream = 0;
-    kkt::ControlSummary *host_ctl = nullptr;  // pinned
+    kkt::ControlSummary *host_ctl = nullptr;  // pinned, mapped: written by k_resid_reduce
+    kkt::ControlSummary *dev_ctl_sum = nullptr;  // the same memory as seen by kernels
     kkt::StepRecord *host_rec = nullptr;      // pinned, kRestartMax + 1 records (one per step)
     kkt::StepRecord *dev_rec = nullptr;       // the same memory as seen by kernels
     hipEvent_t step_ev[2] = {nullptr, nullptr};
@@ -1295,7 +1308,7 @@ struct kkt_handle_s {
         int cls;
         hipEvent_t a, b;
     };
-    bool prof = false;
+    uint32_t prof_mask = 0;  // kernel classes timed with events (bit c: class c)
     std::vector<hipEvent_t> ev_pool;
     std::vector<ProfRec> ev_pending;
     kkt_kernel_times_t times{};
@@ -1322,8 +1335,8 @@ kkt_status_t fail(kkt_handle_t h, kkt_status_t s, const std::string &m) {
     } while (0)
 
 // --- per-launch timing with HIP events --------------------------------------------------
-hipEvent_t prof_begin(kkt_handle_t h, hipStream_t s) {
-    if (!h->prof) return nullptr;
+hipEvent_t prof_begin(kkt_handle_t h, int cls, hipStream_t s) {
+    if (!(h->prof_mask & (1u << cls))) return nullptr;
     hipEvent_t e = nullptr;
     if (!h->ev_pool.empty()) {
         e = h->ev_pool.back();
@@ -1458,9 +1471,12 @@ template <typename T> hipError_t up(char *base, size_t off, const std::vector<T>
 }
 
 // Blocks of 256 threads that fit on the device at once (a persistent grid size).
-int coop_grid(const void *func, int device) {
+int coop_grid(const void *func, int device, size_t dyn_lds = 0) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kCoopBlock, 0) != hipSuccess) return 0;
+    if (dyn_lds > 0 &&
+        hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kCoopBlock, dyn_lds) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
     return per_cu * cus;
 }
@@ -1529,10 +1545,10 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(is64 ? h->grid_trsv64 : h->grid_trsv32, t.ntiles));
     // the variant without the dense-segment path when the schedule has none
     const bool dense = sc.values() > sc.packed;
-    if (lower && dense) k_trsv<T, true, true><<<grid, kTileThreads, 0, s>>>(t);
-    else if (lower) k_trsv<T, true, false><<<grid, kTileThreads, 0, s>>>(t);
-    else if (dense) k_trsv<T, false, true><<<grid, kTileThreads, 0, s>>>(t);
-    else k_trsv<T, false, false><<<grid, kTileThreads, 0, s>>>(t);
+    if (lower && dense) k_trsv<T, true, true><<<grid, kTileThreads, h->tile_lds, s>>>(t);
+    else if (lower) k_trsv<T, true, false><<<grid, kTileThreads, h->tile_lds, s>>>(t);
+    else if (dense) k_trsv<T, false, true><<<grid, kTileThreads, h->tile_lds, s>>>(t);
+    else k_trsv<T, false, false><<<grid, kTileThreads, h->tile_lds, s>>>(t);
     return hipGetLastError();
 }
 
@@ -1541,11 +1557,11 @@ template <typename T>
 hipError_t precond(kkt_handle_t h, const double *b, double *x, const Control *ctl, hipStream_t s) {
     T *y = (T *)(sizeof(T) == 8 ? (void *)h->d.y64 : (void *)h->d.y32);
     T *z = (T *)(sizeof(T) == 8 ? (void *)h->d.z64 : (void *)h->d.z32);
-    hipEvent_t e0 = prof_begin(h, s);
+    hipEvent_t e0 = prof_begin(h, KKT_K_TRSV_L, s);
     hipError_t e = launch_trsv<T>(h, true, b, nullptr, y, nullptr, ctl, s);
     prof_end(h, KKT_K_TRSV_L, e0, s);
     if (e != hipSuccess) return e;
-    e0 = prof_begin(h, s);
+    e0 = prof_begin(h, KKT_K_TRSV_U, s);
     e = launch_trsv<T>(h, false, nullptr, y, z, x, ctl, s);
     prof_end(h, KKT_K_TRSV_U, e0, s);
     return e;
@@ -1554,7 +1570,7 @@ hipError_t precond(kkt_handle_t h, const double *b, double *x, const Control *ct
 template <typename T> void rearm(kkt_handle_t h, hipStream_t s) {
     T *y = (T *)(sizeof(T) == 8 ? (void *)h->d.y64 : (void *)h->d.y32);
     T *z = (T *)(sizeof(T) == 8 ? (void *)h->d.z64 : (void *)h->d.z32);
-    hipEvent_t e0 = prof_begin(h, s);
+    hipEvent_t e0 = prof_begin(h, KKT_K_OTHER, s);
     k_fill_sentinel<T><<<h->grid_stream, kStreamBlock, 0, s>>>(h->an.n, y, z, h->d.ctl);
     prof_end(h, KKT_K_OTHER, e0, s);
 }
@@ -1566,7 +1582,7 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
     const int64_t f = a.nnz_f();
     DevLayout &d = h->d;
     const int rows_grid = (int)std::max<int64_t>(1, std::min<int64_t>((a.n + 255) / 256, 2048));
-    hipEvent_t e0 = prof_begin(h, s);
+    hipEvent_t e0 = prof_begin(h, KKT_K_INGEST, s);
     k_prep_refactor<<<1, 1, 0, s>>>(d.ctl);
     if (dev_values)
         k_ingest<<<2048, 256, 0, s>>>(a.nnz, dev_values, d.kval, f, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32,
@@ -1577,7 +1593,7 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
     k_rownorm<<<rows_grid, 256, 0, s>>>(a.n, d.krp, d.kval, d.ctl);
     prof_end(h, KKT_K_INGEST, e0, s);
     KKT_HIP(h, hipGetLastError());
-    e0 = prof_begin(h, s);
+    e0 = prof_begin(h, KKT_K_REFACTOR, s);
     if (precision == KKT_PREC_MIXED) {
         const unsigned int chunk = work_chunk(a.n, h->grid_refactor32 * (kCoopBlock / 64));
         RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F32, d.T32,
@@ -1601,8 +1617,8 @@ void launch_resid(kkt_handle_t h, const KrylovArgs &ka, const double *b, const d
     else k_resid<false><<<h->grid_stream, kStreamBlock, 0, s>>>(ka, b, x, r);
 }
 
+// The summary is already in host memory (k_resid_reduce wrote it): wait for the stream.
 kkt_status_t read_ctl(kkt_handle_t h, hipStream_t s) {
-    KKT_HIP(h, hipMemcpyAsync(h->host_ctl, h->d.ctl, sizeof(ControlSummary), hipMemcpyDeviceToHost, s));
     KKT_HIP(h, hipStreamSynchronize(s));
     prof_collect(h);
     if (h->host_ctl->hang) {
@@ -1628,14 +1644,14 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     KrylovArgs ka = kargs<T>(h);
     T *y = (T *)(sizeof(T) == 8 ? (void *)d.y64 : (void *)d.y32);
     T *z = (T *)(sizeof(T) == 8 ? (void *)d.z64 : (void *)d.z32);
-    hipEvent_t e0 = prof_begin(h, s);
+    hipEvent_t e0 = prof_begin(h, KKT_K_OTHER, s);
     k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
     prof_end(h, KKT_K_OTHER, e0, s);
     rearm<T>(h, s);
     KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
-    e0 = prof_begin(h, s);
+    e0 = prof_begin(h, KKT_K_RESID, s);
     launch_resid(h, ka, b, x, d.r, s);
-    k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G);
+    k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G, h->dev_ctl_sum);
     prof_end(h, KKT_K_RESID, e0, s);
     KKT_HIP(h, hipGetLastError());
     kkt_status_t st = read_ctl(h, s);
@@ -1675,7 +1691,7 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         }
         const double xn = std::sqrt(h->host_ctl->xnorm2);
         const double inner = paper ? tol * rho0 : target * (knorm * xn + bn);
-        e0 = prof_begin(h, s);
+        e0 = prof_begin(h, KKT_K_OTHER, s);
         k_cycle_start<T><<<G, kStreamBlock, 0, s>>>(ka, d.r, inner, y, z);
         prof_end(h, KKT_K_OTHER, e0, s);
         // Step j+1 is enqueued before the host reads step j's record, so the device never
@@ -1686,11 +1702,11 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         for (int j = 0; j < steps; ++j) {
             const size_t step_mark = h->ev_pending.size();
             if (j < R) KKT_HIP(h, precond<T>(h, d.V + (int64_t)j * a.n, d.Z + (int64_t)j * a.n, d.ctl, s));
-            e0 = prof_begin(h, s);
+            e0 = prof_begin(h, KKT_K_SPMV, s);
             if (dcgs2) k_dcgs2_dots<<<G, kStreamBlock, 0, s>>>(ka, j, j < R ? 1 : 0);
             else k_spmv_dots<<<G, kStreamBlock, 0, s>>>(ka, j);
             prof_end(h, KKT_K_SPMV, e0, s);
-            e0 = prof_begin(h, s);
+            e0 = prof_begin(h, KKT_K_CGS, s);
             const unsigned long long token = ++h->step_token;
             if (dcgs2) {
                 k_dcgs2<T><<<G, kStreamBlock, 0, s>>>(ka, j, R, y, z, h->dev_rec, token);
@@ -1734,12 +1750,12 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
                 break;
             }
         }
-        e0 = prof_begin(h, s);
+        e0 = prof_begin(h, KKT_K_OTHER, s);
         k_xupdate<<<G, kStreamBlock, 0, s>>>(ka, x);
         prof_end(h, KKT_K_OTHER, e0, s);
-        e0 = prof_begin(h, s);
+        e0 = prof_begin(h, KKT_K_RESID, s);
         launch_resid(h, ka, b, x, d.r, s);
-        k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G);
+        k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G, h->dev_ctl_sum);
         prof_end(h, KKT_K_RESID, e0, s);
         KKT_HIP(h, hipGetLastError());
         st = read_ctl(h, s);
@@ -1776,15 +1792,15 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
     DevLayout &d = h->d;
     const int G = h->grid_stream;
     KrylovArgs ka = kargs<T>(h);
-    hipEvent_t e0 = prof_begin(h, s);
+    hipEvent_t e0 = prof_begin(h, KKT_K_OTHER, s);
     k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
     prof_end(h, KKT_K_OTHER, e0, s);
     rearm<T>(h, s);
     KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
     auto residual = [&]() -> kkt_status_t {
-        hipEvent_t r0 = prof_begin(h, s);
+        hipEvent_t r0 = prof_begin(h, KKT_K_RESID, s);
         launch_resid(h, ka, b, x, d.r, s);
-        k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G);
+        k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G, h->dev_ctl_sum);
         prof_end(h, KKT_K_RESID, r0, s);
         KKT_HIP(h, hipGetLastError());
         return read_ctl(h, s);
@@ -1817,7 +1833,7 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
     int it = 0;
     while (!converged && it < h->opts.richardson_max_it) {
         if (inner_fgmres) {
-            hipEvent_t c0 = prof_begin(h, s);
+            hipEvent_t c0 = prof_begin(h, KKT_K_OTHER, s);
             k_copy<<<G, kStreamBlock, 0, s>>>(a.n, d.r, d.rr);
             prof_end(h, KKT_K_OTHER, c0, s);
             kkt_solve_info_t in{};
@@ -1830,7 +1846,7 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
             KKT_HIP(h, precond<T>(h, d.r, d.dv, nullptr, s));
             inf.precond_applications += 1;
         }
-        hipEvent_t x0 = prof_begin(h, s);
+        hipEvent_t x0 = prof_begin(h, KKT_K_OTHER, s);
         k_axpy<<<G, kStreamBlock, 0, s>>>(a.n, d.dv, x);
         prof_end(h, KKT_K_OTHER, x0, s);
         ++it;
@@ -1876,7 +1892,8 @@ AnalysisOptions analysis_options(const kkt_opts_t &o) {
     ao.pivot_tau = o.pivot_tau;
     ao.tile_threads = kTileThreads;
     ao.tile_rows = kTileRows;
-    ao.tile_lds = kTileLds;
+    ao.tile_lds = o.tile_lds_kib > 0 ? o.tile_lds_kib * 1024 : kTileLds;
+    ao.dense_reserve_l = ao.tile_lds / 4;
     return ao;
 }
 
@@ -1964,7 +1981,13 @@ kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowpt
         delete h;
         return fail(nullptr, KKT_EINVAL, "residual must be KKT_RESID_FP64 or KKT_RESID_DD");
     }
+    if (h->opts.tile_lds_kib != 0 &&
+        (h->opts.tile_lds_kib * 1024 < kTileLdsMin || h->opts.tile_lds_kib * 1024 > kTileLdsMax)) {
+        delete h;
+        return fail(nullptr, KKT_EINVAL, "tile_lds_kib must be 0 or in 16..150");
+    }
     AnalysisOptions ao = analysis_options(h->opts);
+    h->tile_lds = (size_t)ao.tile_lds;
     std::string msg;
     int rc = analyze(ao, n, rowptr, colidx, values_first, h->an, &msg);
     if (rc != AN_OK) {
@@ -2030,7 +2053,11 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     if (((uintptr_t)dev_ptr & 255) != 0) return fail(h, KKT_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     KKT_HIP(h, hipGetDevice(&h->device));
-    if (!h->host_ctl) KKT_HIP(h, hipHostMalloc((void **)&h->host_ctl, sizeof(ControlSummary), hipHostMallocDefault));
+    if (!h->host_ctl) {
+        KKT_HIP(h, hipHostMalloc((void **)&h->host_ctl, sizeof(ControlSummary),
+                                 hipHostMallocMapped | hipHostMallocCoherent));
+        KKT_HIP(h, hipHostGetDevicePointer((void **)&h->dev_ctl_sum, h->host_ctl, 0));
+    }
     if (!h->host_rec) {
         KKT_HIP(h, hipHostMalloc((void **)&h->host_rec, sizeof(StepRecord) * (kRestartMax + 1),
                                  hipHostMallocMapped | hipHostMallocCoherent));
@@ -2136,14 +2163,14 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, hipStreamSynchronize(s));
     h->grid_refactor64 = coop_grid((const void *)k_refactor<double>, h->device);
     h->grid_refactor32 = coop_grid((const void *)k_refactor<float>, h->device);
-    h->grid_trsv64 = std::min(std::min(coop_grid((const void *)k_trsv<double, true, true>, h->device),
-                                       coop_grid((const void *)k_trsv<double, false, true>, h->device)),
-                              std::min(coop_grid((const void *)k_trsv<double, true, false>, h->device),
-                                       coop_grid((const void *)k_trsv<double, false, false>, h->device)));
-    h->grid_trsv32 = std::min(std::min(coop_grid((const void *)k_trsv<float, true, true>, h->device),
-                                       coop_grid((const void *)k_trsv<float, false, true>, h->device)),
-                              std::min(coop_grid((const void *)k_trsv<float, true, false>, h->device),
-                                       coop_grid((const void *)k_trsv<float, false, false>, h->device)));
+    h->grid_trsv64 = std::min(std::min(coop_grid((const void *)k_trsv<double, true, true>, h->device, h->tile_lds),
+                                       coop_grid((const void *)k_trsv<double, false, true>, h->device, h->tile_lds)),
+                              std::min(coop_grid((const void *)k_trsv<double, true, false>, h->device, h->tile_lds),
+                                       coop_grid((const void *)k_trsv<double, false, false>, h->device, h->tile_lds)));
+    h->grid_trsv32 = std::min(std::min(coop_grid((const void *)k_trsv<float, true, true>, h->device, h->tile_lds),
+                                       coop_grid((const void *)k_trsv<float, false, true>, h->device, h->tile_lds)),
+                              std::min(coop_grid((const void *)k_trsv<float, true, false>, h->device, h->tile_lds),
+                                       coop_grid((const void *)k_trsv<float, false, false>, h->device, h->tile_lds)));
     if (h->grid_refactor64 <= 0 || h->grid_refactor32 <= 0 || h->grid_trsv64 <= 0 || h->grid_trsv32 <= 0)
         return fail(h, KKT_EDEVICE, "occupancy query failed");
     h->grid_stream = stream_blocks(a.n);
@@ -2251,8 +2278,13 @@ kkt_status_t kkt_get_factor_values(kkt_handle_t h, int32_t precision, double *lx
 }
 
 kkt_status_t kkt_set_profiling(kkt_handle_t h, int32_t on) {
+    return kkt_set_profiling_mask(h, on ? (1u << KKT_K_CLASSES) - 1u : 0u);
+}
+
+kkt_status_t kkt_set_profiling_mask(kkt_handle_t h, uint32_t class_mask) {
     if (!h) return fail(h, KKT_EINVAL, "null handle");
-    h->prof = on != 0;
+    if (class_mask >> KKT_K_CLASSES) return fail(h, KKT_EINVAL, "class mask has bits beyond KKT_K_CLASSES");
+    h->prof_mask = class_mask;
     h->times = kkt_kernel_times_t{};
     return KKT_OK;
 }
@@ -2275,6 +2307,7 @@ kkt_status_t kkt_clone(kkt_handle_t src, kkt_handle_t *out) {
     try {
         h->opts = src->opts;
         h->an = src->an;
+        h->tile_lds = src->tile_lds;
     } catch (const std::bad_alloc &) {
         delete h;
         return fail(src, KKT_ENOMEM, "out of host memory");

@@ -29,7 +29,8 @@ GS_CGS2, GS_DCGS2 = 0, 1
 EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
            "kkt_get_factor_pattern", "kkt_get_analysis_values", "kkt_workspace_size",
            "kkt_bind_workspace", "kkt_refactor", "kkt_solve", "kkt_direct_solve", "kkt_residual",
-           "kkt_get_factor_values", "kkt_set_profiling", "kkt_get_kernel_times", "kkt_release",
+           "kkt_get_factor_values", "kkt_set_profiling", "kkt_set_profiling_mask", "kkt_get_kernel_times",
+           "kkt_release",
            "kkt_last_error",
            "kkt_clone", "kkt_server_create", "kkt_server_add_pattern", "kkt_server_submit",
            "kkt_server_wait", "kkt_server_poll", "kkt_server_stats", "kkt_server_destroy"]
@@ -44,7 +45,7 @@ class Opts(C.Structure):
                 ("mixed_fallback", C.c_int32), ("mixed_max_cycles", C.c_int32), ("ir_method", C.c_int32),
                 ("richardson_max_it", C.c_int32), ("ratio_stop", C.c_double), ("inner_tol", C.c_double),
                 ("residual", C.c_int32), ("repivot_cycles", C.c_int32), ("gram_schmidt", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("tile_lds_kib", C.c_int32)]
 
 
 class AnalysisInfo(C.Structure):
@@ -109,6 +110,7 @@ def lib():
         L.kkt_residual.argtypes = [vp, vp, vp, vp, vp]
         L.kkt_get_factor_values.argtypes = [vp, C.c_int32, f64p, f64p, vp]
         L.kkt_set_profiling.argtypes = [vp, C.c_int32]
+        L.kkt_set_profiling_mask.argtypes = [vp, C.c_uint32]
         L.kkt_get_kernel_times.argtypes = [vp, C.POINTER(KernelTimes), vp]
         L.kkt_release.argtypes = [vp]
         L.kkt_clone.argtypes = [vp, C.POINTER(vp)]
@@ -277,8 +279,16 @@ class Solver:
         return lx, ux
 
     # --- per-kernel timing ------------------------------------------------------------
-    def set_profiling(self, on=True):
-        self._check(lib().kkt_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on=True, classes=None):
+        """Per-launch event timing: all kernel classes, or only those named in `classes`
+        (names of KERNEL_CLASSES)."""
+        if classes is None:
+            self._check(lib().kkt_set_profiling(self._h, 1 if on else 0))
+            return
+        mask = 0
+        for c in classes:
+            mask |= 1 << KERNEL_CLASSES.index(c)
+        self._check(lib().kkt_set_profiling_mask(self._h, mask if on else 0))
 
     def kernel_times(self, stream=None) -> dict:
         """{class: (launches, total ms)} since profiling was enabled (syncs the stream)."""

@@ -106,11 +106,13 @@ def check_solve_backward_error(f, lx, ux, b, x, unit):
     assert np.all(r <= 4 * w * unit * bound + 1e-300), float(np.max(r / np.maximum(bound, 1e-300)))
 
 
+@pytest.mark.parametrize("tile_kib", [0, 150])
 @pytest.mark.parametrize("cfg", [1, 2])
 @pytest.mark.parametrize("step", [1, 2])
-def test_direct_solve_backward_error(dev, cfg, step):
-    say("direct solve config", cfg, "step", step)
-    p, s, f = make(cfg, dev)
+def test_direct_solve_backward_error(dev, cfg, step, tile_kib):
+    # tile_kib: the default 64 KiB solve tiles, and the largest budget (one block per CU)
+    say("direct solve config", cfg, "step", step, "tile KiB", tile_kib)
+    p, s, f = make(cfg, dev, tile_lds_kib=tile_kib)
     v, b = p.system(step)
     s.refactor(cuda(v, dev))
     x = s.direct_solve(cuda(b, dev)).cpu().numpy()
