@@ -52,7 +52,9 @@ def algorithmic_bytes(cls: str, ai: dict) -> float:
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kkt_sequence_60k_hbm_counters.txt")
-KERNEL_NAMES = {"trsv_l": "kkt::k_trsv<double,true>", "trsv_u": "kkt::k_trsv<double,false>",
+# kernel-name prefixes of each class in the counter summary (the solve kernels carry a second
+# template flag: dense segments on or off)
+KERNEL_NAMES = {"trsv_l": "kkt::k_trsv<double,true", "trsv_u": "kkt::k_trsv<double,false",
                 "refactor": "kkt::k_refactor<double>", "spmv": "kkt::k_spmv_dots"}
 
 
@@ -78,7 +80,7 @@ def measured_traffic(cls: str):
     with open(TRAFFIC_FILE) as f:
         for line in f:
             parts = line.split()
-            if len(parts) == 5 and parts[0] == "traffic" and parts[1] == name and parts[4] == digest:
+            if len(parts) == 5 and parts[0] == "traffic" and parts[1].startswith(name) and parts[4] == digest:
                 return float(parts[2]) + float(parts[3])
     return None
 
