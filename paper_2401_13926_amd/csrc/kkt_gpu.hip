@@ -77,41 +77,49 @@ template <typename T> __device__ __forceinline__ void store_ready(T *p, T v) {
 // return the sentinel or the final value), then coherent polling until it is written.  A
 // wait longer than kSpinLimit sets *hang and gives up (every later wait then returns at
 // once), so a broken schedule ends the kernel with an error instead of never finishing.
-// kInFlight coherent loads in flight (4 or 2), one issued per check: a store is seen a
-// fraction of a memory round trip after it lands instead of up to a whole one.  The
-// refactorization waits with 4; the triangular solves, whose staging waits overlap with other
-// tiles' loads, measured faster with 2 (less polling traffic).
+// Waits until *p no longer holds the sentinel.  kInFlight = 4: four coherent loads in
+// flight, one issued per check, so a store is seen about a quarter of a memory round trip
+// after it lands (the refactorization's waits, which sit on its critical chain).
+// kInFlight = 1: one load at a time (the triangular solves' staging waits, which overlap
+// other tiles' loads: less polling traffic measured faster there).
 template <typename T, int kInFlight = 4>
 __device__ __forceinline__ T load_ready(const T *p, unsigned int *hang) {
-    static_assert(kInFlight == 4 || kInFlight == 2, "4 or 2 loads in flight");
+    static_assert(kInFlight == 4 || kInFlight == 1, "4 or 1 loads in flight");
     using U = typename Bits<T>::U;
     T v = *p;
     if (!is_sentinel(v)) return v;
     const U *q = reinterpret_cast<const U *>(p);
+    unsigned int spins = 0;
+    if (kInFlight == 1) {
+        // (no early exit on another wave's hang flag: the check measured slower in this loop;
+        // every waiting lane still gives up after kSpinLimit polls)
+        for (;;) {
+            const U b = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (b != Bits<T>::sent) return __builtin_bit_cast(T, b);
+            if (++spins >= kSpinLimit) {
+                __hip_atomic_store(hang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return T(0);
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
     U b0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __builtin_amdgcn_s_sleep(1);
     U b1 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    U b2 = Bits<T>::sent, b3 = Bits<T>::sent;
-    if (kInFlight == 4) {
-        __builtin_amdgcn_s_sleep(1);
-        b2 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __builtin_amdgcn_s_sleep(1);
-        b3 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-    unsigned int spins = 0;
+    __builtin_amdgcn_s_sleep(1);
+    U b2 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __builtin_amdgcn_s_sleep(1);
+    U b3 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     for (;;) {
         if (b0 != Bits<T>::sent) return __builtin_bit_cast(T, b0);
         b0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        if (kInFlight == 2) __builtin_amdgcn_s_sleep(1);
         if (b1 != Bits<T>::sent) return __builtin_bit_cast(T, b1);
         b1 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        if (kInFlight == 4) {
-            if (b2 != Bits<T>::sent) return __builtin_bit_cast(T, b2);
-            b2 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            if (b3 != Bits<T>::sent) return __builtin_bit_cast(T, b3);
-            b3 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-        spins += kInFlight;
+        if (b2 != Bits<T>::sent) return __builtin_bit_cast(T, b2);
+        b2 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (b3 != Bits<T>::sent) return __builtin_bit_cast(T, b3);
+        b3 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        spins += 4;
         if (spins >= kSpinLimit ||
             ((spins & 1023u) == 0 && __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
             __hip_atomic_store(hang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -516,7 +524,7 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
                 for (int e = tid; e < ne; e += 64) {
                     const int c = a.ent_ref[eb + e];
                     T xk = a.out[c];
-                    if (is_sentinel(xk)) xk = load_ready<T, 2>(a.out + c, a.hang);
+                    if (is_sentinel(xk)) xk = load_ready<T, 1>(a.out + c, a.hang);
                     const T prod = a.val[eb + e] * xk;
                     acc = acc + prod;
                 }
@@ -583,7 +591,7 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
         for (int k = tid; k < nx; k += kTileThreads) {
             const int c = a.ext_src[xb + k];
             T v = a.out[c];
-            if (is_sentinel(v)) v = load_ready<T, 2>(a.out + c, a.hang);
+            if (is_sentinel(v)) v = load_ready<T, 1>(a.out + c, a.hang);
             xs[nr + k] = v;
         }
         __syncthreads();
