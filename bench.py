@@ -85,6 +85,56 @@ def measured_traffic(cls: str):
     return None
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate of this GPU (bytes read + bytes written per second, GB/s):
+    the measured counterpart of the nameplate HBM peak."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    return 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+
+
+def _cpu_worker(cfg, rank, procs, seconds, q):
+    """One process of cpu_all_cores: regenerates the sequence (CPU only, no GPU use) and runs
+    the oracle's direct method on systems rank, rank + procs, ... for about `seconds`."""
+    sys.path.insert(0, ROOT)
+    import kkt_synth as ks
+    import oracle
+    pattern = ks.make_pattern(cfg)
+    nsys = ks.CONFIGS[cfg]["steps"]
+    Q = oracle.order(pattern.rowptr, pattern.colidx)
+    done, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        v, b = pattern.system(1 + (rank + done * procs) % nsys)
+        oracle.direct_solve(pattern.rowptr, pattern.colidx, v, b, Q=Q)
+        done += 1
+    q.put((done, time.perf_counter() - t0))
+
+
+def cpu_all_cores(cfg, seconds, procs):
+    """The oracle's direct method in `procs` fresh processes (spawned, so none inherits this
+    process's GPU state), each solving its share of the sequence's systems for about
+    `seconds`: throughput for independent systems, which a sequence whose next system
+    depends on this solution cannot use.  Returns (solves, wall seconds of the slowest)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    q = ctx.Queue()
+    ps = [ctx.Process(target=_cpu_worker, args=(cfg, r, procs, seconds, q)) for r in range(procs)]
+    for p_ in ps:
+        p_.start()
+    res = [q.get() for _ in ps]
+    for p_ in ps:
+        p_.join()
+    return sum(d for d, _ in res), max(t for _, t in res)
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -100,7 +150,7 @@ WORKLOADS = {1: ("kkt_single_7k", 10), 2: ("kkt_sequence_60k", 10), 3: ("kkt_seq
 
 
 def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, restart=10, gram_schmidt=0,
-            tile_lds_kib=0):
+            tile_lds_kib=0, cold_steps=0):
     dev = torch.device("cuda:0")
     v1, _ = systems[0]
     t0 = time.perf_counter()
@@ -148,6 +198,24 @@ def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, resta
     if profile:
         times = s.kernel_times()
         s.set_profiling(False)
+    # cold-cache leg (not part of `value`): before each step a 1 GiB device copy evicts the
+    # 4 MiB L2s and the 256 MiB MALL; the step itself is timed with events as above
+    cold = None
+    if cold_steps > 0:
+        flush_src = torch.ones((1 << 30) // 8, dtype=torch.float64, device=dev)
+        flush_dst = torch.empty_like(flush_src)
+        cold = []
+        for i in range(cold_steps):
+            k = (warmup + i) % M
+            flush_dst.copy_(flush_src)
+            a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            s.refactor(vals[k])
+            s.solve(rhs[k], x, allow_noconv=True)
+            b_.record()
+            b_.synchronize()
+            cold.append(a.elapsed_time(b_))
+        del flush_src, flush_dst
     # solutions of every system of the sequence, after the timed region (for the comparison
     # with the CPU baseline's solutions)
     xs = []
@@ -156,7 +224,7 @@ def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, resta
         s.solve(rhs[k], x, allow_noconv=True)
         xs.append(x.cpu().numpy().copy())
     return dict(solver=s, analysis_s=analysis_s, wall=wall, lat=lat, infos=infos, times=times,
-                breakdown=breakdown, dominant=dom, xs=xs)
+                breakdown=breakdown, dominant=dom, xs=xs, cold=cold)
 
 
 def cpu_baseline(pattern, systems, budget_s, gpu_xs=None):
@@ -277,6 +345,10 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=10)
     ap.add_argument("--gram-schmidt", choices=["cgs2", "dcgs2"], default="cgs2",
                     help="Arnoldi orthogonalization: CGS2 (default) or delayed CGS2 (one reduction per step)")
+    ap.add_argument("--cold-steps", type=int, default=10,
+                    help="steps timed after a 1 GiB cache flush each (reported apart from value)")
+    ap.add_argument("--cpu-procs", type=int, default=min(16, os.cpu_count() or 1),
+                    help="also time the oracle in this many independent processes (0: skip)")
     ap.add_argument("--tile-lds-kib", type=int, default=0,
                     help="LDS budget of a triangular-solve tile in KiB (0: the library default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -334,7 +406,8 @@ def main():
     wname, restart = WORKLOADS[cfg]
     gs = P.GS_DCGS2 if args.gram_schmidt == "dcgs2" else P.GS_CGS2
     r64 = run_gpu(P, torch, pattern, systems, args.steps, args.warmup, P.PREC_FP64, not args.no_profile, restart, gs,
-                  args.tile_lds_kib)
+                  args.tile_lds_kib, args.cold_steps)
+    copy_gbs = copy_bandwidth(torch)
     ai = r64["solver"].info()
     print("fp64 done: %.1f ms/step" % (1e3 * r64["wall"] / args.steps), file=sys.stderr, flush=True)
     rmx = None
@@ -364,6 +437,10 @@ def main():
                    "tile_lds_kib": args.tile_lds_kib},
         "p50_ms": percentile(r64["lat"], 50),
         "p99_ms": percentile(r64["lat"], 99),
+        "cold_cache": None if not r64["cold"] else {
+            "steps": len(r64["cold"]), "p50_ms": percentile(r64["cold"], 50), "p99_ms": percentile(r64["cold"], 99),
+            "solves_per_s_from_mean": 1e3 / float(np.mean(r64["cold"])),
+            "flush": "1 GiB device copy before each step (L2s and MALL evicted)"},
         "max_nrbe": max(i["nrbe"] for i in infos),
         "all_converged": all(i["converged"] == 1 for i in infos),
         "mean_iterations": float(np.mean([i["iterations"] for i in infos])),
@@ -393,7 +470,20 @@ def main():
         traffic = measured_traffic(dom) if cfg == 2 else None
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per}
+                           "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per,
+                           "measured_copy_peak": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs}
+        # the second floor: dependent levels, each paid in sequence whatever the bandwidth
+        lv = {"refactor": ai["levels_refactor"], "trsv_l": ai["levels_l"], "trsv_u": ai["levels_u"]}
+        out["dependency_floor"] = {
+            "levels": lv,
+            "us_per_level": {c: bd[c][1] / max(1, bd[c][0]) * 1e3 / lv[c] for c in lv if bd[c][0] > 0},
+            "note": "average launch time / DAG levels of that launch; the solves and the refactorization are "
+                    "bound by this chain, not by HBM bandwidth"}
+    if not args.no_cpu and args.cpu_procs > 0:
+        done_p, wall_p = cpu_all_cores(cfg, args.cpu_seconds / 2, args.cpu_procs)
+        out["cpu_all_cores"] = {"value": done_p / wall_p, "unit": "solves/s", "processes": args.cpu_procs,
+                                "kind": "oracle", "note": "independent systems, one per process at a time; "
+                                "a sequence whose next system needs this solution cannot use it"}
     if not args.no_cpu:
         done, el, cmp = cpu_baseline(pattern, systems, args.cpu_seconds, r64["xs"])
         out["cpu_baseline"] = {"value": done / el, "unit": "solves/s", "cores": 1, "kind": "oracle",

@@ -544,3 +544,29 @@ def test_delayed_cgs2_restarts_match_oracle(dev, R):
     assert info["converged"] == 1 and io["converged"]
     assert info["iterations"] == io["iters"] and info["cycles"] == io["cycles"]
     assert info["precond_applications"] == io["applications"]
+
+
+@pytest.mark.parametrize("mode", ["mixed", "error_fgmres"])
+def test_delayed_cgs2_other_paths(dev, mode):
+    # delayed CGS2 inside the FP32-preconditioned solve (with its FP64 fallback) and as the
+    # inner solver of Richardson on the error system: same acceptance as with CGS2
+    say("delayed cgs2 path", mode)
+    opts = dict(gram_schmidt=P.GS_DCGS2)
+    if mode == "mixed":
+        opts["precision"] = P.PREC_MIXED
+    else:
+        opts["ir_method"] = P.IR_ERROR_FGMRES
+    p, s, f = make(1, dev, **opts)
+    ref = P.Solver(p.rowptr, p.colidx, p.system(1)[0],
+                   **{k: v for k, v in opts.items() if k != "gram_schmidt"}).bind(dev)
+    for step in (2, 3):
+        v, b = p.system(step)
+        s.refactor(cuda(v, dev))
+        ref.refactor(cuda(v, dev))
+        x, info = s.solve(cuda(b, dev), allow_noconv=True)
+        xr, ir = ref.solve(cuda(b, dev), allow_noconv=True)
+        say("   step", step, "dcgs2", info["converged"], info["iterations"], "%.2e" % info["nrbe"],
+            "| cgs2", ir["converged"], ir["iterations"], "%.2e" % ir["nrbe"])
+        assert info["converged"] == ir["converged"]
+        m = oracle.metrics(p.rowptr, p.colidx, v, x.cpu().numpy(), b)
+        assert np.isfinite(m["nrbe"]) and m["nrbe"] <= max(10 * ir["nrbe"], 1e-12)

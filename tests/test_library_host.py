@@ -92,6 +92,40 @@ def test_errors():
     assert s.workspace_size() > 0
 
 
+@pytest.mark.parametrize("opt", [dict(tile_lds_kib=8), dict(tile_lds_kib=151), dict(gram_schmidt=2),
+                                 dict(restart=65), dict(residual=3)])
+def test_option_validation(opt):
+    p = ks.small_kkt(20, 10, 1)
+    v, _ = p.system(1)
+    with pytest.raises(P.KKTError) as e:
+        P.Solver(p.rowptr, p.colidx, v, **opt)
+    assert e.value.code == P.KKT_EINVAL
+
+
+def test_tile_budget_changes_the_schedule_not_the_factors():
+    # a larger LDS budget per solve tile packs more levels per tile (fewer windows); the
+    # factor patterns, pivots and refactorization levels do not depend on it
+    p = ks.make_pattern(1)
+    v, _ = p.system(1)
+    a = P.Solver(p.rowptr, p.colidx, v)
+    b = P.Solver(p.rowptr, p.colidx, v, tile_lds_kib=150)
+    ia, ib = a.info(), b.info()
+    for k in ("nnz_l", "nnz_u", "offdiag_pivots", "levels_refactor", "levels_l", "levels_u", "updates"):
+        assert ia[k] == ib[k], k
+    assert [np.array_equal(x, y) for x, y in zip(a.pattern(), b.pattern())] == [True] * 4
+    assert b.workspace_size() > 0 and a.workspace_size() > 0
+
+
+def test_profiling_mask_rejects_unknown_classes():
+    p = ks.small_kkt(20, 10, 1)
+    v, _ = p.system(1)
+    s = P.Solver(p.rowptr, p.colidx, v)
+    s.set_profiling(True, classes=["trsv_u"])
+    s.set_profiling(False)
+    from paper_2401_13926_amd import kkt as K
+    assert K.lib().kkt_set_profiling_mask(s._h, 1 << len(K.KERNEL_CLASSES)) == P.KKT_EINVAL
+
+
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_analysis_bit_exact_nested_dissection(cfg):
     p = ks.make_pattern(cfg)
