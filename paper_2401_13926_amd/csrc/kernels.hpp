@@ -9,7 +9,7 @@ namespace kkt {
 
 constexpr int kRestartMax = 64;        // largest supported FGMRES restart length
 constexpr int kStreamBlock = 256;      // threads per block of the streaming kernels
-constexpr int kStreamGridMax = 256;    // blocks of the streaming kernels (partial-sum rows)
+constexpr int kStreamGridMax = 1024;   // blocks of the streaming kernels (partial-sum rows)
 constexpr int kCoopBlock = 256;        // threads per block of the refactorization
 constexpr int kTileThreads = 256;      // threads per block of the triangular solves
 constexpr int kTileRows = 2048;        // rows of a multi-level solve tile (values in LDS)

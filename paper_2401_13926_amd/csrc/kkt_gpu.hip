@@ -756,11 +756,16 @@ __device__ __forceinline__ double block_col_get(const double *red, int t) {
     return s;
 }
 
-// Reduces columns 0..m-1 of buf (G <= kStreamBlock block rows) into out[] (shared): thread b
-// reads block b's row, per-column sums in a fixed tree (identical in every block).
+// Reduces columns 0..m-1 of buf (G <= kStreamGridMax block rows) into out[] (shared): thread
+// b adds rows b, b + kStreamBlock, ... in that order, then per-column sums in a fixed tree
+// (identical in every block).
 __device__ void reduce_cols(const double *buf, int G, int m, double *out, double *red) {
     const int b = threadIdx.x;
-    for (int t = 0; t < m; ++t) block_col_put(b < G ? buf[(int64_t)b * kPartStride + t] : 0.0, t, red);
+    for (int t = 0; t < m; ++t) {
+        double v = 0.0;
+        for (int r = b; r < G; r += kStreamBlock) v += buf[(int64_t)r * kPartStride + t];
+        block_col_put(v, t, red);
+    }
     __syncthreads();
     for (int t = threadIdx.x; t < m; t += blockDim.x) out[t] = block_col_get(red, t);
     __syncthreads();
@@ -1171,8 +1176,13 @@ __global__ void __launch_bounds__(kStreamBlock) k_resid_reduce(KrylovArgs a, int
     reduce_cols(partbuf(a, 0), G, 4, h, red);
     const double *buf = partbuf(a, 0);
     const int bb = threadIdx.x;
-    const double mr = block_max(bb < G ? buf[(int64_t)bb * kPartStride + 4] : 0.0, red);
-    const double mx = block_max(bb < G ? buf[(int64_t)bb * kPartStride + 5] : 0.0, red);
+    double mr_t = 0.0, mx_t = 0.0;
+    for (int r = bb; r < G; r += kStreamBlock) {
+        mr_t = fmax(mr_t, buf[(int64_t)r * kPartStride + 4]);
+        mx_t = fmax(mx_t, buf[(int64_t)r * kPartStride + 5]);
+    }
+    const double mr = block_max(mr_t, red);
+    const double mx = block_max(mx_t, red);
     if (threadIdx.x == 0) {
         a.ctl->rinf = mr;
         a.ctl->xinf = mx;
