@@ -265,16 +265,16 @@ template <typename T> __device__ __forceinline__ T unit_roundoff();
 template <> __device__ __forceinline__ double unit_roundoff<double>() { return 0x1p-53; }
 template <> __device__ __forceinline__ float unit_roundoff<float>() { return 0x1p-24f; }
 
-// Applies the update chain of column j to x (LDS or the column's own global storage): for
-// each source step k of U(:,j) in ascending order, x[relpos] -= L(:,k) * x[k].  The values
+// Applies the update chain of column j (its update positions start at rp) to x (LDS or the
+// column's own global storage): for each source step k of U(:,j) in ascending order,
+// x[relpos] -= L(:,k) * x[k].  The values
 // of L(:,k) come from the finished-value array; an entry still holding the sentinel is
 // polled until its column's wavefront has written it (no fences: every entry is its own
 // flag, written once with a coherent store).
 template <typename T, bool kLds>
-__device__ void refactor_chain(const RefactorArgs<T> &a, int j, int64_t c0, int nu, T *x) {
+__device__ void refactor_chain(const RefactorArgs<T> &a, int64_t rp, int64_t c0, int nu, T *x) {
     const int lane = threadIdx.x & 63;
     unsigned int *hang = &a.ctl->hang;
-    int64_t rp = a.relptr[j];
     for (int t0 = 0; t0 < nu; t0 += 64) {
         const int cnt = nu - t0 < 64 ? nu - t0 : 64;
         // lane s holds the metadata of source step t0 + s: its L part [l0, l0 + nl)
@@ -366,11 +366,23 @@ __global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
             if (cbeg >= a.n) break;
             cend = cbeg + 1;
         }
+        // metadata of the whole grab at once, lane l holding column cbeg + l (a grab has at
+        // most 16 columns): one dependent round trip per grab instead of two per column
+        int nu_l = 0;
+        long long c0_l = 0, end_l = 0, rp_l = 0;
+        if (lane < cend - cbeg) {
+            const int j_l = a.order[cbeg + lane];
+            c0_l = a.fp[j_l];
+            end_l = a.fp[j_l + 1];
+            nu_l = a.fdiag[j_l];
+            rp_l = a.relptr[j_l];
+        }
         for (int64_t t = cbeg; t < cend; ++t) {
-        const int j = a.order[t];
-        const int64_t c0 = a.fp[j];
-        const int len = (int)(a.fp[j + 1] - c0);
-        const int nu = a.fdiag[j];
+        const int src = (int)(t - cbeg);
+        const int64_t c0 = __shfl(c0_l, src, 64);
+        const int len = (int)(__shfl(end_l, src, 64) - c0);
+        const int nu = __shfl(nu_l, src, 64);
+        const int64_t rpj = __shfl(rp_l, src, 64);
         const bool in_lds = len <= kRefactorLds;
         T cm = 0;
         for (int e = lane; e < len; e += 64) {
@@ -381,8 +393,8 @@ __global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
         cm = wave_max(cm);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        if (in_lds) refactor_chain<T, true>(a, j, c0, nu, xs);
-        else refactor_chain<T, false>(a, j, c0, nu, a.F + c0);
+        if (in_lds) refactor_chain<T, true>(a, rpj, c0, nu, xs);
+        else refactor_chain<T, false>(a, rpj, c0, nu, a.F + c0);
         const T *x = in_lds ? xs : a.F + c0;
         T d = x[nu];
         const T ur = unit_roundoff<T>();
