@@ -109,6 +109,11 @@ typedef struct {
                                (0: 64).  Larger tiles hold more levels of the elimination tree,
                                so fewer cross-block hands-offs lie on a solve's critical path;
                                above 80 KiB one solve block occupies a compute unit alone */
+    int32_t narrow_columns; /* refactorization levels with at most this many columns are handed
+                               out one column per wavefront, wider ones 16 columns per grab
+                               (0: automatic, n/64 clamped to 1024..16384; measured best at
+                               60k, 500k and 2M unknowns); >= 1 otherwise */
+    int32_t reserved;
 } kkt_opts_t;
 
 enum { KKT_IR_FGMRES = 0, KKT_IR_RICHARDSON = 1, KKT_IR_ERROR_FGMRES = 2 };

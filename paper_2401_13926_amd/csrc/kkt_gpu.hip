@@ -292,26 +292,34 @@ __device__ void refactor_chain(const RefactorArgs<T> &a, int64_t rp, int64_t c0,
             if (lane >= o) off_l += v;
         }
         off_l -= nl_l;
-        // first 64 updates of step 0; each step prefetches the next step's
-        int64_t l0 = __shfl(l0_l, 0, 64);
-        int nl = __shfl(nl_l, 0, 64);
-        int64_t ro = rp + __shfl(off_l, 0, 64);
-        T lv = lane < nl ? a.Ld[l0 + lane] : T(0);
-        int pos = lane < nl ? a.relpos[ro + lane] : 0;
-        for (int s = 0; s < cnt; ++s) {
-            int64_t l0n = 0, ron = 0;
-            int nln = 0;
-            T lvn = T(0);
-            int posn = 0;
-            if (s + 1 < cnt) {
-                l0n = __shfl(l0_l, s + 1, 64);
-                nln = __shfl(nl_l, s + 1, 64);
-                ron = rp + __shfl(off_l, s + 1, 64);
-                if (lane < nln) {
-                    lvn = a.Ld[l0n + lane];
-                    posn = a.relpos[ron + lane];
+        // first 64 updates of a step: its L values and positions are loaded two steps ahead
+        // (two dependent loads in flight per lane while a step is applied)
+        auto fetch = [&](int st, int64_t &l0x, int &nlx, int64_t &rox, T &lvx, int &posx) {
+            l0x = 0;
+            nlx = 0;
+            rox = 0;
+            lvx = T(0);
+            posx = 0;
+            if (st < cnt) {
+                l0x = __shfl(l0_l, st, 64);
+                nlx = __shfl(nl_l, st, 64);
+                rox = rp + __shfl(off_l, st, 64);
+                if (lane < nlx) {
+                    lvx = a.Ld[l0x + lane];
+                    posx = a.relpos[rox + lane];
                 }
             }
+        };
+        int64_t l0, ro, l0n, ron;
+        int nl, pos, nln, posn;
+        T lv, lvn;
+        fetch(0, l0, nl, ro, lv, pos);
+        fetch(1, l0n, nln, ron, lvn, posn);
+        for (int s = 0; s < cnt; ++s) {
+            int64_t l0nn, ronn;
+            int nlnn, posnn;
+            T lvnn;
+            fetch(s + 2, l0nn, nlnn, ronn, lvnn, posnn);
             if (lane < nl && is_sentinel(lv)) lv = load_ready(a.Ld + l0 + lane, hang);
             const T u = x[t0 + s];
             if (lane < nl) {
@@ -333,6 +341,11 @@ __device__ void refactor_chain(const RefactorArgs<T> &a, int64_t rp, int64_t c0,
             ro = ron;
             lv = lvn;
             pos = posn;
+            l0n = l0nn;
+            nln = nlnn;
+            ron = ronn;
+            lvn = lvnn;
+            posn = posnn;
         }
         rp += __shfl(off_l + nl_l, cnt - 1, 64);
     }
@@ -1925,7 +1938,7 @@ using namespace kkt;
 namespace kkt {
 namespace {
 
-AnalysisOptions analysis_options(const kkt_opts_t &o) {
+AnalysisOptions analysis_options(const kkt_opts_t &o, int64_t n) {
     AnalysisOptions ao;
     ao.ordering = o.ordering == KKT_ORDER_ND ? ORDER_ND : ORDER_MD;
     ao.nd_leaf = o.nd_leaf;
@@ -1934,6 +1947,15 @@ AnalysisOptions analysis_options(const kkt_opts_t &o) {
     ao.tile_rows = kTileRows;
     ao.tile_lds = o.tile_lds_kib > 0 ? o.tile_lds_kib * 1024 : kTileLds;
     ao.dense_reserve_l = ao.tile_lds / 4;
+    // Wide levels go 16 columns per grab, narrow ones a column at a time.  A grab's columns
+    // run in sequence on one wavefront, which only pays while their sources are long done
+    // (the leaves); past that, a source queued behind others in someone's grab delays every
+    // column above it.  The width where this turns was measured to grow with n: 1,024 best at
+    // 60k unknowns, ~8,192 at 500k and 8,192-16,384 at 2M (refactorization 6.7 -> 2.8 ms and
+    // 19.3 -> 7.5 ms against a fixed 1,024).
+    ao.narrow_columns = o.narrow_columns > 0
+                            ? o.narrow_columns
+                            : (int)std::min<int64_t>(16384, std::max<int64_t>(1024, n / 64));
     return ao;
 }
 
@@ -1946,7 +1968,7 @@ kkt_status_t repivot_impl(kkt_handle_t h, hipStream_t s) {
     std::vector<double> vals(old.nnz);
     KKT_HIP(h, hipMemcpyAsync(vals.data(), h->d.kval, old.nnz * sizeof(double), hipMemcpyDeviceToHost, s));
     KKT_HIP(h, hipStreamSynchronize(s));
-    AnalysisOptions ao = analysis_options(h->opts);
+    AnalysisOptions ao = analysis_options(h->opts, old.n);
     const std::vector<int32_t> q = old.q;
     ao.fixed_order = q.data();
     Analysis na;
@@ -1980,6 +2002,7 @@ extern "C" {
 
 void kkt_opts_default(kkt_opts_t *o) {
     if (!o) return;
+    *o = kkt_opts_t{};  // every field not set below is 0 (tile_lds_kib, narrow_columns: automatic)
     o->ordering = KKT_ORDER_MD;
     o->nd_leaf = 64;
     o->pivot_tau = 0.1;
@@ -2026,7 +2049,11 @@ kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowpt
         delete h;
         return fail(nullptr, KKT_EINVAL, "tile_lds_kib must be 0 or in 16..150");
     }
-    AnalysisOptions ao = analysis_options(h->opts);
+    if (h->opts.narrow_columns < 0) {
+        delete h;
+        return fail(nullptr, KKT_EINVAL, "narrow_columns must be >= 0");
+    }
+    AnalysisOptions ao = analysis_options(h->opts, n);
     h->tile_lds = (size_t)ao.tile_lds;
     std::string msg;
     int rc = analyze(ao, n, rowptr, colidx, values_first, h->an, &msg);

@@ -93,7 +93,7 @@ def test_errors():
 
 
 @pytest.mark.parametrize("opt", [dict(tile_lds_kib=8), dict(tile_lds_kib=151), dict(gram_schmidt=2),
-                                 dict(restart=65), dict(residual=3)])
+                                 dict(restart=65), dict(residual=3), dict(narrow_columns=-1)])
 def test_option_validation(opt):
     p = ks.small_kkt(20, 10, 1)
     v, _ = p.system(1)
@@ -114,6 +114,19 @@ def test_tile_budget_changes_the_schedule_not_the_factors():
         assert ia[k] == ib[k], k
     assert [np.array_equal(x, y) for x, y in zip(a.pattern(), b.pattern())] == [True] * 4
     assert b.workspace_size() > 0 and a.workspace_size() > 0
+
+
+def test_narrow_level_threshold_keeps_the_factors():
+    # the hand-out threshold of the refactorization changes only which levels go a column at a
+    # time; patterns, pivots and the level structure are the same
+    p = ks.make_pattern(1)
+    v, _ = p.system(1)
+    a = P.Solver(p.rowptr, p.colidx, v)
+    b = P.Solver(p.rowptr, p.colidx, v, narrow_columns=1)
+    c = P.Solver(p.rowptr, p.colidx, v, narrow_columns=1 << 30)
+    for s in (b, c):
+        assert s.info()["levels_refactor"] == a.info()["levels_refactor"]
+        assert all(np.array_equal(x, y) for x, y in zip(a.pattern(), s.pattern()))
 
 
 def test_profiling_mask_rejects_unknown_classes():
