@@ -1554,9 +1554,10 @@ int stream_blocks(int64_t n) {
 }
 
 unsigned int work_chunk(int64_t items, int waves) {
-    // about four grabs per wavefront, at most 16 items per grab
+    // about four grabs per wavefront, at most 8 items per grab (refactorization at 500k:
+    // 2.62 ms with grabs of 8 against 2.84 with 16; 2M within 1 %; 60k uses 4 either way)
     const int64_t c = items / (4 * (int64_t)std::max(waves, 1));
-    return (unsigned int)std::max<int64_t>(1, std::min<int64_t>(16, c));
+    return (unsigned int)std::max<int64_t>(1, std::min<int64_t>(8, c));
 }
 
 template <typename T>
