@@ -110,9 +110,10 @@ typedef struct {
                                so fewer cross-block hands-offs lie on a solve's critical path;
                                above 80 KiB one solve block occupies a compute unit alone */
     int32_t narrow_columns; /* refactorization levels with at most this many columns are handed
-                               out one column per wavefront, wider ones 16 columns per grab
-                               (0: automatic, n/64 clamped to 1024..16384; measured best at
-                               60k, 500k and 2M unknowns); >= 1 otherwise */
+                               out one column per wavefront, wider ones up to 8 columns per
+                               grab (0: automatic, n/64 clamped to 1024..16384; measured best
+                               at 60k, 500k and 2M unknowns); negative values are rejected
+                               (KKT_EINVAL).  The factors do not depend on it. */
     int32_t reserved;
 } kkt_opts_t;
 
