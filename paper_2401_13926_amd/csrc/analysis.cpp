@@ -884,6 +884,8 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
         for (int64_t j = 0; j < n; ++j) a.col_order[j] = (int32_t)j;
         std::stable_sort(a.col_order.begin(), a.col_order.end(),
                          [&](int32_t x, int32_t y) { return level[x] < level[y]; });
+        a.col_level.resize(n);
+        for (int64_t t = 0; t < n; ++t) a.col_level[t] = (int32_t)level[a.col_order[t]];
         a.levels_refactor = n ? 1 + *std::max_element(level.begin(), level.end()) : 0;
         std::vector<int64_t> width(a.levels_refactor + 1, 0);
         for (int64_t j = 0; j < n; ++j) ++width[level[j]];

@@ -114,6 +114,7 @@ struct Analysis {
 
     // Refactorization schedule: columns sorted by (DAG level, index).
     std::vector<int32_t> col_order;
+    std::vector<int32_t> col_level;  // DAG level of each col_order position (non-decreasing)
     int64_t levels_refactor = 0;
     // Columns at col_order positions >= refactor_split belong to narrow levels (few columns
     // each, mostly a dependency chain): they are handed out one at a time so that each starts

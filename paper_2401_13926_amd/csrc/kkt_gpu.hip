@@ -251,6 +251,7 @@ template <typename T> struct RefactorArgs {
     const int64_t *relptr;
     const int32_t *relpos;
     const int32_t *order;
+    const int32_t *clev;  // level of each order position
     const int32_t *f2t;
     T *F;                // factor values (ingested on entry, final on exit)
     T *Tv;               // solve layout copy
@@ -351,8 +352,95 @@ __device__ void refactor_chain(const RefactorArgs<T> &a, int64_t rp, int64_t c0,
     }
 }
 
+// Small columns of one dependency level, run side by side: group g of 16 lanes takes column
+// src0 + g (g < b <= 4) with at most kGroupLen entries, staged in its quarter of the
+// wavefront's LDS.  Each column gets the operations of the one-column path in the same order
+// (staging and column max, updates in ascending source step, guard, division, publication),
+// so the factors are the same bits.  Columns of one level never read each other's values, so
+// no group waits for another group of its own wavefront.
+constexpr int kGroupLanes = 16;
+constexpr int kGroups = 64 / kGroupLanes;
+constexpr int kGroupLen = 32;
+static_assert(kGroupLen <= kRefactorLds / kGroups, "a group's column fits its LDS quarter");
+
 template <typename T>
-__global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
+__device__ void refactor_group(const RefactorArgs<T> &a, T *xs_wave, int src0, int b, long long c0_l,
+                               long long end_l, int nu_l, long long rp_l) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, gl = lane & 15;
+    const bool act = g < b;
+    const int src = src0 + (act ? g : 0);
+    const int64_t c0 = __shfl(c0_l, src, 64);
+    const int64_t endc = __shfl(end_l, src, 64);
+    const int nus = __shfl(nu_l, src, 64);
+    int64_t rp = __shfl(rp_l, src, 64);
+    const int len = act ? (int)(endc - c0) : 0;
+    const int nu = act ? nus : 0;
+    T *x = xs_wave + g * (kRefactorLds / kGroups);
+    unsigned int *hang = &a.ctl->hang;
+    T cm = 0;
+    for (int e = gl; e < len; e += kGroupLanes) {
+        const T v = a.F[c0 + e];
+        x[e] = v;
+        cm = fmax(cm, fabs(v));
+    }
+    for (int o = kGroupLanes / 2; o > 0; o >>= 1) cm = fmax(cm, __shfl_xor(cm, o, kGroupLanes));
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int t0 = 0; t0 < nu; t0 += kGroupLanes) {
+        const int cnt = nu - t0 < kGroupLanes ? nu - t0 : kGroupLanes;
+        int64_t l0_l = 0;
+        int nl_l = 0;
+        if (gl < cnt) {
+            const int k = a.fi[c0 + t0 + gl];
+            l0_l = a.fp[k] + a.fdiag[k] + 1;
+            nl_l = (int)(a.fp[k + 1] - l0_l);
+        }
+        int off_l = nl_l;
+        for (int o = 1; o < kGroupLanes; o <<= 1) {
+            const int v = __shfl_up(off_l, o, kGroupLanes);
+            if (gl >= o) off_l += v;
+        }
+        off_l -= nl_l;
+        for (int st = 0; st < cnt; ++st) {
+            const int64_t l0 = __shfl(l0_l, st, kGroupLanes);
+            const int nl = __shfl(nl_l, st, kGroupLanes);
+            const int64_t ro = rp + __shfl(off_l, st, kGroupLanes);
+            const T u = x[t0 + st];
+            for (int e = gl; e < nl; e += kGroupLanes) {
+                T lv = a.Ld[l0 + e];
+                if (is_sentinel(lv)) lv = load_ready(a.Ld + l0 + e, hang);
+                const int p2 = a.relpos[ro + e];
+                const T prod = lv * u;
+                x[p2] = x[p2] - prod;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        rp += __shfl(off_l + nl_l, cnt - 1, kGroupLanes);
+    }
+    if (!act) return;
+    T d = x[nu];
+    const T ur = unit_roundoff<T>();
+    const T cmx = cm > T(0) ? cm : T(1);
+    if (!(fabs(d) > ur * cmx) || !isfinite(d)) {
+        d = (d < T(0) ? T(-1) : T(1)) * ur * cmx;
+        if (gl == 0) {
+            atomicAdd(&a.ctl->nguard, 1ull);
+            if (a.guard_fail_policy) atomicOr(&a.ctl->guard_fail, 1u);
+        }
+    }
+    for (int e = nu + 1 + gl; e < len; e += kGroupLanes) store_ready(a.Ld + c0 + e, x[e] / d);
+    for (int e = gl; e < len; e += kGroupLanes) {
+        T v = x[e];
+        if (e == nu) v = d;
+        else if (e > nu) v = v / d;
+        a.F[c0 + e] = v;
+        a.Tv[a.f2t[c0 + e]] = v;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(3))) k_refactor(RefactorArgs<T> a) {
     __shared__ T lds[(kCoopBlock / 64) * kRefactorLds];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     T *xs = lds + wid * kRefactorLds;
@@ -381,17 +469,35 @@ __global__ void __launch_bounds__(kCoopBlock) k_refactor(RefactorArgs<T> a) {
         }
         // metadata of the whole grab at once, lane l holding column cbeg + l (a grab has at
         // most 16 columns): one dependent round trip per grab instead of two per column
-        int nu_l = 0;
+        int nu_l = 0, lev_l = -1;
         long long c0_l = 0, end_l = 0, rp_l = 0;
         if (lane < cend - cbeg) {
             const int j_l = a.order[cbeg + lane];
+            lev_l = a.clev[cbeg + lane];
             c0_l = a.fp[j_l];
             end_l = a.fp[j_l + 1];
             nu_l = a.fdiag[j_l];
             rp_l = a.relptr[j_l];
         }
-        for (int64_t t = cbeg; t < cend; ++t) {
+        for (int64_t t = cbeg; t < cend;) {
         const int src = (int)(t - cbeg);
+        {
+            // a run of small columns of one level goes to 16-lane groups, four at a time
+            const int lev0 = __shfl(lev_l, src, 64);
+            int b = 0;
+            while (b < kGroups && t + b < cend) {
+                const int sb = src + b;
+                const int lenb = (int)(__shfl(end_l, sb, 64) - __shfl(c0_l, sb, 64));
+                if (__shfl(lev_l, sb, 64) != lev0 || lenb > kGroupLen) break;
+                ++b;
+            }
+            if (b >= 2) {
+                refactor_group<T>(a, xs, src, b, c0_l, end_l, nu_l, rp_l);
+                t += b;
+                continue;
+            }
+        }
+        ++t;
         const int64_t c0 = __shfl(c0_l, src, 64);
         const int len = (int)(__shfl(end_l, src, 64) - c0);
         const int nu = __shfl(nu_l, src, 64);
@@ -1303,7 +1409,7 @@ thread_local std::string g_last_error;
 struct DevLayout {
     // structure
     int64_t *fp;
-    int32_t *fi, *fdiag, *order, *f2t;
+    int32_t *fi, *fdiag, *order, *clev, *f2t;
     int64_t *relptr, *fsrc;
     int32_t *relpos;
     int64_t *krp;
@@ -1449,7 +1555,7 @@ struct Planner {
 
 // Offsets of every array inside the workspace (also gives the total size).
 struct Offsets {
-    size_t fp, fi, fdiag, order, f2t, relptr, fsrc, relpos, krp, kci, l_rows, l_seg, l_tseg,
+    size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, krp, kci, l_rows, l_seg, l_tseg,
         l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, l_tden, l_sdof, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
         u_rent, u_tlds, u_tden, u_sdof, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
         z32, dv, rr, part, ctl, total;
@@ -1465,6 +1571,7 @@ Offsets plan(const kkt_handle_t h) {
     o.fi = p.take<int32_t>(f);
     o.fdiag = p.take<int32_t>(n);
     o.order = p.take<int32_t>(n);
+    o.clev = p.take<int32_t>(n);
     o.f2t = p.take<int32_t>(f);
     o.relptr = p.take<int64_t>(n + 1);
     o.fsrc = p.take<int64_t>(f);
@@ -1650,12 +1757,12 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
     e0 = prof_begin(h, KKT_K_REFACTOR, s);
     if (precision == KKT_PREC_MIXED) {
         const unsigned int chunk = work_chunk(a.n, h->grid_refactor32 * (kCoopBlock / 64));
-        RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F32, d.T32,
+        RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.F32, d.T32,
                               d.Ld32, chunk, h->an.refactor_split, h->opts.guard_policy, d.ctl};
         k_refactor<float><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r);
     } else {
         const unsigned int chunk = work_chunk(a.n, h->grid_refactor64 * (kCoopBlock / 64));
-        RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.f2t, d.F64, d.T64,
+        RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.F64, d.T64,
                                d.Ld64, chunk, h->an.refactor_split, h->opts.guard_policy, d.ctl};
         k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r);
     }
@@ -2140,6 +2247,7 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.fi = (int32_t *)(b + o.fi);
     d.fdiag = (int32_t *)(b + o.fdiag);
     d.order = (int32_t *)(b + o.order);
+    d.clev = (int32_t *)(b + o.clev);
     d.f2t = (int32_t *)(b + o.f2t);
     d.relptr = (int64_t *)(b + o.relptr);
     d.fsrc = (int64_t *)(b + o.fsrc);
@@ -2193,6 +2301,7 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.fi, a.fi, s));
     KKT_HIP(h, up(b, o.fdiag, a.fdiag, s));
     KKT_HIP(h, up(b, o.order, a.col_order, s));
+    KKT_HIP(h, up(b, o.clev, a.col_level, s));
     KKT_HIP(h, up(b, o.f2t, a.f2t, s));
     KKT_HIP(h, up(b, o.relptr, a.relptr, s));
     KKT_HIP(h, up(b, o.fsrc, a.fsrc, s));
