@@ -352,9 +352,9 @@ __device__ void refactor_chain(const RefactorArgs<T> &a, int64_t rp, int64_t c0,
     }
 }
 
-// Small columns of one dependency level, run side by side: group g of 16 lanes takes column
-// src0 + g (g < b <= 4) with at most kGroupLen entries, staged in its quarter of the
-// wavefront's LDS.  Each column gets the operations of the one-column path in the same order
+// Small columns of one dependency level, run side by side: group g of kGroupLanes lanes takes
+// column src0 + g (g < b <= kGroups) with at most kGroupLen entries, staged in its share of
+// the wavefront's LDS.  Each column gets the operations of the one-column path in the same order
 // (staging and column max, updates in ascending source step, guard, division, publication),
 // so the factors are the same bits.  Columns of one level never read each other's values, so
 // no group waits for another group of its own wavefront.
@@ -366,7 +366,7 @@ static_assert(kGroupLen <= kRefactorLds / kGroups, "a group's column fits its LD
 template <typename T>
 __device__ void refactor_group(const RefactorArgs<T> &a, T *xs_wave, int src0, int b, long long c0_l,
                                long long end_l, int nu_l, long long rp_l) {
-    const int lane = threadIdx.x & 63, g = lane >> 4, gl = lane & 15;
+    const int lane = threadIdx.x & 63, g = lane / kGroupLanes, gl = lane % kGroupLanes;
     const bool act = g < b;
     const int src = src0 + (act ? g : 0);
     const int64_t c0 = __shfl(c0_l, src, 64);
@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu
         for (int64_t t = cbeg; t < cend;) {
         const int src = (int)(t - cbeg);
         {
-            // a run of small columns of one level goes to 16-lane groups, four at a time
+            // a run of small columns of one level goes to lane groups, kGroups at a time
             const int lev0 = __shfl(lev_l, src, 64);
             int b = 0;
             while (b < kGroups && t + b < cend) {
