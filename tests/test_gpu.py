@@ -61,6 +61,21 @@ def test_refactor_fp64_bit_exact(dev, cfg):
             assert np.array_equal(lx, f.Lx) and np.array_equal(ux, f.Ux)
 
 
+@pytest.mark.parametrize("narrow", [1, 1 << 30])
+def test_refactor_handout_does_not_change_factors(dev, narrow):
+    # every column handed out alone (narrow = 1: no lane groups either), or every level in
+    # grabs with small same-level columns run by lane groups (narrow = 2^30): the same bits
+    say("refactor hand-out narrow_columns", narrow)
+    p, s, f = make(2, dev, narrow_columns=narrow)
+    for step in (2, 3):
+        v, _ = p.system(step)
+        s.refactor(cuda(v, dev))
+        torch.cuda.synchronize()
+        lx, ux = s.factor_values(0)
+        olx, oux, _ = f.refactor64(p.rowptr, p.colidx, v)
+        assert np.array_equal(lx, olx) and np.array_equal(ux, oux), "factors differ at step %d" % step
+
+
 def test_refactor_fp32_bit_exact(dev):
     say("refactor fp32 config 1")
     p, s, f = make(1, dev, precision=P.PREC_MIXED)
