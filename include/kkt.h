@@ -61,7 +61,13 @@ typedef struct {
                                dissection */
     int32_t nd_leaf;        /* nested dissection: sets of <= nd_leaf vertices are not dissected (64) */
     double pivot_tau;       /* threshold partial pivoting: keep the diagonal row when
-                               |x_c| >= tau * max |x_i| (0.1) */
+                               |x_c| >= tau * max |x_i| (1e-10).  K_k of eq. (kktlinear) with a
+                               dual regularization -delta I (delta > 0) is quasi-definite, so every
+                               diagonal pivot of a symmetric ordering is nonzero; a small tau keeps
+                               them, gives P = Q (symmetric factor patterns, least fill) and a
+                               pivot sequence that stays valid when D is redrawn.  tau = 0.1
+                               (textbook threshold pivoting) picks off-diagonal pivots from system
+                               1's D that later systems no longer support. */
     int32_t restart;        /* FGMRES restart length R (10, Section 4.1.1) */
     int32_t max_restarts;   /* cycles after the first (20) */
     double delta_tol;       /* refine/stop tolerance delta_tol (1e-14, Section 4.1.2) */

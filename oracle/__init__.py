@@ -56,8 +56,8 @@ def lib():
         L.or_refactor64.argtypes = [C.c_void_p, i64p, i32p, f64p, C.c_int, f64p, f64p, i64p, i64p]
         L.or_refactor32.argtypes = [C.c_void_p, i64p, i32p, f64p, C.c_int, f32p, f32p, i64p, i64p]
         L.or_solve_with.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p]
-        L.or_arnoldi.argtypes = [C.c_void_p, f64p, f64p, i64p, i32p, f64p, f64p, C.c_int, C.c_int, f64p,
-                                 f64p, f64p]
+        L.or_arnoldi.argtypes = [C.c_void_p, f64p, f64p, f32p, f32p, C.c_int, i64p, i32p, f64p, f64p,
+                                 C.c_int, C.c_int, f64p, f64p, f64p]
         L.or_solve_with32.argtypes = [C.c_void_p, f32p, f32p, f64p, f64p]
         L.or_residual.argtypes = [i64, i64p, i32p, f64p, f64p, f64p, f64p]
         L.or_residual_dd.argtypes = [i64, i64p, i32p, f64p, f64p, f64p, f64p]
@@ -115,7 +115,7 @@ def order(rowptr, colidx, method: str = "md", leaf: int = 64) -> np.ndarray:
 class LU:
     """Pivoted factors of K(:,Q): P K Q = L U (see or_factor in oracle.c)."""
 
-    def __init__(self, rowptr, colidx, values, Q=None, tau=0.1):
+    def __init__(self, rowptr, colidx, values, Q=None, tau=1e-10):
         rp, ci, v = _csr(rowptr, colidx, values)
         n = rp.size - 1
         if Q is None:
@@ -241,20 +241,25 @@ class LU:
                        converged=bool(info[4]), nrbe0=info[5], est=info[6], true_resid=info[7],
                        applications=int(info[8]), hist=hist[:min(it, hist_cap)].copy())
 
-    def arnoldi(self, rowptr, colidx, values, r0, restart, gs="cgs2", Lx=None, Ux=None):
-        """One FGMRES Arnoldi cycle from r0 run to `restart` steps (see or_arnoldi).
+    def arnoldi(self, rowptr, colidx, values, r0, restart, gs="cgs2", Lx=None, Ux=None, Lx32=None, Ux32=None):
+        """One FGMRES Arnoldi cycle from r0 run to `restart` steps (see or_arnoldi); with
+        Lx32/Ux32 the preconditioner is the binary32 solve with those FP32 factors.
         Returns (V, Z, Hbar, k): columns of V and Z are basis vectors, Hbar is unrotated."""
         if gs not in ("cgs2", "dcgs2"):
             raise ValueError("gs must be 'cgs2' or 'dcgs2'")
         rp, ci, v = _csr(rowptr, colidx, values)
         Lx = self.Lx if Lx is None else np.ascontiguousarray(Lx, np.float64)
         Ux = self.Ux if Ux is None else np.ascontiguousarray(Ux, np.float64)
+        prec = 1 if Lx32 is not None else 0
+        l32 = np.zeros(1, np.float32) if Lx32 is None else np.ascontiguousarray(Lx32, np.float32)
+        u32 = np.zeros(1, np.float32) if Ux32 is None else np.ascontiguousarray(Ux32, np.float32)
         r0 = np.ascontiguousarray(r0, np.float64)
         R = int(restart)
         V = np.zeros((R + 1, self.n))
         Z = np.zeros((R, self.n))
         H = np.zeros((R, R + 1))
-        k = lib().or_arnoldi(self._h, _p(Lx, C.c_double), _p(Ux, C.c_double), _p(rp, C.c_int64),
+        k = lib().or_arnoldi(self._h, _p(Lx, C.c_double), _p(Ux, C.c_double), _p(l32, C.c_float),
+                             _p(u32, C.c_float), prec, _p(rp, C.c_int64),
                              _p(ci, C.c_int32), _p(v, C.c_double), _p(r0, C.c_double), R,
                              1 if gs == "dcgs2" else 0, _p(V, C.c_double), _p(Z, C.c_double),
                              _p(H, C.c_double))
@@ -300,8 +305,10 @@ def norm_inf(rowptr, values) -> float:
     return lib().or_norm_inf_mat(rp.size - 1, _p(rp, C.c_int64), _p(v, C.c_double))
 
 
-def direct_solve(rowptr, colidx, values, b, Q, tau=0.1):
-    """Plain direct method (fresh pivoting, ordering reused): the CPU baseline solve."""
+def direct_solve(rowptr, colidx, values, b, Q, tau=1e-10):
+    """Plain direct method (fresh pivoting with threshold tau, ordering reused): the CPU
+    baseline solve.  The default tau = 1e-10 keeps the diagonal pivots of a quasi-definite
+    K (the library's default); tau = 0.1 is textbook threshold partial pivoting."""
     f = LU(rowptr, colidx, values, Q=Q, tau=tau)
     return f.solve(b), f
 

@@ -49,11 +49,15 @@ def dense_lu(A: np.ndarray, Q: np.ndarray, tau: float):
     return prow, Lfull, Ufull
 
 
-def dense_solve(prow, Lfull, Ufull, Q, b):
-    """x = Q U^-1 L^-1 P b, scalar loops over the dense factors."""
+def dense_solve(prow, Lfull, Ufull, Q, b, dtype=np.float64):
+    """x = Q U^-1 L^-1 P b, scalar loops over the dense factors, every operation in `dtype`
+    (b rounded to it first; float32 factors with dtype=np.float32 give a binary32 solve).
+    Returns float64."""
     n = b.size
-    w = b.astype(np.float64).copy()
-    z = np.zeros(n)
+    Lfull = np.asarray(Lfull).astype(dtype)
+    Ufull = np.asarray(Ufull).astype(dtype)
+    w = b.astype(dtype).copy()
+    z = np.zeros(n, dtype=dtype)
     for k in range(n):
         z[k] = w[prow[k]]
         w = w - Lfull[:, k] * z[k]
@@ -61,7 +65,7 @@ def dense_solve(prow, Lfull, Ufull, Q, b):
         z[j] = z[j] / Ufull[j, j]
         z[:j] = z[:j] - Ufull[:j, j] * z[j]
     x = np.zeros(n)
-    x[np.asarray(Q)] = z
+    x[np.asarray(Q)] = z.astype(np.float64)
     return x
 
 

@@ -1398,10 +1398,11 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
    Hessenberg matrix before rotation (column-major (R+1) x R) so that tests can check the
    Arnoldi relation K Z_k = V_{k+1} Hbar_k and the orthonormality of V.  gs: 0 CGS2, 1 DCGS2
    (whose last vector, v_k, is left after its first pass: the relation holds for k - 1
-   columns).  Returns k, the number of Hessenberg columns, or -1 on error. */
-int or_arnoldi(const or_lu_t *f, const double *Lx, const double *Ux, const int64_t *rp, const int32_t *ci,
-               const double *v, const double *r0, int R, int gs, double *Vout, double *Zout,
-               double *Hout) {
+   columns).  precision 1 applies the FP32 factors (Lx32, Ux32) in binary32, as
+   or_fgmres_ir does.  Returns k, the number of Hessenberg columns, or -1 on error. */
+int or_arnoldi(const or_lu_t *f, const double *Lx, const double *Ux, const float *Lx32, const float *Ux32,
+               int precision, const int64_t *rp, const int32_t *ci, const double *v, const double *r0, int R,
+               int gs, double *Vout, double *Zout, double *Hout) {
     const int64_t n = f->n;
     if (R < 1) return -1;
     fg_ws_t ws;
@@ -1433,10 +1434,10 @@ int or_arnoldi(const or_lu_t *f, const double *Lx, const double *Ux, const int64
         long applications = 0;
         int64_t nh = 0;
         if (gs == 1)
-            k = fgmres_cycle_dcgs2(&ws, f, Lx, Ux, NULL, NULL, 0, rp, ci, v, 0.0, &est, &applications,
+            k = fgmres_cycle_dcgs2(&ws, f, Lx, Ux, Lx32, Ux32, precision, rp, ci, v, 0.0, &est, &applications,
                                    NULL, &nh, 0);
         else
-            k = fgmres_cycle_cgs2(&ws, f, Lx, Ux, NULL, NULL, 0, rp, ci, v, 0.0, &est, &applications,
+            k = fgmres_cycle_cgs2(&ws, f, Lx, Ux, Lx32, Ux32, precision, rp, ci, v, 0.0, &est, &applications,
                                   NULL, &nh, 0);
     }
     free(ws.H); free(ws.cs); free(ws.sn); free(ws.g); free(ws.h); free(ws.h2); free(ws.c);

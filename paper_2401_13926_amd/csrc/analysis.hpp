@@ -14,7 +14,7 @@ struct AnalysisOptions {
     int ordering = ORDER_MD;     // exact minimum degree, or BFS nested dissection
     const int32_t *fixed_order = nullptr;  // when set: this column order (n entries) is used
     int64_t nd_leaf = 64;
-    double pivot_tau = 0.1;
+    double pivot_tau = 1e-10;
     int tile_threads = 256;      // threads of a triangular-solve block
     int tile_rows = 2048;        // rows of a tile at most
     int64_t tile_lds = 65536;    // LDS bytes of a staged tile at most (tile_lds_bytes)

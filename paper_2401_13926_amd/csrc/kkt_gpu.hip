@@ -2113,7 +2113,7 @@ void kkt_opts_default(kkt_opts_t *o) {
     *o = kkt_opts_t{};  // every field not set below is 0 (tile_lds_kib, narrow_columns: automatic)
     o->ordering = KKT_ORDER_MD;
     o->nd_leaf = 64;
-    o->pivot_tau = 0.1;
+    o->pivot_tau = 1e-10;
     o->restart = 10;
     o->max_restarts = 20;
     o->delta_tol = 1e-14;

@@ -41,7 +41,7 @@ def make(cfg_or_pattern, dev, **opts):
     p = cfg_or_pattern if isinstance(cfg_or_pattern, ks.KKTPattern) else ks.make_pattern(cfg_or_pattern)
     v1, _ = p.system(1)
     s = P.Solver(p.rowptr, p.colidx, v1, **opts).bind(dev)
-    f = oracle.LU(p.rowptr, p.colidx, v1, tau=opts.get("pivot_tau", 0.1))
+    f = oracle.LU(p.rowptr, p.colidx, v1, tau=opts.get("pivot_tau", P.default_opts().pivot_tau))
     return p, s, f
 
 

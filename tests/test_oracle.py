@@ -139,7 +139,7 @@ def test_order_is_permutation_and_reduces_fill():
 # ----------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("seed", range(8))
-@pytest.mark.parametrize("tau", [0.1, 1.0])
+@pytest.mark.parametrize("tau", [1e-10, 0.1, 1.0])
 def test_factor_matches_dense_bruteforce_kkt(seed, tau):
     p = ks.small_kkt(30 + 3 * seed, 20 + 2 * seed, seed)
     v, _ = p.system(1 + seed % 3)
@@ -240,7 +240,8 @@ def test_solve_matches_numpy_and_manufactured(seed):
     p = ks.small_kkt(80, 50, 30 + seed, dlog=(-2.0, 2.0))
     v, b = p.system(1)
     A = ks.to_dense(p.rowptr, p.colidx, v, p.N)
-    xs, f = oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=oracle.order(p.rowptr, p.colidx, leaf=8))
+    # threshold partial pivoting: the forward error of a backward-stable solve
+    xs, f = oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=oracle.order(p.rowptr, p.colidx, leaf=8), tau=0.1)
     xn = np.linalg.solve(A, b)
     kappa = np.linalg.cond(A, 1)
     assert np.linalg.norm(xs - xn) / np.linalg.norm(xn) <= 100 * np.finfo(float).eps * kappa
@@ -248,9 +249,15 @@ def test_solve_matches_numpy_and_manufactured(seed):
     bt = A @ xt
     xm = f.solve(bt)
     assert np.linalg.norm(xm - xt) / np.linalg.norm(xt) <= 100 * np.finfo(float).eps * kappa
-    # dense brute-force solve with the same factors is bit-identical
+    # dense brute-force solves with the same factors are bit-identical, for threshold
+    # pivoting and for the default diagonal-preferring threshold
     prow, Lf, Uf = dense.dense_lu(A, f.Q, 0.1)
+    assert np.array_equal(prow, f.prow)
     assert np.array_equal(dense.dense_solve(prow, Lf, Uf, f.Q, b), xs)
+    xd, g = oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=f.Q)
+    prow, Lf, Uf = dense.dense_lu(A, f.Q, 1e-10)
+    assert np.array_equal(prow, g.prow) and np.array_equal(prow, g.Q)   # diagonal pivots: P = Q
+    assert np.array_equal(dense.dense_solve(prow, Lf, Uf, f.Q, b), xd)
 
 
 def test_metrics_definitions_on_known_residual():
@@ -305,7 +312,8 @@ def test_refactor_matches_dense_static(seed):
     p = ks.small_kkt(40, 25, 60 + seed, dlog=(-1.0, 1.0))
     v1, _ = p.system(1)
     v2, _ = p.system(2)
-    f = oracle.LU(p.rowptr, p.colidx, v1, Q=oracle.order(p.rowptr, p.colidx, leaf=4))
+    # threshold pivoting keeps every FP32 static pivot clear of the guard
+    f = oracle.LU(p.rowptr, p.colidx, v1, Q=oracle.order(p.rowptr, p.colidx, leaf=4), tau=0.1)
     A2 = ks.to_dense(p.rowptr, p.colidx, v2, p.N)
     Lx, Ux, ng = f.refactor64(p.rowptr, p.colidx, v2)
     Lf, Uf = dense.dense_lu_static(A2, f.Q, f.prow, np.float64)
@@ -321,11 +329,10 @@ def test_refactor_matches_dense_static(seed):
     Ls32, Us32 = lu_to_dense(g)
     assert ng32 == 0
     assert np.array_equal(Ls32, Lf32.astype(np.float64)) and np.array_equal(Us32, Uf32.astype(np.float64))
-    # FP32 solve agrees with a float32 dense solve
+    # the FP32 solve is the binary32 substitution with these factors, bit for bit
     b = np.random.default_rng(seed).standard_normal(p.N)
     x32 = f.solve32(b, Lx32, Ux32)
-    xd = np.linalg.solve(A2, b)
-    assert np.linalg.norm(x32 - xd) / np.linalg.norm(xd) < 1e-3
+    assert np.array_equal(x32, dense.dense_solve(f.prow, Lf32, Uf32, f.Q, b, dtype=np.float32))
 
 
 def test_refactor_pivot_guard():
@@ -444,7 +451,10 @@ def test_fgmres_ir_exact_preconditioner_and_sequence():
     x, info = g.fgmres_ir(p2.rowptr, p2.colidx, w3, b3, Lx=Lx, Ux=Ux, restart=10, mode=1, eta=1e-14)
     m = oracle.metrics(p2.rowptr, p2.colidx, w3, x, b3)
     assert info["converged"] and 1 <= info["iters"] <= 30
-    assert m["nrbe"] <= 1e-12 and m["resid"] < 1e-3 * m0["resid"]
+    assert m["nrbe"] <= 1e-12 and m["resid"] < 0.1 * m0["resid"]
+    # down to the rounding floor of a backward-stable solve (threshold-pivoted, fresh)
+    xs, _ = oracle.direct_solve(p2.rowptr, p2.colidx, w3, b3, Q=g.Q, tau=0.1)
+    assert m["resid"] <= 10 * oracle.metrics(p2.rowptr, p2.colidx, w3, xs, b3)["resid"]
 
 
 # ----------------------------------------------------------------------------------------
@@ -643,7 +653,7 @@ def test_arnoldi_relation_and_orthonormal_basis(gs):
     p = ks.small_kkt(300, 200, 5, (-4.0, 4.0))
     v1, bk = p.system(1)
     v2 = v1 * (1.0 + 1e-6 * np.random.default_rng(11).standard_normal(v1.size))
-    f = oracle.LU(p.rowptr, p.colidx, v1)
+    f = oracle.LU(p.rowptr, p.colidx, v1, tau=0.1)   # threshold pivoting: small |L||U|
     nk = p.rowptr.size - 1
     K2 = sp.csr_matrix((v2, p.colidx, p.rowptr), shape=(nk, nk))
     K1 = sp.csr_matrix((v1, p.colidx, p.rowptr), shape=(nk, nk))
@@ -651,3 +661,134 @@ def test_arnoldi_relation_and_orthonormal_basis(gs):
     assert k == 10
     rel, orth, zr = _arnoldi_invariants(K2, K1, V, Z, H, k)
     assert rel <= 1e-12 and orth <= 1e-13 and zr <= 1e-11
+
+
+# ----------------------------------------------------------------------------------------
+# binary32 triangular solves and the FP32-preconditioned FGMRES cycle
+# ----------------------------------------------------------------------------------------
+
+def _fp32_static_factors(seed, n=50, perturb=0.0):
+    """A well-conditioned sparse matrix, its pivoted FP64 analysis, FP32 static-pivot
+    factors from the oracle and the same factors from the dense brute force; with perturb > 0
+    the factors are those of a matrix whose entries differ by that relative amount (an
+    inexact preconditioner)."""
+    A = random_sparse(n, 0.08, 700 + seed)
+    A[np.arange(n), np.arange(n)] += 6.0 * np.sign(A[np.arange(n), np.arange(n)] + 1e-300)
+    rp, ci, v = csr_of(A)
+    Q = np.random.default_rng(seed).permutation(n).astype(np.int32)
+    f = oracle.LU(rp, ci, v, Q=Q, tau=0.1)
+    v1 = v * (1.0 + perturb * np.random.default_rng(seed + 1).standard_normal(v.size))
+    Lx32, Ux32, ng = f.refactor32(rp, ci, v1)
+    assert ng == 0
+    A1 = sp.csr_matrix((v1, ci, rp), shape=(n, n)).toarray()
+    Lf32, Uf32 = dense.dense_lu_static(A1, f.Q, f.prow, np.float32)
+    return A, rp, ci, v, f, Lx32, Ux32, Lf32, Uf32
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_solve32_is_a_binary32_substitution(seed):
+    # or_solve_with32 rounds b to binary32 and substitutes in binary32: bit-identical to the
+    # dense float32 substitution with the same factors (and not to a binary64 one)
+    A, rp, ci, v, f, Lx32, Ux32, Lf32, Uf32 = _fp32_static_factors(seed)
+    b = np.random.default_rng(40 + seed).standard_normal(A.shape[0])
+    x = f.solve32(b, Lx32, Ux32)
+    x_d32 = dense.dense_solve(f.prow, Lf32, Uf32, f.Q, b, dtype=np.float32)
+    x_d64 = dense.dense_solve(f.prow, Lf32, Uf32, f.Q, b, dtype=np.float64)
+    assert np.array_equal(x, x_d32)
+    assert not np.array_equal(x, x_d64)
+
+
+@pytest.mark.parametrize("gs", ["cgs2", "dcgs2"])
+def test_fgmres_with_fp32_preconditioner(gs):
+    # precision 1: x0 and every z_j = M^-1 v_j are binary32 solves with the FP32 factors
+    # (bit-identical to the dense float32 substitution), and the cycle's update minimises
+    # the residual over x0 + span(Z) (flexible GMRES, Saad 1993)
+    A, rp, ci, v, f, Lx32, Ux32, Lf32, Uf32 = _fp32_static_factors(9, perturb=0.05)
+    n = A.shape[0]
+    K = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    b = np.random.default_rng(19).standard_normal(n)
+    x0 = dense.dense_solve(f.prow, Lf32, Uf32, f.Q, b, dtype=np.float32)
+    R = 3
+    x, info = f.fgmres_ir(rp, ci, v, b, Lx32=Lx32, Ux32=Ux32, restart=R, max_restarts=0, eta=1e-30, mode=1,
+                          gs=gs)
+    assert info["nrbe0"] == oracle.metrics(rp, ci, v, x0, b)["nrbe"]
+    r0 = oracle.residual(rp, ci, v, x0, b)
+    V, Z, H, k = f.arnoldi(rp, ci, v, r0, R, gs, Lx32=Lx32, Ux32=Ux32)
+    assert k == info["iters"] == R
+    m = k if gs == "cgs2" else k - 1   # DCGS2 leaves its last vector after one pass
+    for j in range(m):
+        zd = dense.dense_solve(f.prow, Lf32, Uf32, f.Q, V[:, j], dtype=np.float32)
+        if gs == "cgs2" or j == 0:
+            assert np.array_equal(Z[:, j], zd)
+        else:
+            # DCGS2 forms z_j = (M^-1 u_j - Z s) / beta from the linearity of M^-1, which the
+            # binary32 solve has only to its rounding
+            assert np.linalg.norm(Z[:, j] - zd) <= 1e-5 * np.linalg.norm(zd)
+    beta = np.linalg.norm(r0)
+    e1 = np.zeros(k + 1)
+    e1[0] = beta
+    y = np.linalg.lstsq(H[:k + 1, :k], e1, rcond=None)[0]
+    # the update x - x0 = Z y is small next to x: compare at x's rounding level
+    assert np.linalg.norm(x - (x0 + Z[:, :k] @ y)) <= 1e-8 * np.linalg.norm(x - x0) + 4e-16 * np.linalg.norm(x)
+    yls = np.linalg.lstsq((K @ Z[:, :k]), r0, rcond=None)[0]
+    best = np.linalg.norm(r0 - K @ (Z[:, :k] @ yls))
+    assert np.linalg.norm(b - K @ x) <= best * (1 + 1e-6) + 1e-14 * beta
+
+
+# ----------------------------------------------------------------------------------------
+# Richardson iterative refinement: closed forms with M = c K
+# ----------------------------------------------------------------------------------------
+
+def _scaled_factors(c, n=60, seed=3):
+    """K well conditioned; factors of c K, so M^-1 = K^-1 / c and every Richardson
+    correction multiplies the error by q = 1 - 1/c exactly (up to rounding)."""
+    A = random_sparse(n, 0.06, 900 + seed)
+    A[np.arange(n), np.arange(n)] = 8.0 + np.abs(A[np.arange(n), np.arange(n)])
+    rp, ci, v = csr_of(A)
+    f = oracle.LU(rp, ci, c * v, Q=np.arange(n, dtype=np.int32), tau=0.1)
+    b = np.random.default_rng(seed).standard_normal(n)
+    return A, rp, ci, v, f, b
+
+
+def test_richardson_contraction_closed_form():
+    # q = 1/4: x_k = x*(1 - q^(k+1)), rho_k = q^(k+1) b, ||rho_k|| / ||rho_0|| = q^k; the first k
+    # with q^k < 1e-6 is 10 (q^9 = 3.8e-6, q^10 = 9.5e-7); NSR_k / NSR_(k-1) =
+    # q (1 - q^k) / (1 - q^(k+1)) < 1/2, so MA57's ratio test never stops it earlier
+    c = 4.0 / 3.0
+    q = 1.0 - 1.0 / c
+    A, rp, ci, v, f, b = _scaled_factors(c)
+    xs = np.linalg.solve(A, b)
+    x, info = oracle.richardson(f, rp, ci, v, b, max_it=50, tol=1e-6, ratio=0.5)
+    assert info["converged"] and info["corrections"] == 10 and info["applications"] == 11
+    assert info["rr"] == pytest.approx(q ** 10, rel=1e-8)
+    assert np.linalg.norm(x - xs * (1 - q ** 11)) <= 1e-12 * np.linalg.norm(xs)
+    h = info["hist"]
+    for k in range(1, len(h)):
+        assert h[k] / h[k - 1] == pytest.approx(q * (1 - q ** (k + 1)) / (1 - q ** (k + 2)), rel=1e-8)
+
+
+def test_richardson_ratio_stop_closed_form():
+    # q = 0.8: the NSR ratio is q/(1+q) = 0.444 after the first correction and
+    # 0.8 * 0.36 / 0.488 = 0.590 > 1/2 after the second, so the ratio test stops at 2
+    c = 5.0
+    A, rp, ci, v, f, b = _scaled_factors(c)
+    x, info = oracle.richardson(f, rp, ci, v, b, max_it=50, tol=1e-12, ratio=0.5)
+    assert info["corrections"] == 2 and not info["converged"]
+    assert info["rr"] == pytest.approx(0.8 ** 2, rel=1e-8)
+    # with a laxer ratio (0.9 > every step's 0.8 (1 - 0.8^k) / (1 - 0.8^(k+1))) it runs to max_it
+    x, info = oracle.richardson(f, rp, ci, v, b, max_it=7, tol=1e-12, ratio=0.9)
+    assert info["corrections"] == 7 and not info["converged"]
+    assert info["rr"] == pytest.approx(0.8 ** 7, rel=1e-8)
+
+
+def test_richardson_error_system_fgmres_is_exact_in_one_step():
+    # with M = c K the preconditioned operator K M^-1 is I / c: the inner FGMRES solves
+    # K d = rho exactly in one Arnoldi step (x0 and z_0: two applications), so one
+    # correction reaches the solution: 1 + 2 applications
+    c = 4.0 / 3.0
+    A, rp, ci, v, f, b = _scaled_factors(c)
+    xs = np.linalg.solve(A, b)
+    x, info = oracle.richardson(f, rp, ci, v, b, max_it=50, tol=1e-10, ratio=0.5, inner_restart=5,
+                                inner_tol=1e-2)
+    assert info["converged"] and info["corrections"] == 1 and info["applications"] == 3
+    assert np.linalg.norm(x - xs) <= 1e-13 * np.linalg.norm(xs)
