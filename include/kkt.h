@@ -44,7 +44,9 @@ typedef enum {
     KKT_ENOMEM = 2,     /* host allocation failed or the workspace is too small */
     KKT_ESINGULAR = 3,  /* singular column in the pivoted analysis, or a guarded pivot with
                            guard_policy = KKT_GUARD_FAIL */
-    KKT_ENOCONV = 4,    /* FGMRES-IR did not meet the tolerance; x holds the last iterate */
+    KKT_ENOCONV = 4,    /* FGMRES-IR did not meet the tolerance; x holds the iterate with the
+                           lowest true residual ||r - K x||_2 seen (x0 included) and the info
+                           describes that iterate */
     KKT_EDEVICE = 5,    /* a HIP call failed; the handle accepts only kkt_release() */
     KKT_ESTATE = 6      /* call out of order (solve before refactor, no workspace, ...) */
 } kkt_status_t;
@@ -176,7 +178,8 @@ typedef struct {
     double nsr;              /* ||r - K x||_inf / (||K||_inf ||x||_inf), MA57's measure */
     int64_t precond_applications; /* triangular-solve pairs (x0 included) */
     int32_t repivoted;       /* 1 if this solve re-pivoted (opts.repivot_cycles) */
-    int32_t reserved;
+    int32_t restored_best;   /* 1 if the solve did not converge and x was set back to an
+                                earlier iterate with a lower true residual */
 } kkt_solve_info_t;
 
 /* Fill *opts with the defaults listed above. */
@@ -231,7 +234,9 @@ kkt_status_t kkt_refactor(kkt_handle_t h, const double *dev_values, void *stream
  * synchronizes `stream` at each restart and before returning; *info
  * (may be NULL) is filled on return.  Errors: KKT_ESTATE (no refactor yet), KKT_EINVAL
  * (non-finite K values or b), KKT_ESINGULAR (guard_policy = FAIL and a guarded pivot),
- * KKT_ENOCONV (tolerance not met; x holds the last iterate, info is filled). */
+ * KKT_ENOCONV (tolerance not met; x holds the iterate with the lowest true residual seen,
+ * x0 included, and info describes it).  An iterate whose true residual exceeds that of x0 is
+ * never accepted, in either stop_mode. */
 kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, double tol,
                        kkt_solve_info_t *info, void *stream);
 

@@ -209,10 +209,12 @@ class LU:
 
     def fgmres_ir(self, rowptr, colidx, values, b, Lx=None, Ux=None, Lx32=None, Ux32=None,
                   restart=10, max_restarts=20, eta=1e-12, mode=0, hist_cap=4096, residual="fp64",
-                  gs="cgs2"):
+                  gs="cgs2", keep_best=True):
         """FGMRES-IR with these factors as right preconditioner (see or_fgmres_ir);
         residual="dd" forms every residual in extended precision (or_residual_dd);
-        gs="dcgs2" runs the Arnoldi steps with delayed CGS2 (one reduction per step)."""
+        gs="dcgs2" runs the Arnoldi steps with delayed CGS2 (one reduction per step);
+        keep_best=False returns the last iterate of a refinement that does not converge
+        instead of the one with the lowest true residual."""
         if residual not in ("fp64", "dd"):
             raise ValueError("residual must be 'fp64' or 'dd'")
         if residual == "dd":
@@ -221,6 +223,8 @@ class LU:
             raise ValueError("gs must be 'cgs2' or 'dcgs2'")
         if gs == "dcgs2":
             mode = int(mode) | 4
+        if not keep_best:
+            mode = int(mode) | 8
         rp, ci, v = _csr(rowptr, colidx, values)
         b = np.ascontiguousarray(b, np.float64)
         prec = 1 if Lx32 is not None else 0

@@ -23,6 +23,11 @@
  *   or_fgmres_ir   FGMRES-IR with the LU factors as right preconditioner, CGS2 (or delayed CGS2) Arnoldi,
  *                  estimated residual, solution formed only at restart/convergence
  *                  (Section 2.1, stopping tests of Section 2.2, refine decision of 2.3)
+ *   or_richardson  Richardson iterative refinement with MA57's ratio stop (Section 1.3)
+ *
+ * Where the paper is silent: a refinement that does not converge returns the iterate with the
+ * lowest true residual seen (x0 included), and no iterate whose true residual exceeds that of
+ * x0 is accepted (NRBE alone is lenient when ||x|| grows).
  *
  * Parity pins (tests under tests/): dense brute force on tiny matrices (same pivot rule),
  * LAPACK getrf agreement with tau = 1 and Q = I, closed-form 2x2 KKT blocks, the
@@ -1319,8 +1324,9 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
     ws.w = (double *)malloc((size_t)n * sizeof(double));
     double *yv = (double *)malloc((size_t)R * sizeof(double));
     double *r = (double *)malloc((size_t)n * sizeof(double));
+    double *xbest = (double *)malloc((size_t)n * sizeof(double));
     int ok = ws.V && ws.Z && ws.H && ws.Hu && ws.cs && ws.sn && ws.g && ws.h && ws.h2 && ws.c &&
-             ws.sv && ws.e && ws.hs && ws.w && yv && r;
+             ws.sv && ws.e && ws.hs && ws.w && yv && r && xbest;
     int status = OR_ENOMEM;
     if (ok) {
         double *V = ws.V, *Z = ws.Z, *H = ws.H, *g = ws.g;
@@ -1329,6 +1335,7 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
         void (*resid)(int64_t, const int64_t *, const int32_t *, const double *, const double *,
                       const double *, double *) = (mode & 2) ? or_residual_dd : or_residual;
         const int dcgs2 = (mode & 4) != 0;
+        const int inner_solver = (mode & 8) != 0; /* a correction solve: no best-iterate restore */
         mode &= 1;
         double kn = or_norm_inf_mat(n, rp, v);
         double bn = nrm2(n, b);
@@ -1341,6 +1348,10 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
         info[5] = nrbe;
         int iters = 0, cycles = 0, converged = 0;
         double est = rn;
+        /* the iterate with the lowest true residual so far (x0 included) is returned when the
+           refinement does not converge; best_nrbe is its NRBE */
+        double best_rn = rn, best_nrbe = nrbe;
+        memcpy(xbest, x, (size_t)n * sizeof(double));
         if (mode == 0 ? (nrbe <= eta) : (rn / bn < eta)) converged = 1;
         while (!converged && cycles <= max_restarts) {
             cycles++;
@@ -1375,7 +1386,19 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
             resid(n, rp, ci, v, x, b, r);
             rn = nrm2(n, r);
             nrbe = rn / (kn * nrm2(n, x) + bn);
-            if (mode == 0 ? (nrbe <= eta) : (est < eta * rho0)) converged = 1;
+            /* an iterate whose true residual exceeds that of x0 is never accepted: the NRBE
+               test alone passes when rounding makes ||x|| grow without bound */
+            if ((mode == 0 ? (nrbe <= eta) : (est < eta * rho0)) && rn <= rho0) converged = 1;
+            if (rn < best_rn) {
+                best_rn = rn;
+                best_nrbe = nrbe;
+                memcpy(xbest, x, (size_t)n * sizeof(double));
+            }
+        }
+        if (!converged && !inner_solver && rn > best_rn) {
+            memcpy(x, xbest, (size_t)n * sizeof(double));
+            rn = best_rn;
+            nrbe = best_nrbe;
         }
         info[0] = iters;
         info[1] = cycles;
@@ -1389,7 +1412,7 @@ int or_fgmres_ir(const or_lu_t *f, const double *Lx, const double *Ux, const flo
     }
     free(ws.V); free(ws.Z); free(ws.H); free(ws.Hu); free(ws.cs); free(ws.sn); free(ws.g);
     free(ws.h); free(ws.h2); free(ws.c); free(ws.sv); free(ws.e); free(ws.hs); free(ws.w);
-    free(yv); free(r);
+    free(yv); free(r); free(xbest);
     return status;
 }
 
@@ -1465,8 +1488,9 @@ int or_richardson(const or_lu_t *f, const double *Lx, const double *Ux, const in
     int64_t n = f->n;
     double *r = (double *)malloc((size_t)n * sizeof(double));
     double *d = (double *)malloc((size_t)n * sizeof(double));
-    if (!r || !d) {
-        free(r); free(d);
+    double *xbest = (double *)malloc((size_t)n * sizeof(double));
+    if (!r || !d || !xbest) {
+        free(r); free(d); free(xbest);
         return OR_ENOMEM;
     }
     double kn = or_norm_inf_mat(n, rp, v);
@@ -1477,11 +1501,14 @@ int or_richardson(const or_lu_t *f, const double *Lx, const double *Ux, const in
     double rho0 = nrm2(n, r);
     double rn = rho0;
     double nsr = nrminf(n, r) / (kn * nrminf(n, x));
+    /* the iterate with the lowest true residual (x0 included) is returned if not converged */
+    double best_rn = rn, best_nsr = nsr;
+    memcpy(xbest, x, (size_t)n * sizeof(double));
     int it = 0, converged = rn < tol * rho0;
     while (!converged && it < max_it) {
         if (inner_restart > 0) {
             double inner[9];
-            or_fgmres_ir(f, Lx, Ux, NULL, NULL, 0, rp, ci, v, r, d, inner_restart, 0, inner_tol, 1, inner,
+            or_fgmres_ir(f, Lx, Ux, NULL, NULL, 0, rp, ci, v, r, d, inner_restart, 0, inner_tol, 1 | 8, inner,
                          NULL, 0);
             applications += (long)inner[8];
         } else {
@@ -1497,7 +1524,17 @@ int or_richardson(const or_lu_t *f, const double *Lx, const double *Ux, const in
         converged = rn < tol * rho0;
         int stalled = nsr_new > ratio * nsr;
         nsr = nsr_new;
+        if (rn < best_rn) {
+            best_rn = rn;
+            best_nsr = nsr;
+            memcpy(xbest, x, (size_t)n * sizeof(double));
+        }
         if (stalled) break;
+    }
+    if (!converged && rn > best_rn) {
+        memcpy(x, xbest, (size_t)n * sizeof(double));
+        rn = best_rn;
+        nsr = best_nsr;
     }
     info[0] = it;
     info[1] = (double)applications;
@@ -1505,7 +1542,7 @@ int or_richardson(const or_lu_t *f, const double *Lx, const double *Ux, const in
     info[3] = rn / (kn * nrm2(n, x) + bn);
     info[4] = converged;
     info[5] = rho0 > 0.0 ? rn / rho0 : 0.0;
-    free(r); free(d);
+    free(r); free(d); free(xbest);
     return converged ? OR_OK : 4;
 }
 

@@ -1329,15 +1329,17 @@ __global__ void __launch_bounds__(kStreamBlock) k_resid_reduce(KrylovArgs a, int
 }
 
 // Start of a cycle: v_0 = rho / ||rho||, g = (beta, 0, ...), re-arm sentinels
+// (and, when xsave is given, xsave = x: the iterate the cycle starts from is the best so far)
 template <typename T>
 __global__ void __launch_bounds__(kStreamBlock) k_cycle_start(KrylovArgs a, const double *r, double inner_tol,
-                                                              T *s1, T *s2) {
+                                                              T *s1, T *s2, const double *x, double *xsave) {
     const double beta = sqrt(a.ctl->rnorm2);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
         a.V[i] = r[i] / beta;
         s1[i] = sentinel<T>();
         s2[i] = sentinel<T>();
+        if (xsave) xsave[i] = x[i];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Control *c = a.ctl;
@@ -1382,10 +1384,14 @@ __global__ void __launch_bounds__(kStreamBlock) k_xupdate(KrylovArgs a, double *
     }
 }
 
-// x += d
-__global__ void k_axpy(int64_t n, const double *d, double *x) {
+// x += d (and, when xsave is given, xsave = x before the update)
+__global__ void k_axpy(int64_t n, const double *d, double *x, double *xsave) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = x[i] + d[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double xi = x[i];
+        if (xsave) xsave[i] = xi;
+        x[i] = xi + d[i];
+    }
 }
 
 __global__ void k_copy(int64_t n, const double *src, double *dst) {
@@ -1428,7 +1434,7 @@ struct DevLayout {
     double *Ld64;
     float *Ld32;
     // vectors
-    double *V, *Z, *w, *r, *y64, *z64, *dv, *rr;
+    double *V, *Z, *w, *r, *y64, *z64, *dv, *rr, *xb;
     float *y32, *z32;
     double *part;
     Control *ctl;
@@ -1558,7 +1564,7 @@ struct Offsets {
     size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, krp, kci, l_rows, l_seg, l_tseg,
         l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, l_tden, l_sdof, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
         u_rent, u_tlds, u_tden, u_sdof, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
-        z32, dv, rr, part, ctl, total;
+        z32, dv, rr, xb, part, ctl, total;
 };
 
 Offsets plan(const kkt_handle_t h) {
@@ -1619,6 +1625,7 @@ Offsets plan(const kkt_handle_t h) {
     o.z32 = p.take<float>(n);
     o.dv = p.take<double>(n);
     o.rr = p.take<double>(n);
+    o.xb = p.take<double>(n);
     o.part = p.take<double>((size_t)3 * kStreamGridMax * kPartStride);
     o.ctl = p.take<Control>(1);
     o.total = p.off;
@@ -1844,6 +1851,13 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     inf.refined = !converged;
     int iters = 0, cycles = 0;
     double est = rn;
+    // The iterate with the lowest true residual so far (x0 included) is what a solve that
+    // does not converge returns.  x holds it while x_best; a cycle that starts from it saves
+    // a copy in xb first (fused into the cycle start), and its summary is kept for the info.
+    const bool track = require_nrbe;
+    bool x_best = true;
+    double best_rn = rho0;
+    ControlSummary best_sum = c;
     while (!converged && cycles < max_cycles) {
         ++cycles;
         if (!(rn > 0.0)) {
@@ -1853,7 +1867,9 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         const double xn = std::sqrt(h->host_ctl->xnorm2);
         const double inner = paper ? tol * rho0 : target * (knorm * xn + bn);
         e0 = prof_begin(h, KKT_K_OTHER, s);
-        k_cycle_start<T><<<G, kStreamBlock, 0, s>>>(ka, d.r, inner, y, z);
+        const bool save = track && x_best;
+        k_cycle_start<T><<<G, kStreamBlock, 0, s>>>(ka, d.r, inner, y, z, save ? x : nullptr,
+                                                      save ? d.xb : nullptr);
         prof_end(h, KKT_K_OTHER, e0, s);
         // Step j+1 is enqueued before the host reads step j's record, so the device never
         // waits for the host; kernels of a step enqueued after the stop return at once.
@@ -1927,7 +1943,26 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         est = h->host_ctl->est;
         rn = std::sqrt(h->host_ctl->rnorm2);
         nrbe = rn / (knorm * std::sqrt(h->host_ctl->xnorm2) + bn);
-        converged = paper ? (est < tol * rho0 && nrbe <= target) : nrbe <= target;
+        // NRBE alone is lenient when ||x|| grows (||K|| ||x|| is in its denominator): an
+        // iterate whose true residual exceeds that of x0 is never accepted
+        converged = (paper ? (est < tol * rho0 && nrbe <= target) : nrbe <= target) && rn <= rho0;
+        x_best = rn < best_rn;
+        if (x_best) {
+            best_rn = rn;
+            best_sum = *h->host_ctl;
+        }
+    }
+    const ControlSummary *fin = h->host_ctl;
+    if (!converged && track && !x_best) {
+        // restore the best iterate (saved when the cycle that left it started)
+        e0 = prof_begin(h, KKT_K_OTHER, s);
+        k_copy<<<G, kStreamBlock, 0, s>>>(a.n, d.xb, x);
+        prof_end(h, KKT_K_OTHER, e0, s);
+        KKT_HIP(h, hipGetLastError());
+        fin = &best_sum;
+        rn = best_rn;
+        nrbe = rn / (knorm * std::sqrt(fin->xnorm2) + bn);
+        inf.restored_best = 1;
     }
     inf.converged = converged;
     inf.iterations = iters;
@@ -1937,7 +1972,7 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     inf.rr = rho0 > 0.0 ? rn / rho0 : 0.0;
     inf.est_resid = est;
     inf.true_resid = rn;
-    inf.nsr = h->host_ctl->rinf / (knorm * h->host_ctl->xinf);
+    inf.nsr = fin->rinf / (knorm * fin->xinf);
     if (info) *info = inf;
     return converged ? KKT_OK : KKT_ENOCONV;
 }
@@ -1992,6 +2027,10 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
     bool converged = bn == 0.0 || (rn < tol * rho0 && nrbe <= target);
     inf.refined = !converged;
     int it = 0;
+    // best iterate so far, as in solve_impl: x holds it while x_best, else xb does
+    bool x_best = true;
+    double best_rn = rho0;
+    ControlSummary best_sum = c;
     while (!converged && it < h->opts.richardson_max_it) {
         if (inner_fgmres) {
             hipEvent_t c0 = prof_begin(h, KKT_K_OTHER, s);
@@ -2008,7 +2047,7 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
             inf.precond_applications += 1;
         }
         hipEvent_t x0 = prof_begin(h, KKT_K_OTHER, s);
-        k_axpy<<<G, kStreamBlock, 0, s>>>(a.n, d.dv, x);
+        k_axpy<<<G, kStreamBlock, 0, s>>>(a.n, d.dv, x, x_best ? d.xb : nullptr);
         prof_end(h, KKT_K_OTHER, x0, s);
         ++it;
         st = residual();
@@ -2017,9 +2056,24 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
         nrbe = rn / (knorm * std::sqrt(h->host_ctl->xnorm2) + bn);
         const double nsr_new = h->host_ctl->rinf / (knorm * h->host_ctl->xinf);
         converged = rn < tol * rho0 && nrbe <= target;
+        x_best = rn < best_rn;
+        if (x_best) {
+            best_rn = rn;
+            best_sum = *h->host_ctl;
+        }
         const bool stalled = nsr_new > h->opts.ratio_stop * nsr;
         nsr = nsr_new;
         if (stalled) break;
+    }
+    if (!converged && !x_best) {
+        hipEvent_t x0 = prof_begin(h, KKT_K_OTHER, s);
+        k_copy<<<G, kStreamBlock, 0, s>>>(a.n, d.xb, x);
+        prof_end(h, KKT_K_OTHER, x0, s);
+        KKT_HIP(h, hipGetLastError());
+        rn = best_rn;
+        nrbe = rn / (knorm * std::sqrt(best_sum.xnorm2) + bn);
+        nsr = best_sum.rinf / (knorm * best_sum.xinf);
+        inf.restored_best = 1;
     }
     inf.converged = converged;
     inf.cycles = it;
@@ -2095,9 +2149,16 @@ kkt_status_t repivot_impl(kkt_handle_t h, hipStream_t s) {
     kkt_status_t st = kkt_bind_workspace(h, h->ws, h->ws_bytes, s);
     if (st != KKT_OK) return st;
     KKT_HIP(h, hipMemcpyAsync(h->d.kval, vals.data(), h->an.nnz * sizeof(double), hipMemcpyHostToDevice, s));
+    // mixed precision: the FP32 factors of the old layout are meaningless now, so the FP32
+    // refactorization runs in the new layout as well (kkt_direct_solve and the factor getters
+    // read them); the FP64 factors, refactored last, serve this system's remaining solves
+    if (h->opts.precision == KKT_PREC_MIXED) {
+        st = refactor_impl(h, nullptr, KKT_PREC_MIXED, s);
+        if (st != KKT_OK) return st;
+    }
     st = refactor_impl(h, nullptr, KKT_PREC_FP64, s);
     if (st != KKT_OK) return st;
-    h->fp64_current = h->factor_precision == KKT_PREC_MIXED || h->fp64_current;
+    h->fp64_current = h->opts.precision == KKT_PREC_MIXED;
     h->factor_precision = h->opts.precision;
     h->repivots += 1;
     return KKT_OK;
@@ -2295,6 +2356,7 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.z32 = (float *)(b + o.z32);
     d.dv = (double *)(b + o.dv);
     d.rr = (double *)(b + o.rr);
+    d.xb = (double *)(b + o.xb);
     d.part = (double *)(b + o.part);
     d.ctl = (Control *)(b + o.ctl);
     KKT_HIP(h, up(b, o.fp, a.fp, s));

@@ -69,7 +69,7 @@ class SolveInfo(C.Structure):
                 ("pivots_perturbed", C.c_int64), ("nrbe", C.c_double), ("nrbe0", C.c_double),
                 ("rel_resid", C.c_double), ("rr", C.c_double), ("est_resid", C.c_double),
                 ("true_resid", C.c_double), ("knorm_inf", C.c_double), ("nsr", C.c_double),
-                ("precond_applications", C.c_int64), ("repivoted", C.c_int32), ("reserved", C.c_int32)]
+                ("precond_applications", C.c_int64), ("repivoted", C.c_int32), ("restored_best", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -792,3 +792,23 @@ def test_richardson_error_system_fgmres_is_exact_in_one_step():
                                 inner_tol=1e-2)
     assert info["converged"] and info["corrections"] == 1 and info["applications"] == 3
     assert np.linalg.norm(x - xs) <= 1e-13 * np.linalg.norm(xs)
+
+
+def test_richardson_divergence_returns_best_iterate():
+    # c = 1/4: q = 1 - 1/c = -3, so x0 = 4 x*, rho0 = -3 b and the first correction gives
+    # x1 = -8 x*, rho1 = 9 b.  NSR goes from 3/4 to 9/8 of ||b||inf / (||K||inf ||x*||inf), a
+    # ratio of 1.5 > 1/2, so MA57's test stops after one correction; x1's residual is three
+    # times x0's, so the refinement returns x0 itself (the direct solve), with rr = 1
+    c = 0.25
+    A, rp, ci, v, f, b = _scaled_factors(c)
+    xs = np.linalg.solve(A, b)
+    x0 = f.solve(b)
+    x, info = oracle.richardson(f, rp, ci, v, b, max_it=50, tol=1e-12, ratio=0.5)
+    assert info["corrections"] == 1 and not info["converged"]
+    assert np.array_equal(x, x0)
+    assert np.linalg.norm(x - 4.0 * xs) <= 1e-12 * np.linalg.norm(xs)
+    assert info["rr"] == 1.0
+    # with a ratio that lets it run, every correction triples the residual: x0 again
+    x, info = oracle.richardson(f, rp, ci, v, b, max_it=4, tol=1e-12, ratio=10.0)
+    assert info["corrections"] == 4 and not info["converged"]
+    assert np.array_equal(x, x0) and info["rr"] == 1.0
