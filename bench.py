@@ -1,8 +1,10 @@
 """Benchmark: KKT solves/s (refactor + FGMRES-IR to NRBE <= 1e-12) on one MI355X.
 
-Workload (default): the 60,000-unknown sequence of 20 same-pattern KKT systems
-(n = 35,000, m = 25,000; D log-uniform in [1e-10, 1e10], 1 % perturbation of H/J values per
-step, fresh right-hand side), plain FP64 path.  The host analysis runs once (timed
+Workload (default): the largest single-GPU instance, a sequence of 5 same-pattern KKT systems
+of 2,000,000 unknowns (n = 1,150,000, m = 850,000, 10.55 M nonzeros; D log-uniform in
+[1e-12, 1e12], 1 % perturbation of H/J values per step, fresh right-hand side), FGMRES(50),
+plain FP64 path.  `--config 2` runs the 60,000-unknown sequence of 20 systems (FGMRES(10)),
+`--config 3` the 500,000-unknown one (FGMRES(30)).  The host analysis runs once (timed
 separately); a timed step is one refactorization plus one FGMRES-IR solve of the next
 system of the sequence, with every system's values and right-hand side already resident in
 HBM.  The same steps are also run with FP32 factors as the preconditioner (mixed).
@@ -31,27 +33,28 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E nameplate
 
 
 def algorithmic_bytes(cls: str, ai: dict) -> float:
-    """Bytes a kernel class must move per launch, each array counted once (FP64 factors)."""
+    """Bytes a kernel class must move per launch, each array counted once (FP64 factors, 4-byte
+    indices), as the per-stage table of the method's data movement gives them:
+      SpTRSV (one triangle): nnz_T (8 + 4) + (N + 1) 4 + 2 N 8    (values + indices, row
+                             pointers, right-hand side read, solution written)
+      refactorization:       f 8 (read) + f 4 (pattern) + f 8 (write) + 4 per precomputed
+                             update position (the update list)
+      SpMV:                  nnz_K 12 + (N + 1) 4 + 3 N 8"""
     n, nnz, lnz, unz, upd = ai["n"], ai["nnz"], ai["nnz_l"], ai["nnz_u"], ai["updates"]
     f = lnz + unz
     if cls == "trsv_l":
-        # L values + column indices, row pointers, row order, rhs gather + prow, y read/write
-        return lnz * 12 + (n + 1) * 8 + n * (4 + 8 + 4 + 8 + 8)
+        return lnz * 12 + (n + 1) * 4 + 2 * n * 8
     if cls == "trsv_u":
-        # strict U values + indices, diagonal, row pointers, row order, y read, z write and
-        # read, q, x write
-        return (unz - n) * 12 + n * 8 + (n + 1) * 8 + n * (4 + 8 + 8 + 8 + 4 + 8)
+        return unz * 12 + (n + 1) * 4 + 2 * n * 8
     if cls == "refactor":
-        # ingested values read, final values written twice (column and solve layouts) with the
-        # layout map, update positions, column pointers / diagonal offsets / order / flags
-        return f * (8 + 8 + 8 + 4) + upd * 4 + n * (8 + 4 + 4 + 4 + 8)
+        return f * (8 + 4 + 8) + upd * 4
     if cls == "spmv":
-        return nnz * 12 + (n + 1) * 8 + n * 8 * 3
+        return nnz * 12 + (n + 1) * 4 + 3 * n * 8
     raise KeyError(cls)
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kkt_sequence_60k_hbm_counters.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 # kernel-name prefixes of each class in the counter summary (the solve kernels carry a second
 # template flag: dense segments on or off)
 KERNEL_NAMES = {"trsv_l": "kkt::k_trsv<double,true", "trsv_u": "kkt::k_trsv<double,false",
@@ -70,14 +73,16 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(cls: str):
+def measured_traffic(cls: str, workload: str):
     """HBM bytes (read + written) per launch of a kernel class, from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary of the 60k workload; None when the sources changed since."""
+    FETCH_SIZE / WRITE_SIZE summary of this workload; None when there is none or the library
+    sources changed since the counters were taken."""
     name = KERNEL_NAMES.get(cls)
-    if not name or not os.path.exists(TRAFFIC_FILE):
+    path = os.path.join(PROFILES, workload + "_hbm_counters.txt")
+    if not name or not os.path.exists(path):
         return None
     digest = source_digest()
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             parts = line.split()
             if len(parts) == 5 and parts[0] == "traffic" and parts[1].startswith(name) and parts[4] == digest:
@@ -133,6 +138,24 @@ def cpu_all_cores(cfg, seconds, procs):
     for p_ in ps:
         p_.join()
     return sum(d for d, _ in res), max(t for _, t in res)
+
+
+def host_cpu() -> dict:
+    """Logical CPUs this process may run on, and the CPU model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model}
 
 
 def percentile(xs, q):
@@ -218,12 +241,13 @@ def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, resta
         del flush_src, flush_dst
     # solutions of every system of the sequence, after the timed region (for the comparison
     # with the CPU baseline's solutions)
-    xs = []
+    xs, nrbe_all = [], []
     for k in range(M):
         s.refactor(vals[k])
-        s.solve(rhs[k], x, allow_noconv=True)
+        _, info = s.solve(rhs[k], x, allow_noconv=True)
         xs.append(x.cpu().numpy().copy())
-    return dict(solver=s, analysis_s=analysis_s, wall=wall, lat=lat, infos=infos, times=times,
+        nrbe_all.append(info["nrbe"])
+    return dict(nrbe_all=nrbe_all, solver=s, analysis_s=analysis_s, wall=wall, lat=lat, infos=infos, times=times,
                 breakdown=breakdown, dominant=dom, xs=xs, cold=cold)
 
 
@@ -338,10 +362,11 @@ def run_serving(P, torch, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS),
-                    help="workload: 1 (7k, one system), 2 (60k x 20), 3 (500k x 10), 5 (2M x 5)")
+    ap.add_argument("--config", type=int, default=5, choices=sorted(WORKLOADS),
+                    help="workload: 1 (7k, one system), 2 (60k x 20), 3 (500k x 10), 5 (2M x 5, "
+                         "the largest single-GPU instance; default)")
     ap.add_argument("--mixed-steps", type=int, default=10)
     ap.add_argument("--gram-schmidt", choices=["cgs2", "dcgs2"], default="cgs2",
                     help="Arnoldi orthogonalization: CGS2 (default) or delayed CGS2 (one reduction per step)")
@@ -469,11 +494,21 @@ def main():
         avg_s = ms / n_l / 1e3
         bytes_per = algorithmic_bytes(dom, ai)
         achieved = bytes_per / avg_s / 1e9
-        traffic = measured_traffic(dom) if cfg == 2 else None
+        traffic = measured_traffic(dom, wname)
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per,
                            "measured_copy_peak": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs}
+        # every class of the breakdown pass against the same peak (SpMV and refactorization
+        # separately, as well as the dominant class above)
+        per = {}
+        for c in ("refactor", "trsv_l", "trsv_u", "spmv"):
+            if bd[c][0] > 0:
+                us = bd[c][1] / bd[c][0] * 1e3
+                by = algorithmic_bytes(c, ai)
+                per[c] = {"avg_launch_us": us, "algorithmic_bytes_per_launch": by,
+                          "achieved_gbs": by / us / 1e3, "frac": by / us / 1e3 / HBM_PEAK_GBS}
+        out["roofline_per_kernel"] = per
         # the second floor: dependent levels, each paid in sequence whatever the bandwidth
         lv = {"refactor": ai["levels_refactor"], "trsv_l": ai["levels_l"], "trsv_u": ai["levels_u"]}
         out["dependency_floor"] = {
@@ -489,6 +524,7 @@ def main():
     if not args.no_cpu:
         done, el, cmp = cpu_baseline(pattern, systems, args.cpu_seconds, r64["xs"])
         out["cpu_baseline"] = {"value": done / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                               "host": host_cpu(),
                                "sample": "%d systems of the same sequence, plain direct method (reused "
                                          "ordering, fresh threshold-pivoted LU + triangular solves), "
                                          "single thread, %.1f s" % (done, el)}
@@ -499,6 +535,10 @@ def main():
                 "max_condest": max(c for _, c in cmp),
                 "all_within_1e-8_condest": all(r <= 1e-8 * c for r, c in cmp),
                 "max_ratio_to_bound": max(r / (1e-8 * c) for r, c in cmp),
+                "per_system": [{"system": k + 1, "rel_diff": r, "condest": c, "nrbe": n_}
+                               for k, ((r, c), n_) in enumerate(zip(cmp, r64["nrbe_all"]))],
+                "note": "rel_diff = ||x_gpu - x_oracle||_inf / ||x_oracle||_inf against the oracle's plain "
+                        "direct method; condest = the oracle's 1-norm condition estimate of that system",
             }
     print(json.dumps(out), flush=True)
 

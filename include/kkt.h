@@ -158,6 +158,12 @@ typedef struct {
     int64_t levels_u;       /* depth of the row DAG of the U solve */
     int64_t updates;        /* scalar multiply-subtract updates per refactorization */
     double analysis_seconds;/* host time spent in kkt_analyze */
+    int64_t max_column;     /* longest factor column (U part, diagonal and L part); columns
+                               beyond the refactorization's LDS stage are updated in HBM */
+    int64_t tiles_l;        /* triangular-solve tiles of L (see kkt_bind_workspace) */
+    int64_t tiles_u;        /* ... and of U */
+    int64_t unstaged_l;     /* tiles of L whose row is too long for LDS (read from HBM) */
+    int64_t unstaged_u;     /* ... and of U */
 } kkt_analysis_info_t;
 
 typedef struct {

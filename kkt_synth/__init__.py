@@ -129,6 +129,7 @@ class KKTPattern:
     _edge_j: np.ndarray
     _h_base: np.ndarray
     _j_base: np.ndarray       # (m, 3)
+    delta: float = DUAL_REG   # the (2,2) block is -delta I
 
     @property
     def N(self) -> int:
@@ -161,14 +162,15 @@ class KKTPattern:
         # source vector layout: [h (E), h again for the mirror (E), H diag + D (n),
         #                        J (3m), J^T (3m), -delta (m)]
         src = np.concatenate([h, h, hdiag + dvals, jv.reshape(-1), jv.reshape(-1),
-                              np.full(m, -DUAL_REG)])
+                              np.full(m, -self.delta)])
         return src[self._src], b
 
 
 @functools.lru_cache(maxsize=16)
 def make_pattern(config: int, pattern: int = 0, n: int | None = None, m: int | None = None,
-                 dlog: tuple | None = None) -> KKTPattern:
-    """Build the pattern (and base values) for a workload; see the module docstring."""
+                 dlog: tuple | None = None, delta: float = DUAL_REG) -> KKTPattern:
+    """Build the pattern (and base values) for a workload; see the module docstring.
+    `delta` sets the dual regularisation (the moderate family uses 1)."""
     if n is None:
         if config == 4:
             dim = SERVING_DIMS[pattern]
@@ -207,12 +209,24 @@ def make_pattern(config: int, pattern: int = 0, n: int | None = None, m: int | N
     assert rowptr[-1] == 2 * E + n + 6 * m + m
     return KKTPattern(config=config, pattern=pattern, n=n, m=m, dlog=tuple(dlog), rowptr=rowptr,
                       colidx=cols.astype(np.int32), _src=src, _edge_i=ei, _edge_j=ej,
-                      _h_base=h_base, _j_base=j_base)
+                      _h_base=h_base, _j_base=j_base, delta=float(delta))
 
 
-def small_kkt(n: int, m: int, seed: int, dlog=(-8.0, 8.0)) -> KKTPattern:
+def small_kkt(n: int, m: int, seed: int, dlog=(-8.0, 8.0), delta: float = DUAL_REG) -> KKTPattern:
     """A tiny pattern of the same family, for brute-force checks (config id 0)."""
-    return make_pattern(0, seed, n=n, m=m, dlog=tuple(dlog))
+    return make_pattern(0, seed, n=n, m=m, dlog=tuple(dlog), delta=float(delta))
+
+
+#: The moderately conditioned family: D log-uniform in [1e-2, 1e2], delta = 1.  With these
+#: values the condition number is small enough that a forward-error bound of the form
+#: 1e-8 * cond-estimate is informative (on the workload configs it is vacuous).
+MODERATE_DLOG = (-2.0, 2.0)
+MODERATE_DELTA = 1.0
+
+
+def moderate_kkt(n: int, m: int, seed: int = 0) -> KKTPattern:
+    """A pattern of the moderate family (config id 6) with the generator's structure."""
+    return make_pattern(6, seed, n=n, m=m, dlog=MODERATE_DLOG, delta=MODERATE_DELTA)
 
 
 def to_dense(rowptr: np.ndarray, colidx: np.ndarray, values: np.ndarray, N: int) -> np.ndarray:
@@ -221,3 +235,75 @@ def to_dense(rowptr: np.ndarray, colidx: np.ndarray, values: np.ndarray, N: int)
     for i in range(N):
         a[i, colidx[rowptr[i]:rowptr[i + 1]]] = values[rowptr[i]:rowptr[i + 1]]
     return a
+
+
+class ArrowKKT:
+    """A KKT matrix of the same block form with one dense constraint row ("arrow head"):
+    H on a path graph (h_i,i+1 ~ N(0,1), diagonal 1 + sum |h_ij|), constraint 0 couples
+    `dense` primal variables (every n/dense-th), constraints 1..m-1 three consecutive ones.
+    A minimum-degree ordering eliminates the dense constraint last, so its factor column
+    and its row of L hold about `dense` entries: long columns and rows of the kind the
+    generator's planar-like graphs never produce.  Steps redraw D, perturb H/J by 1 % and
+    draw a fresh right-hand side, as the generator does."""
+
+    def __init__(self, n: int, m: int, dense: int, seed: int = 0, dlog=(-8.0, 8.0), delta: float = DUAL_REG):
+        if not (2 <= m <= n - 3) or not (3 <= dense <= n):
+            raise ValueError("need 2 <= m <= n - 3 and 3 <= dense <= n")
+        self.n, self.m, self.dlog, self.delta, self.seed = n, m, tuple(dlog), float(delta), seed
+        rng = np.random.default_rng([BASE_SEED, 7, seed, 0])
+        self._h = rng.standard_normal(n - 1)
+        cols = [np.unique(np.linspace(0, n - 1, dense).round().astype(np.int64))]
+        starts = rng.integers(0, n - 2, size=m - 1)
+        cols += [np.arange(s, s + 3) for s in starts]
+        self._jcols = cols
+        self._jbase = [rng.standard_normal(c.size) for c in cols]
+        N = n + m
+        rows, colsl, kind, idx = [], [], [], []
+        # kind 0: h edge (idx = edge), 1: H diagonal (idx = i), 2: J entry (idx = flat), 3: -delta
+        e = np.arange(n - 1)
+        rows += [e, e + 1]; colsl += [e + 1, e]; kind += [np.zeros(n - 1, int)] * 2; idx += [e, e]
+        rows.append(np.arange(n)); colsl.append(np.arange(n)); kind.append(np.ones(n, int)); idx.append(np.arange(n))
+        flat = 0
+        for r, c in enumerate(cols):
+            fi = np.arange(flat, flat + c.size)
+            rows += [np.full(c.size, n + r), c]; colsl += [c, np.full(c.size, n + r)]
+            kind += [np.full(c.size, 2)] * 2; idx += [fi, fi]
+            flat += c.size
+        rows.append(n + np.arange(m)); colsl.append(n + np.arange(m)); kind.append(np.full(m, 3)); idx.append(np.arange(m))
+        rows, colsl = np.concatenate(rows), np.concatenate(colsl)
+        kind, idx = np.concatenate(kind), np.concatenate(idx)
+        order = np.lexsort((colsl, rows))
+        rows, colsl, self._kind, self._idx = rows[order], colsl[order], kind[order], idx[order]
+        if np.any((rows[1:] == rows[:-1]) & (colsl[1:] == colsl[:-1])):
+            raise ValueError("duplicate entry in the arrow pattern")
+        rowptr = np.zeros(N + 1, dtype=np.int64)
+        np.add.at(rowptr, rows + 1, 1)
+        self.rowptr = np.cumsum(rowptr)
+        self.colidx = colsl.astype(np.int32)
+
+    @property
+    def N(self) -> int:
+        return self.n + self.m
+
+    def system(self, step: int):
+        if step < 1:
+            raise ValueError("steps are numbered from 1")
+        rng = np.random.default_rng([BASE_SEED, 7, self.seed, step])
+        n = self.n
+        d = 10.0 ** rng.uniform(self.dlog[0], self.dlog[1], size=n)
+        h = self._h
+        jv = np.concatenate(self._jbase)
+        if step >= 2:
+            h = h * (1.0 + 0.01 * rng.standard_normal(h.size))
+            jv = jv * (1.0 + 0.01 * rng.standard_normal(jv.size))
+        b = rng.standard_normal(self.N)
+        hd = np.ones(n)
+        np.add.at(hd, np.arange(n - 1), np.abs(h))
+        np.add.at(hd, np.arange(1, n), np.abs(h))
+        vals = np.empty(self._kind.size)
+        k = self._kind
+        vals[k == 0] = h[self._idx[k == 0]]
+        vals[k == 1] = (hd + d)[self._idx[k == 1]]
+        vals[k == 2] = jv[self._idx[k == 2]]
+        vals[k == 3] = -self.delta
+        return vals, b

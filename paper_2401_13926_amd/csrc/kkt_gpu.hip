@@ -2248,6 +2248,12 @@ kkt_status_t kkt_get_analysis_info(kkt_handle_t h, kkt_analysis_info_t *info) {
     info->levels_u = a.usched.levels;
     info->updates = a.updates();
     info->analysis_seconds = a.seconds;
+    info->max_column = 0;
+    for (int64_t j = 0; j < a.n; ++j) info->max_column = std::max(info->max_column, a.fp[j + 1] - a.fp[j]);
+    info->tiles_l = a.lsched.tiles();
+    info->tiles_u = a.usched.tiles();
+    info->unstaged_l = (int64_t)std::count(a.lsched.tile_lds.begin(), a.lsched.tile_lds.end(), (uint8_t)0);
+    info->unstaged_u = (int64_t)std::count(a.usched.tile_lds.begin(), a.usched.tile_lds.end(), (uint8_t)0);
     return KKT_OK;
 }
 

@@ -52,7 +52,8 @@ class AnalysisInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64),
                 ("offdiag_pivots", C.c_int64), ("levels_refactor", C.c_int64),
                 ("levels_l", C.c_int64), ("levels_u", C.c_int64), ("updates", C.c_int64),
-                ("analysis_seconds", C.c_double)]
+                ("analysis_seconds", C.c_double), ("max_column", C.c_int64), ("tiles_l", C.c_int64),
+                ("tiles_u", C.c_int64), ("unstaged_l", C.c_int64), ("unstaged_u", C.c_int64)]
 
 
 class RequestTimes(C.Structure):

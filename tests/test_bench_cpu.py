@@ -20,10 +20,12 @@ def test_multi_gpu_request_exits_with_message():
 
 def test_algorithmic_bytes_counts():
     ai = dict(n=10, nnz=40, nnz_l=20, nnz_u=30, updates=100)
-    assert bench.algorithmic_bytes("trsv_l", ai) == 20 * 12 + 11 * 8 + 10 * 32
-    assert bench.algorithmic_bytes("trsv_u", ai) == 20 * 12 + 10 * 8 + 11 * 8 + 10 * 40
-    assert bench.algorithmic_bytes("refactor", ai) == 50 * 28 + 100 * 4 + 10 * 28
-    assert bench.algorithmic_bytes("spmv", ai) == 40 * 12 + 11 * 8 + 10 * 24
+    # per-stage byte counts: triangle values + indices, row pointers, 2 vectors; factor read,
+    # pattern, factor write, update list; K values + indices, row pointers, 3 vectors
+    assert bench.algorithmic_bytes("trsv_l", ai) == 20 * 12 + 11 * 4 + 10 * 16
+    assert bench.algorithmic_bytes("trsv_u", ai) == 30 * 12 + 11 * 4 + 10 * 16
+    assert bench.algorithmic_bytes("refactor", ai) == 50 * 20 + 100 * 4
+    assert bench.algorithmic_bytes("spmv", ai) == 40 * 12 + 11 * 4 + 10 * 24
     with pytest.raises(KeyError):
         bench.algorithmic_bytes("nope", ai)
 
@@ -47,3 +49,8 @@ def test_cpu_baseline_compares_solutions():
     bad = [xs[0] * (1 + 1e-3), xs[1]]
     _, _, cmp = bench.cpu_baseline(p, systems[:1], 0.0, gpu_xs=bad)
     assert abs(cmp[0][0] - 1e-3) < 1e-9
+
+
+def test_host_cpu_reports_cores():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and h["cpu_count"] >= h["nproc"]

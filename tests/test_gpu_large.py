@@ -1,0 +1,180 @@
+"""GPU parity at the workload sizes and on the matrix shapes the default workloads leave out.
+
+* 500k sequence (FGMRES(30)) on every system, and the 2M instance (FGMRES(50)): factors
+  bit-identical to the oracle's static-pivot refactorization, direct solve within the LU
+  backward-error bound on every row, FGMRES-IR against the oracle's refinement of the same
+  factors and against a fresh pivoted solve, with the condition estimate per result.
+* The moderately conditioned family (D in [1e-2, 1e2], delta = 1), where the forward-error
+  bound 1e-8 * cond-estimate is informative: FP64 and FP32-preconditioned solves (no
+  fallback) checked against the oracle's fresh pivoted solve system by system.
+* An arrow-head KKT: a factor column longer than the refactorization's LDS stage (updated
+  in HBM) and an L row too long for a staged solve tile (an unstaged tile), FP64 and FP32.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import kkt_synth as ks
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2401_13926_amd as P  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def cuda(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev)
+
+
+def rel_inf(x, y):
+    return float(np.abs(x - y).max() / np.abs(y).max())
+
+
+def check_backward_error(f, lx, ux, b, x, unit):
+    """|P b - L U z| <= 4 w u |L| |U| |z| on every row (z = Q^T x, w = longest row of L or U):
+    the componentwise bound of a forward/backward substitution pair with these factors."""
+    import scipy.sparse as sp
+    n = f.n
+    L = sp.csc_matrix((lx, f.pinv[f.Li], f.Lp), shape=(n, n)) + sp.eye(n, format="csc")
+    U = sp.csc_matrix((ux, f.Ui, f.Up), shape=(n, n))
+    z = x[f.Q]
+    r = np.abs(b[f.prow] - L @ (U @ z))
+    bound = abs(L) @ (abs(U) @ np.abs(z))
+    w = max(np.diff(L.tocsr().indptr).max(), np.diff(U.tocsr().indptr).max())
+    ratio = r / np.maximum(4 * w * unit * bound, 1e-300)
+    assert np.all(ratio <= 1.0), float(ratio.max())
+    return float(ratio.max())
+
+
+def refine_and_compare(p, s, f, v, b, restart, dev, label):
+    """One refactor + FGMRES-IR on the GPU against the oracle: acceptance, iteration count
+    against the oracle's refinement of the same static-pivot factors, and the distance of
+    both from a fresh pivoted solve, with that system's condition estimate."""
+    s.refactor(cuda(v, dev))
+    xg, info = s.solve(cuda(b, dev))
+    x = xg.cpu().numpy()
+    m = oracle.metrics(p.rowptr, p.colidx, v, x, b)
+    assert info["converged"] == 1 and m["nrbe"] <= 1e-12
+    assert info["nrbe"] == pytest.approx(m["nrbe"], rel=1e-6, abs=1e-30)
+    olx, oux, ng = f.refactor64(p.rowptr, p.colidx, v)
+    assert info["pivots_perturbed"] == ng
+    xo, oi = f.fgmres_ir(p.rowptr, p.colidx, v, b, Lx=olx, Ux=oux, restart=restart, mode=1, eta=1e-14)
+    assert oi["converged"]
+    xd, fd = oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=f.Q)
+    kappa = fd.condest(p.rowptr, v)
+    rel, relo = rel_inf(x, xd), rel_inf(xo, xd)
+    say("   %s: iters %d (oracle %d) nrbe %.2e rel diff vs fresh solve %.2e (oracle IR %.2e) condest %.2e"
+        % (label, info["iterations"], oi["iters"], m["nrbe"], rel, relo, kappa))
+    assert abs(info["iterations"] - oi["iters"]) <= 1
+    assert rel <= 1e-8 * kappa
+    return x, xo, xd, rel, relo
+
+
+def test_500k_sequence_fgmres_ir_every_system(dev):
+    say("500k sequence, FGMRES(30), systems 2..10")
+    p = ks.make_pattern(3)
+    v1, _ = p.system(1)
+    s = P.Solver(p.rowptr, p.colidx, v1, restart=30).bind(dev)
+    f = oracle.LU(p.rowptr, p.colidx, v1)
+    for step in range(2, ks.CONFIGS[3]["steps"] + 1):
+        v, b = p.system(step)
+        x, xo, xd, rel, relo = refine_and_compare(p, s, f, v, b, 30, dev, "system %d" % step)
+        # the GPU and the oracle refine the same factors: they land equally close to the
+        # fresh pivoted solution (measured ratio 1.0 +- 0.3)
+        assert rel <= 4.0 * relo + 1e-14
+
+
+def test_2m_refactor_direct_solve_and_fgmres(dev):
+    say("2M instance: refactor, direct solve, FGMRES(50)")
+    p = ks.make_pattern(5)
+    v1, _ = p.system(1)
+    s = P.Solver(p.rowptr, p.colidx, v1, restart=50).bind(dev)
+    say("   analysis done: nnz_l %d nnz_u %d" % (s.info()["nnz_l"], s.info()["nnz_u"]))
+    f = oracle.LU(p.rowptr, p.colidx, v1)
+    v2, b2 = p.system(2)
+    s.refactor(cuda(v2, dev))
+    torch.cuda.synchronize()
+    lx, ux = s.factor_values(0)
+    olx, oux, _ = f.refactor64(p.rowptr, p.colidx, v2)
+    assert np.array_equal(lx, olx) and np.array_equal(ux, oux)
+    del lx, ux
+    z = s.direct_solve(cuda(b2, dev)).cpu().numpy()
+    say("   direct solve: worst row at %.2f of the bound" % check_backward_error(f, olx, oux, b2, z, 2.0 ** -53))
+    refine_and_compare(p, s, f, v2, b2, 50, dev, "system 2")
+
+
+@pytest.mark.parametrize("n,m", [(35000, 25000), (290000, 210000)])
+def test_moderate_family_forward_error(dev, n, m):
+    # condition estimates of about 2e2 here, so 1e-8 * cond-estimate (~2e-6) binds; the FP32
+    # preconditioner converges without the FP64 fallback, as it does in the oracle
+    say("moderate family N =", n + m)
+    p = ks.moderate_kkt(n, m)
+    v1, _ = p.system(1)
+    s64 = P.Solver(p.rowptr, p.colidx, v1).bind(dev)
+    s32 = P.Solver(p.rowptr, p.colidx, v1, precision=P.PREC_MIXED, mixed_fallback=0).bind(dev)
+    f = oracle.LU(p.rowptr, p.colidx, v1)
+    for step in (2, 3, 4):
+        v, b = p.system(step)
+        xd, fd = oracle.direct_solve(p.rowptr, p.colidx, v, b, Q=f.Q)
+        kappa = fd.condest(p.rowptr, v)
+        assert kappa < 1e4
+        for s, label in ((s64, "fp64"), (s32, "mixed")):
+            s.refactor(cuda(v, dev))
+            xg, info = s.solve(cuda(b, dev))
+            x = xg.cpu().numpy()
+            rel = rel_inf(x, xd)
+            say("   system %d %s: iters %d nrbe %.2e rel diff %.2e bound %.2e fallback %d"
+                % (step, label, info["iterations"], info["nrbe"], rel, 1e-8 * kappa, info["fallback"]))
+            assert info["converged"] == 1 and info["nrbe"] <= 1e-12 and info["fallback"] == 0
+            assert rel <= 1e-8 * kappa
+        # the FP32-preconditioned refinement against the oracle's (precision 1): the same
+        # binary32 factors bit for bit, iteration counts within one
+        l32, u32, ng = f.refactor32(p.rowptr, p.colidx, v)
+        glx, gux = s32.factor_values(1)
+        assert np.array_equal(glx, l32.astype(np.float64)) and np.array_equal(gux, u32.astype(np.float64))
+        _, oi = f.fgmres_ir(p.rowptr, p.colidx, v, b, Lx32=l32, Ux32=u32, restart=10, mode=1, eta=1e-14)
+        assert oi["converged"] and abs(info["iterations"] - oi["iters"]) <= 1 and info["pivots_perturbed"] == ng
+
+
+@pytest.mark.parametrize("tile_kib", [0, 16])
+def test_arrow_long_column_and_unstaged_row(dev, tile_kib):
+    # one constraint couples 2,500 primal variables: its factor column (2,855 entries) is
+    # refactored in HBM, not in the 1,024-entry LDS stage, and its L row is an unstaged tile
+    say("arrow-head KKT, tile KiB", tile_kib)
+    a = ks.ArrowKKT(4000, 1500, 2500, seed=1)
+    v1, _ = a.system(1)
+    s = P.Solver(a.rowptr, a.colidx, v1, tile_lds_kib=tile_kib).bind(dev)
+    s32 = P.Solver(a.rowptr, a.colidx, v1, tile_lds_kib=tile_kib, precision=P.PREC_MIXED).bind(dev)
+    inf = s.info()
+    assert inf["max_column"] > 1024 and inf["unstaged_l"] >= 1
+    f = oracle.LU(a.rowptr, a.colidx, v1)
+    for step in (1, 2, 3):
+        v, b = a.system(step)
+        s.refactor(cuda(v, dev))
+        s32.refactor(cuda(v, dev))
+        torch.cuda.synchronize()
+        lx, ux = s.factor_values(0)
+        olx, oux, _ = f.refactor64(a.rowptr, a.colidx, v)
+        assert np.array_equal(lx, olx) and np.array_equal(ux, oux), "FP64 factors differ at step %d" % step
+        l32, u32 = s32.factor_values(1)
+        ol32, ou32, _ = f.refactor32(a.rowptr, a.colidx, v)
+        assert np.array_equal(l32, ol32.astype(np.float64)) and np.array_equal(u32, ou32.astype(np.float64))
+        z = s.direct_solve(cuda(b, dev)).cpu().numpy()
+        check_backward_error(f, olx, oux, b, z, 2.0 ** -53)
+        xg, info = s.solve(cuda(b, dev))
+        m = oracle.metrics(a.rowptr, a.colidx, v, xg.cpu().numpy(), b)
+        assert info["converged"] == 1 and m["nrbe"] <= 1e-12

@@ -52,6 +52,29 @@ def test_analysis_bit_exact_configs(cfg):
     check_parity(p.rowptr, p.colidx, v)
 
 
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_analysis_bit_exact_configs_default_tau(cfg):
+    # the default threshold 1e-10 keeps every diagonal pivot of the quasi-definite K: P = Q
+    p = ks.make_pattern(cfg)
+    v, _ = p.system(1)
+    s, f = check_parity(p.rowptr, p.colidx, v, tau=1e-10)
+    assert s.info()["offdiag_pivots"] == 0 and np.array_equal(f.prow, f.Q)
+
+
+def test_analysis_arrow_long_column_and_unstaged_row():
+    # a dense constraint row: one factor column beyond the refactorization's 1,024-entry LDS
+    # stage and an L row too long for a staged solve tile; the analysis still matches the
+    # oracle bit for bit and reports both
+    a = ks.ArrowKKT(4000, 1500, 2500, seed=1)
+    v, _ = a.system(1)
+    s, f = check_parity(a.rowptr, a.colidx, v, tau=1e-10)
+    inf = s.info()
+    assert inf["max_column"] == int((np.diff(f.Up) + np.diff(f.Lp)).max()) > 1024
+    assert inf["unstaged_l"] >= 1 and inf["tiles_l"] > inf["unstaged_l"]
+    s16 = P.Solver(a.rowptr, a.colidx, v, tile_lds_kib=16)
+    assert s16.info()["unstaged_l"] >= 1 and s16.info()["tiles_l"] > inf["tiles_l"]
+
+
 @pytest.mark.parametrize("seed", range(12))
 def test_analysis_bit_exact_small(seed):
     p = ks.small_kkt(40 + 7 * seed, 25 + 4 * seed, 300 + seed, dlog=(-8.0, 8.0))

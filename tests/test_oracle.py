@@ -82,6 +82,25 @@ def test_generator_deterministic_and_shaped():
     assert v3.shape == v1.shape and not np.array_equal(v3, v1) and not np.array_equal(b3, b1)
 
 
+def test_moderate_and_arrow_generators():
+    # the moderate family: D in [1e-2, 1e2] and delta = 1 on the (2,2) block
+    p = ks.moderate_kkt(300, 200)
+    v, b = p.system(2)
+    K = sp.csr_matrix((v, p.colidx, p.rowptr), shape=(p.N, p.N))
+    assert abs(K - K.T).max() == 0.0 and np.all(K.diagonal()[p.n:] == -1.0)
+    h = K.diagonal()[:p.n] - (1.0 + np.asarray(abs(K[:p.n, :p.n]).sum(axis=1)).ravel() - np.abs(K.diagonal()[:p.n]))
+    assert np.all((h > 10 ** -2.0 * (1 - 1e-12)) & (h < 10 ** 2.0 * (1 + 1e-12)))
+    # the arrow-head KKT: symmetric, one constraint row with `dense` entries, pattern fixed
+    a = ks.ArrowKKT(400, 150, 250, seed=3)
+    v1, b1 = a.system(1)
+    v2, b2 = a.system(2)
+    A = sp.csr_matrix((v1, a.colidx, a.rowptr), shape=(a.N, a.N))
+    assert abs(A - A.T).max() == 0.0 and oracle.check_csr(a.rowptr, a.colidx)
+    assert np.diff(a.rowptr)[a.n] == 250 + 1 and np.all(A.diagonal()[a.n:] == -ks.DUAL_REG)
+    assert not np.array_equal(v1, v2) and not np.array_equal(b1, b2)
+    assert np.array_equal(a.system(2)[0], v2)
+
+
 # ----------------------------------------------------------------------------------------
 # ordering (hand-derived cases follow the nested-dissection rules step by step)
 # ----------------------------------------------------------------------------------------
