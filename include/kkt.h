@@ -251,6 +251,18 @@ kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, doubl
  * Enqueued on `stream`, not synchronized. */
 kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x, void *stream);
 
+/* kkt_direct_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * result bit for bit, but the intermediate vectors of the two sweeps and their tile counters
+ * live in a static device array of the library (32 MiB + 256 B per GPU, held until the process
+ * ends) instead of the handle's workspace.  It calls no allocating routine.  The handle must be
+ * bound and refactored (its factors are read from its workspace), n <= 2,097,152 (else
+ * KKT_EINVAL, checked before any device call) and the handle's device current (else
+ * KKT_EINVAL).  DEVICE arrays of n float64; enqueued on `stream`, not synchronized.  Every
+ * call on one GPU uses that GPU's single copy of the array: calls that overlap on one GPU
+ * (other streams, other threads) race and give undefined results; serialize them. */
+kkt_status_t kkt_direct_solve_noalloc(kkt_handle_t h, const double *dev_b, double *dev_x, void *stream);
+
 /* Residual rho = b - K x of the last refactored K (original ordering), each row summed in
  * CSR order; with opts.residual = KKT_RESID_DD the row is carried as a double-double sum
  * (error-free products and the accurate double-word addition of Joldes, Muller and Popescu)

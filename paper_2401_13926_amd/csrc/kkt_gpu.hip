@@ -29,6 +29,7 @@
 #include <cstddef>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -827,11 +828,15 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
     }
 }
 
+// Arms the two solve vectors with the sentinel and zeroes the tile counters of the two
+// sweeps (and the wait-failure flag, when given).
 template <typename T>
-__global__ void k_fill_sentinel(int64_t n, T *a, T *b, Control *ctl) {
+__global__ void k_fill_sentinel(int64_t n, T *a, T *b, unsigned int *work_lower, unsigned int *work_upper,
+                                unsigned int *hang) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->work_lower = 0;
-        ctl->work_upper = 0;
+        *work_lower = 0;
+        *work_upper = 0;
+        if (hang) *hang = 0;
     }
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -1676,7 +1681,8 @@ unsigned int work_chunk(int64_t items, int waves) {
 
 template <typename T>
 hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T *rhs_step, T *out, double *xout,
-                       const Control *stopflag, hipStream_t s) {
+                       const Control *stopflag, hipStream_t s, unsigned int *work = nullptr,
+                       unsigned int *hang = nullptr) {
     const Analysis &a = h->an;
     TrsvArgs<T> t{};
     const bool is64 = sizeof(T) == 8;
@@ -1708,8 +1714,8 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     }
     t.out = out;
     t.stopflag = stopflag;
-    t.work = lower ? &d.ctl->work_lower : &d.ctl->work_upper;
-    t.hang = &d.ctl->hang;
+    t.work = work ? work : lower ? &d.ctl->work_lower : &d.ctl->work_upper;
+    t.hang = hang ? hang : &d.ctl->hang;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(is64 ? h->grid_trsv64 : h->grid_trsv32, t.ntiles));
     // the variant without the dense-segment path when the schedule has none
     const bool dense = sc.values() > sc.packed;
@@ -1739,7 +1745,8 @@ template <typename T> void rearm(kkt_handle_t h, hipStream_t s) {
     T *y = (T *)(sizeof(T) == 8 ? (void *)h->d.y64 : (void *)h->d.y32);
     T *z = (T *)(sizeof(T) == 8 ? (void *)h->d.z64 : (void *)h->d.z32);
     hipEvent_t e0 = prof_begin(h, KKT_K_OTHER, s);
-    k_fill_sentinel<T><<<h->grid_stream, kStreamBlock, 0, s>>>(h->an.n, y, z, h->d.ctl);
+    k_fill_sentinel<T><<<h->grid_stream, kStreamBlock, 0, s>>>(h->an.n, y, z, &h->d.ctl->work_lower,
+                                                                &h->d.ctl->work_upper, nullptr);
     prof_end(h, KKT_K_OTHER, e0, s);
 }
 
@@ -2092,6 +2099,25 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
 }  // namespace kkt
 
 // ---------------------------------------------------------------------------------------
+// Scratch of the allocation-free direct solve (kkt_direct_solve_noalloc): the two tile
+// counters and the wait-failure flag in the first 256 bytes, then the intermediate vectors
+// y = L^-1 P b and z = U^-1 y, kNoAllocMaxRows values of 8 bytes each (FP32 factors use the
+// first half of each).  One copy per GPU, for the life of the process; calls on one GPU
+// share it.
+// ---------------------------------------------------------------------------------------
+
+namespace kkt {
+constexpr int64_t kNoAllocMaxRows = int64_t(1) << 21;  // 2,097,152 rows
+constexpr size_t kNoAllocHead = 256;
+constexpr size_t kNoAllocBytes = kNoAllocHead + 2 * sizeof(double) * (size_t)kNoAllocMaxRows;  // 32 MiB + 256 B
+struct NoAllocHead {
+    unsigned int work_lower, work_upper, hang;
+};
+}  // namespace kkt
+
+static __device__ __align__(256) unsigned char scratch[kkt::kNoAllocBytes];
+
+// ---------------------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------------------
 
@@ -2162,6 +2188,41 @@ kkt_status_t repivot_impl(kkt_handle_t h, hipStream_t s) {
     h->factor_precision = h->opts.precision;
     h->repivots += 1;
     return KKT_OK;
+}
+
+// Device address of `scratch` on the current device, looked up once per device (each GPU
+// holds its own copy of the array).  The host-side name `scratch` is not a device address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// x = Q U^-1 L^-1 P b with the current factors of precision T, the intermediate vectors and
+// the tile counters in the static scratch at `base` (device address).
+template <typename T>
+hipError_t direct_solve_scratch(kkt_handle_t h, const double *b, double *x, unsigned char *base, hipStream_t s) {
+    NoAllocHead *head = (NoAllocHead *)base;
+    T *y = (T *)(base + kNoAllocHead);
+    T *z = (T *)(base + kNoAllocHead + sizeof(double) * (size_t)kNoAllocMaxRows);
+    k_fill_sentinel<T><<<h->grid_stream, kStreamBlock, 0, s>>>(h->an.n, y, z, &head->work_lower, &head->work_upper,
+                                                                &head->hang);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_trsv<T>(h, true, b, nullptr, y, nullptr, nullptr, s, &head->work_lower, &head->hang);
+    if (e != hipSuccess) return e;
+    return launch_trsv<T>(h, false, nullptr, y, z, x, nullptr, s, &head->work_upper, &head->hang);
 }
 
 }  // namespace
@@ -2484,6 +2545,26 @@ kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x
         rearm<double>(h, s);
         KKT_HIP(h, precond<double>(h, dev_b, dev_x, nullptr, s));
     }
+    return KKT_OK;
+}
+
+kkt_status_t kkt_direct_solve_noalloc(kkt_handle_t h, const double *dev_b, double *dev_x, void *stream) {
+    if (!h || !dev_b || !dev_x) return fail(h, KKT_EINVAL, "null argument");
+    if (h->an.n > kNoAllocMaxRows)
+        return fail(h, KKT_EINVAL, "kkt_direct_solve_noalloc: n = " + std::to_string(h->an.n) +
+                                       " exceeds its static scratch of " + std::to_string(kNoAllocMaxRows) + " rows");
+    if (h->device_failed) return fail(h, KKT_EDEVICE, "handle unusable after a device error");
+    if (!h->bound || !h->have_factors) return fail(h, KKT_ESTATE, "refactor before solve");
+    int dev = -1;
+    KKT_HIP(h, hipGetDevice(&dev));
+    if (dev != h->device) return fail(h, KKT_EINVAL, "the handle's device must be current");
+    void *base = nullptr;
+    KKT_HIP(h, scratch_address(dev, &base));
+    hipStream_t s = (hipStream_t)stream;
+    if (h->factor_precision == KKT_PREC_MIXED)
+        KKT_HIP(h, direct_solve_scratch<float>(h, dev_b, dev_x, (unsigned char *)base, s));
+    else
+        KKT_HIP(h, direct_solve_scratch<double>(h, dev_b, dev_x, (unsigned char *)base, s));
     return KKT_OK;
 }
 

@@ -28,7 +28,8 @@ GS_CGS2, GS_DCGS2 = 0, 1
 #: every entry point declared in include/kkt.h
 EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
            "kkt_get_factor_pattern", "kkt_get_analysis_values", "kkt_workspace_size",
-           "kkt_bind_workspace", "kkt_refactor", "kkt_solve", "kkt_direct_solve", "kkt_residual",
+           "kkt_bind_workspace", "kkt_refactor", "kkt_solve", "kkt_direct_solve", "kkt_direct_solve_noalloc",
+           "kkt_residual",
            "kkt_get_factor_values", "kkt_set_profiling", "kkt_set_profiling_mask", "kkt_get_kernel_times",
            "kkt_release",
            "kkt_last_error",
@@ -108,6 +109,7 @@ def lib():
         L.kkt_refactor.argtypes = [vp, vp, vp]
         L.kkt_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(SolveInfo), vp]
         L.kkt_direct_solve.argtypes = [vp, vp, vp, vp]
+        L.kkt_direct_solve_noalloc.argtypes = [vp, vp, vp, vp]
         L.kkt_residual.argtypes = [vp, vp, vp, vp, vp]
         L.kkt_get_factor_values.argtypes = [vp, C.c_int32, f64p, f64p, vp]
         L.kkt_set_profiling.argtypes = [vp, C.c_int32]
@@ -258,6 +260,16 @@ class Solver:
             x = torch.empty_like(b)
         self._check(lib().kkt_direct_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                                            _stream_ptr(stream)))
+        return x
+
+    def direct_solve_noalloc(self, b, x, stream=None):
+        """kkt_direct_solve_noalloc: x = Q U^-1 L^-1 P b with the library's static scratch; x is
+        the caller's output tensor (nothing is allocated)."""
+        import torch
+        for t in (b, x):
+            assert t.is_cuda and t.dtype == torch.float64 and t.numel() == self.n
+        self._check(lib().kkt_direct_solve_noalloc(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                                   _stream_ptr(stream)))
         return x
 
     def residual(self, b, x, r=None, stream=None):

@@ -192,3 +192,14 @@ def test_abi_struct_sizes_match_header(tmp_path):
     sizes = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert sizes == [C.sizeof(K.Opts), C.sizeof(K.SolveInfo), C.sizeof(K.AnalysisInfo), C.sizeof(K.KernelTimes),
                      C.sizeof(K.RequestTimes)]
+
+
+def test_noalloc_direct_solve_rejects_oversize_before_device_calls():
+    # the allocation-free direct solve has a static scratch of 2^21 rows: a larger handle is
+    # refused with KKT_EINVAL before any device call (so this runs without a GPU)
+    import ctypes as C
+    n = (1 << 21) + 1
+    s = P.Solver(np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), np.full(n, 2.0))
+    rc = K.lib().kkt_direct_solve_noalloc(s._h, C.c_void_p(8), C.c_void_p(16), None)
+    assert rc == K.KKT_EINVAL
+    assert b"static scratch" in K.lib().kkt_last_error(s._h)
