@@ -857,6 +857,9 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
             }
         a.relptr.assign(n + 1, 0);
         a.relpos.resize(total);
+        const bool flat = a.nnz_f() < ((int64_t)1 << 31);
+        a.relsrc.assign(flat ? total : 0, 0);
+        a.relslot.assign(flat ? total : 0, 0);
         std::vector<int32_t> where(n, -1);
         std::vector<int64_t> level(n, 0);
         int64_t r = 0;
@@ -873,6 +876,10 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
                         *msg = "internal: update outside the factor pattern";
                         return AN_EINVAL;
                     }
+                    if (flat) {
+                        a.relsrc[r] = (int32_t)s;
+                        a.relslot[r] = (uint16_t)std::min<int64_t>(t - a.fp[j], 65535);
+                    }
                     a.relpos[r++] = pos;
                 }
             }
@@ -880,23 +887,56 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
             for (int64_t t = a.fp[j]; t < a.fp[j + 1]; ++t) where[a.fi[t]] = -1;
         }
         a.relptr[n] = r;
+        // columns by (level, lane-sized first, index)
+        auto lane_sized = [&](int32_t j) { return flat && a.fp[j + 1] - a.fp[j] <= kLaneLen; };
         a.col_order.resize(n);
         for (int64_t j = 0; j < n; ++j) a.col_order[j] = (int32_t)j;
-        std::stable_sort(a.col_order.begin(), a.col_order.end(),
-                         [&](int32_t x, int32_t y) { return level[x] < level[y]; });
+        std::stable_sort(a.col_order.begin(), a.col_order.end(), [&](int32_t x, int32_t y) {
+            if (level[x] != level[y]) return level[x] < level[y];
+            return lane_sized(x) && !lane_sized(y);
+        });
         a.col_level.resize(n);
         for (int64_t t = 0; t < n; ++t) a.col_level[t] = (int32_t)level[a.col_order[t]];
         a.levels_refactor = n ? 1 + *std::max_element(level.begin(), level.end()) : 0;
         std::vector<int64_t> width(a.levels_refactor + 1, 0);
         for (int64_t j = 0; j < n; ++j) ++width[level[j]];
-        a.refactor_split = n;
-        int64_t pos = 0;
-        for (int64_t l = 0; l < a.levels_refactor; ++l) {
-            if (width[l] <= opt.narrow_columns) {
-                a.refactor_split = pos;
-                break;
+        a.ref_item.clear();
+        a.ref_item_lane.clear();
+        for (int64_t p0 = 0; p0 < n;) {
+            const int64_t l = level[a.col_order[p0]];
+            const int64_t p1 = p0 + width[l];
+            const bool wide = width[l] > opt.narrow_columns;
+            int64_t pe = p0;
+            while (wide && pe < p1 && lane_sized(a.col_order[pe])) ++pe;
+            for (int64_t t = p0; t < pe; t += 64) {
+                a.ref_item.push_back((int32_t)t);
+                a.ref_item_lane.push_back(1);
             }
-            pos += width[l];
+            const int64_t step = wide ? kLaneChunk : 1;
+            for (int64_t t = pe; t < p1; t += step) {
+                a.ref_item.push_back((int32_t)t);
+                a.ref_item_lane.push_back(0);
+            }
+            p0 = p1;
+        }
+        a.ref_item.push_back((int32_t)n);
+        // a wavefront runs a lane item's columns together, so none may wait for another: one
+        // level, at most 64 columns of at most kLaneLen entries (checked, since a violation
+        // would stall the refactorization until its spin limit)
+        for (size_t t = 0; t + 1 < a.ref_item.size(); ++t) {
+            const int64_t b = a.ref_item[t], e = a.ref_item[t + 1];
+            bool ok = e > b;
+            if (a.ref_item_lane[t]) {
+                ok = ok && e - b <= 64;
+                for (int64_t q = b; ok && q < e; ++q)
+                    ok = a.col_level[q] == a.col_level[b] && lane_sized(a.col_order[q]);
+            } else {
+                ok = ok && e - b <= kLaneChunk && a.col_level[e - 1] == a.col_level[b];
+            }
+            if (!ok) {
+                *msg = "internal: refactorization hand-out item " + std::to_string(t);
+                return AN_EINVAL;
+            }
         }
     }
     // --- solve layout: L strict CSR, U strict CSR, diagonal; map F -> T

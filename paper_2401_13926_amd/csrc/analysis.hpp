@@ -10,6 +10,12 @@ namespace kkt {
 
 enum { ORDER_MD = 0, ORDER_ND = 1 };
 
+// Refactorization hand-out: columns of at most kLaneLen entries run one per lane of a
+// wavefront (64 x kLaneLen entries fill its LDS stage of 1,024); longer columns of a wide
+// level are handed out kLaneChunk at a time.
+constexpr int kLaneLen = 16;
+constexpr int kLaneChunk = 8;
+
 struct AnalysisOptions {
     int ordering = ORDER_MD;     // exact minimum degree, or BFS nested dissection
     const int32_t *fixed_order = nullptr;  // when set: this column order (n entries) is used
@@ -111,15 +117,27 @@ struct Analysis {
     // entry of column k in order: offset (inside column j) of that row.
     std::vector<int64_t> relptr;  // n+1
     std::vector<int32_t> relpos;  // sum of updates
+    // The same updates as a flat list (the refactorization's lane and one-column-per-wave
+    // paths for columns staged in LDS): the F index of the L entry each update applies, and
+    // the position in column j of its source's U entry (65535 when that position does not fit
+    // 16 bits; such columns are longer than the LDS stage and never use the list).  Empty when
+    // the factor has 2^31 entries or more.
+    std::vector<int32_t> relsrc;
+    std::vector<uint16_t> relslot;
 
     // Refactorization schedule: columns sorted by (DAG level, index).
     std::vector<int32_t> col_order;
     std::vector<int32_t> col_level;  // DAG level of each col_order position (non-decreasing)
     int64_t levels_refactor = 0;
-    // Columns at col_order positions >= refactor_split belong to narrow levels (few columns
-    // each, mostly a dependency chain): they are handed out one at a time so that each starts
-    // its update chain as early as possible.
-    int64_t refactor_split = 0;
+    // Hand-out items of the refactorization, in col_order (level) order: item t covers
+    // positions [ref_item[t], ref_item[t + 1]).  In a wide level (more than narrow_columns
+    // columns) a lane item holds up to 64 columns with at most kLaneLen entries each,
+    // refactored one per lane, and the longer columns go kLaneChunk per item; in a narrow
+    // level (the dependency chain at the top of the elimination tree) every column is an item
+    // of its own, refactored by a whole wavefront.  Within a level, col_order puts the
+    // lane-sized columns first.
+    std::vector<int32_t> ref_item;
+    std::vector<uint8_t> ref_item_lane;
 
     // Row-wise triangles in step space (strict L, strict U), from which the solve schedules
     // are built.  Solve layout T = [L values | strict U values | U diagonal (n, step order)],

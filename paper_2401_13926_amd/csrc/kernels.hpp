@@ -17,6 +17,8 @@ constexpr int kTileLds = 65536;        // default LDS bytes of a staged solve ti
 constexpr int kTileLdsMin = 16 * 1024;  // smallest and largest tile budgets (gfx950: 160 KiB of LDS
 constexpr int kTileLdsMax = 150 * 1024; // per compute unit, the rest for the kernel's own arrays)
 constexpr int kRefactorLds = 1024;     // factor entries staged in LDS per wavefront
+constexpr int kWorkQueues = 8;         // refactorization hand-out queues (one per XCD of MI355X: a
+                                       // block's queue is its index mod 8, the XCD it runs on)
 // Spin limit of one dependency wait (iterations of a short sleep, a few seconds in all);
 // exceeding it marks Control::hang and lets every wave run to completion.
 constexpr unsigned int kSpinLimit = 1u << 22;
@@ -51,10 +53,11 @@ struct Control {
     double H[(kRestartMax + 1) * kRestartMax];  // rotated Hessenberg (upper triangular), column-major
     double Hbar[(kRestartMax + 1) * kRestartMax];  // DCGS2: final columns before rotation
     double hp[2][kRestartMax + 1];  // DCGS2: one-pass column j in hp[j & 1] (read by step j + 1)
-    unsigned int work_refactor;     // next column-order index to hand out (refactorization)
+    // Refactorization hand-out: kWorkQueues counters, one per 256-byte line; queue q hands out
+    // items q, q + kWorkQueues, ... to the blocks b with b % kWorkQueues == q.
+    unsigned int work_refactor[kWorkQueues * 64];
     unsigned int work_lower;        // next task index to hand out (L solve)
     unsigned int work_upper;        // next task index to hand out (U solve)
-    unsigned int work_refactor2;    // next narrow-level column to hand out (refactorization)
 };
 
 // What the host needs after each Arnoldi step, written by the normalization kernel into

@@ -189,8 +189,7 @@ __global__ void k_prep_solve(Control *c) {
 }
 
 __global__ void k_prep_refactor(Control *c) {
-    c->work_refactor = 0;
-    c->work_refactor2 = 0;
+    for (int q = 0; q < kWorkQueues; ++q) c->work_refactor[q * 64] = 0;
     c->hang = 0;
     c->knorm_bits = 0;
     c->nonfinite = 0;
@@ -254,11 +253,14 @@ template <typename T> struct RefactorArgs {
     const int32_t *order;
     const int32_t *clev;  // level of each order position
     const int32_t *f2t;
+    const int32_t *relsrc;   // per update: F index of the L entry it applies
+    const uint16_t *relslot; // per update: position of its source's U entry in the column
+    const int32_t *item;     // hand-out items: first col_order position of each (nitems + 1)
+    const uint8_t *item_lane;  // 1: one column per lane
+    int64_t nitems;
     T *F;                // factor values (ingested on entry, final on exit)
     T *Tv;               // solve layout copy
     T *Ld;               // finished L values in F layout; sentinel until written (ready flags)
-    unsigned int chunk;  // columns taken per grab below split
-    int64_t split;       // first column-order position handed out one column at a time
     int guard_fail_policy;
     Control *ctl;
 };
@@ -353,6 +355,55 @@ __device__ void refactor_chain(const RefactorArgs<T> &a, int64_t rp, int64_t c0,
     }
 }
 
+// The update chain of column j from the flat update list [rp, re) (column staged in LDS at x):
+// a round loads 64 updates at once, lane t holding update rp + t (the F index of its L entry,
+// its target position and the position of its source's U entry), and their L values; then
+// the sources of the round are applied one after another in ascending step (the updates of
+// one source are consecutive in the list and go to distinct positions, so its lanes apply
+// them together), each update as x[pos] = x[pos] - L * x[slot] from LDS.  The next round's
+// metadata is in flight while a round is applied.
+static_assert(kRefactorLds <= 65535, "update-list slots of LDS-staged columns fit 16 bits");
+
+template <typename T>
+__device__ void refactor_flat(const RefactorArgs<T> &a, int64_t rp, int64_t re, T *x) {
+    const int lane = threadIdx.x & 63;
+    unsigned int *hang = &a.ctl->hang;
+    int src = 0, pos = 0, slot = 0;
+    if (rp + lane < re) {
+        src = a.relsrc[rp + lane];
+        pos = a.relpos[rp + lane];
+        slot = a.relslot[rp + lane];
+    }
+    for (int64_t b = rp; b < re; b += 64) {
+        const int cnt = re - b < 64 ? (int)(re - b) : 64;
+        const bool mine = lane < cnt;
+        T lv = mine ? a.Ld[src] : T(0);
+        const int cpos = pos, cslot = slot, csrc = src;
+        // the next round's metadata
+        src = pos = slot = 0;
+        if (b + 64 + lane < re) {
+            src = a.relsrc[b + 64 + lane];
+            pos = a.relpos[b + 64 + lane];
+            slot = a.relslot[b + 64 + lane];
+        }
+        const int prev = __shfl_up(cslot, 1, 64);
+        unsigned long long starts = __ballot(mine && (lane == 0 || cslot != prev));
+        while (starts) {
+            const int g = __builtin_ctzll(starts);
+            starts &= starts - 1;
+            const int ge = starts ? __builtin_ctzll(starts) : cnt;
+            if (lane >= g && lane < ge) {
+                if (is_sentinel(lv)) lv = load_ready(a.Ld + csrc, hang);
+                const T u = x[cslot];
+                const T prod = lv * u;
+                x[cpos] = x[cpos] - prod;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
 // Small columns of one dependency level, run side by side: group g of kGroupLanes lanes takes
 // column src0 + g (g < b <= kGroups) with at most kGroupLen entries, staged in its share of
 // the wavefront's LDS.  Each column gets the operations of the one-column path in the same order
@@ -440,6 +491,95 @@ __device__ void refactor_group(const RefactorArgs<T> &a, T *xs_wave, int src0, i
     }
 }
 
+// One column per lane: the columns of a lane item (one dependency level, at most kLaneLen
+// entries each) run side by side, lane l taking col_order position cbeg + l.  Each column gets
+// the operations of the one-column path in the same order (staging and column max, its
+// updates in ascending source step from the flat update list, guard, division, publication),
+// so the factors are the same bits.  Entry e of lane l's column sits at xs[e * 64 + l]; no
+// lane reads another lane's entries, and columns of one level never wait for each other.
+// A wavefront applies its columns' updates eight at a time: the eight metadata loads, then
+// the eight L values, are in flight together.
+template <typename T>
+__device__ void refactor_lanes(const RefactorArgs<T> &a, T *xs, int64_t cbeg, int64_t cend) {
+    const int lane = threadIdx.x & 63;
+    const bool act = cbeg + lane < cend;
+    int64_t c0 = 0, rp = 0, re = 0;
+    int len = 0, nu = 0;
+    if (act) {
+        const int j = a.order[cbeg + lane];
+        c0 = a.fp[j];
+        len = (int)(a.fp[j + 1] - c0);
+        nu = a.fdiag[j];
+        rp = a.relptr[j];
+        re = a.relptr[j + 1];
+    }
+    T *x = xs + lane;
+    T cm = 0;
+#pragma unroll
+    for (int h = 0; h < kLaneLen; h += 8) {
+        T v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = h + e < len ? a.F[c0 + h + e] : T(0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            x[(h + e) * 64] = v[e];
+            cm = fmax(cm, fabs(v[e]));
+        }
+    }
+    unsigned int *hang = &a.ctl->hang;
+    for (int64_t b = rp; b < re; b += 8) {
+        const int cnt = re - b < 8 ? (int)(re - b) : 8;
+        int src[8], pos[8], slot[8];
+        T lv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            src[t] = 0;
+            pos[t] = 0;
+            slot[t] = 0;
+            if (t < cnt) {
+                src[t] = a.relsrc[b + t];
+                pos[t] = a.relpos[b + t];
+                slot[t] = a.relslot[b + t];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) lv[t] = t < cnt ? a.Ld[src[t]] : T(0);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t < cnt) {
+                T l = lv[t];
+                if (is_sentinel(l)) l = load_ready<T, 1>(a.Ld + src[t], hang);
+                const T u = x[slot[t] * 64];
+                const T prod = l * u;
+                x[pos[t] * 64] = x[pos[t] * 64] - prod;
+            }
+        }
+    }
+    if (!act) return;
+    T d = x[nu * 64];
+    const T ur = unit_roundoff<T>();
+    const T cmx = cm > T(0) ? cm : T(1);
+    if (!(fabs(d) > ur * cmx) || !isfinite(d)) {
+        d = (d < T(0) ? T(-1) : T(1)) * ur * cmx;
+        atomicAdd(&a.ctl->nguard, 1ull);
+        if (a.guard_fail_policy) atomicOr(&a.ctl->guard_fail, 1u);
+    }
+    // publish L(:,j) first (later columns wait for it), then the copies in F and T
+#pragma unroll
+    for (int e = 1; e < kLaneLen; ++e)
+        if (e > nu && e < len) store_ready(a.Ld + c0 + e, x[e * 64] / d);
+#pragma unroll
+    for (int e = 0; e < kLaneLen; ++e) {
+        if (e < len) {
+            T v = x[e * 64];
+            if (e == nu) v = d;
+            else if (e > nu) v = v / d;
+            a.F[c0 + e] = v;
+            a.Tv[a.f2t[c0 + e]] = v;
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(3))) k_refactor(RefactorArgs<T> a) {
     __shared__ T lds[(kCoopBlock / 64) * kRefactorLds];
@@ -448,30 +588,35 @@ __global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu
     (void)wid;
     // Columns are handed out in dependency-level order to running wavefronts only: the
     // earliest unfinished column is always held by a running wave whose earlier work is
-    // done, so the kernel finishes whatever the residency.  Positions below `split` (wide
-    // levels) go a chunk at a time; the narrow levels above it go one column at a time from
-    // a second counter, so that no column of a dependency chain waits behind another one
-    // grabbed by the same wave.
-    bool narrow = a.split <= 0;
+    // done, so the kernel finishes whatever the residency.  The items (built by the analysis)
+    // are lane items (up to 64 short columns of one level, one per lane), chunks of longer
+    // columns of a wide level, and single columns of the narrow levels, so that no column of
+    // a dependency chain waits behind another one grabbed by the same wave.
+    // Items go round robin to kWorkQueues counters, item t to queue t % kWorkQueues (one counter
+    // serializes its atomics: about 85 grabs per microsecond measured at 2M unknowns, which
+    // bounded the hand-out).  Each queue is in level order, so the minimal unfinished item is
+    // either held by a running wave or will be taken by one as long as every queue has a
+    // resident block: block b serves queue b % kWorkQueues (blocks are dispatched in index
+    // order, so any 8 resident blocks cover every queue), and a block whose queue is exhausted
+    // moves on to the next queue.
+    unsigned int queue = blockIdx.x % kWorkQueues;
+    int exhausted = 0;
     for (;;) {
-        int64_t cbeg = 0, cend = 0;
-        if (!narrow) {
-            const unsigned int c0w = grab(&a.ctl->work_refactor, a.chunk);
-            if ((int64_t)c0w >= a.split) narrow = true;
-            else {
-                cbeg = c0w;
-                cend = (int64_t)c0w + a.chunk < a.split ? (int64_t)c0w + a.chunk : a.split;
-            }
+        const unsigned int it = queue + kWorkQueues * grab(&a.ctl->work_refactor[queue * 64], 1u);
+        if ((int64_t)it >= a.nitems) {
+            if (++exhausted == kWorkQueues) break;
+            queue = (queue + 1) % kWorkQueues;
+            continue;
         }
-        if (narrow) {
-            cbeg = a.split + (int64_t)grab(&a.ctl->work_refactor2, 1u);
-            if (cbeg >= a.n) break;
-            cend = cbeg + 1;
+        const int64_t cbeg = a.item[it], cend = a.item[it + 1];
+        if (a.item_lane[it]) {
+            refactor_lanes<T>(a, xs, cbeg, cend);
+            continue;
         }
         // metadata of the whole grab at once, lane l holding column cbeg + l (a grab has at
         // most 16 columns): one dependent round trip per grab instead of two per column
         int nu_l = 0, lev_l = -1;
-        long long c0_l = 0, end_l = 0, rp_l = 0;
+        long long c0_l = 0, end_l = 0, rp_l = 0, rpe_l = 0;
         if (lane < cend - cbeg) {
             const int j_l = a.order[cbeg + lane];
             lev_l = a.clev[cbeg + lane];
@@ -479,6 +624,7 @@ __global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu
             end_l = a.fp[j_l + 1];
             nu_l = a.fdiag[j_l];
             rp_l = a.relptr[j_l];
+            rpe_l = a.relptr[j_l + 1];
         }
         for (int64_t t = cbeg; t < cend;) {
         const int src = (int)(t - cbeg);
@@ -492,7 +638,7 @@ __global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu
                 if (__shfl(lev_l, sb, 64) != lev0 || lenb > kGroupLen) break;
                 ++b;
             }
-            if (b >= 2) {
+            if (b >= 2 && !a.relsrc) {
                 refactor_group<T>(a, xs, src, b, c0_l, end_l, nu_l, rp_l);
                 t += b;
                 continue;
@@ -513,7 +659,8 @@ __global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu
         cm = wave_max(cm);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        if (in_lds) refactor_chain<T, true>(a, rpj, c0, nu, xs);
+        if (in_lds && a.relsrc) refactor_flat<T>(a, rpj, __shfl(rpe_l, src, 64), xs);
+        else if (in_lds) refactor_chain<T, true>(a, rpj, c0, nu, xs);
         else refactor_chain<T, false>(a, rpj, c0, nu, a.F + c0);
         const T *x = in_lds ? xs : a.F + c0;
         T d = x[nu];
@@ -1422,7 +1569,9 @@ struct DevLayout {
     int64_t *fp;
     int32_t *fi, *fdiag, *order, *clev, *f2t;
     int64_t *relptr, *fsrc;
-    int32_t *relpos;
+    int32_t *relpos, *relsrc, *item;
+    uint16_t *relslot;
+    uint8_t *item_lane;
     int64_t *krp;
     int32_t *lci, *uci, *kci;
     int32_t *prow, *q;
@@ -1566,7 +1715,7 @@ struct Planner {
 
 // Offsets of every array inside the workspace (also gives the total size).
 struct Offsets {
-    size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, krp, kci, l_rows, l_seg, l_tseg,
+    size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, relsrc, relslot, item, item_lane, krp, kci, l_rows, l_seg, l_tseg,
         l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, l_tden, l_sdof, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
         u_rent, u_tlds, u_tden, u_sdof, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
         z32, dv, rr, xb, part, ctl, total;
@@ -1587,6 +1736,10 @@ Offsets plan(const kkt_handle_t h) {
     o.relptr = p.take<int64_t>(n + 1);
     o.fsrc = p.take<int64_t>(f);
     o.relpos = p.take<int32_t>(a.relpos.size());
+    o.relsrc = p.take<int32_t>(a.relsrc.size());
+    o.relslot = p.take<uint16_t>(a.relslot.size());
+    o.item = p.take<int32_t>(a.ref_item.size());
+    o.item_lane = p.take<uint8_t>(a.ref_item_lane.size());
     o.krp = p.take<int64_t>(n + 1);
     o.kci = p.take<int32_t>(a.nnz);
     o.l_rows = p.take<int32_t>(n);
@@ -1670,13 +1823,6 @@ template <typename T> KrylovArgs kargs(kkt_handle_t h) {
 int stream_blocks(int64_t n) {
     int64_t b = (n + kStreamBlock - 1) / kStreamBlock;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, kStreamGridMax));
-}
-
-unsigned int work_chunk(int64_t items, int waves) {
-    // about four grabs per wavefront, at most 8 items per grab (refactorization at 500k:
-    // 2.62 ms with grabs of 8 against 2.84 with 16; 2M within 1 %; 60k uses 4 either way)
-    const int64_t c = items / (4 * (int64_t)std::max(waves, 1));
-    return (unsigned int)std::max<int64_t>(1, std::min<int64_t>(8, c));
 }
 
 template <typename T>
@@ -1770,14 +1916,14 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
     KKT_HIP(h, hipGetLastError());
     e0 = prof_begin(h, KKT_K_REFACTOR, s);
     if (precision == KKT_PREC_MIXED) {
-        const unsigned int chunk = work_chunk(a.n, h->grid_refactor32 * (kCoopBlock / 64));
-        RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.F32, d.T32,
-                              d.Ld32, chunk, h->an.refactor_split, h->opts.guard_policy, d.ctl};
+        RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.relsrc,
+                              d.relslot, d.item, d.item_lane, (int64_t)a.ref_item.size() - 1, d.F32, d.T32,
+                              d.Ld32, h->opts.guard_policy, d.ctl};
         k_refactor<float><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r);
     } else {
-        const unsigned int chunk = work_chunk(a.n, h->grid_refactor64 * (kCoopBlock / 64));
-        RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.F64, d.T64,
-                               d.Ld64, chunk, h->an.refactor_split, h->opts.guard_policy, d.ctl};
+        RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.relsrc,
+                               d.relslot, d.item, d.item_lane, (int64_t)a.ref_item.size() - 1, d.F64, d.T64,
+                               d.Ld64, h->opts.guard_policy, d.ctl};
         k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r);
     }
     prof_end(h, KKT_K_REFACTOR, e0, s);
@@ -2380,6 +2526,10 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.relptr = (int64_t *)(b + o.relptr);
     d.fsrc = (int64_t *)(b + o.fsrc);
     d.relpos = (int32_t *)(b + o.relpos);
+    d.relsrc = (int32_t *)(b + o.relsrc);
+    d.relslot = (uint16_t *)(b + o.relslot);
+    d.item = (int32_t *)(b + o.item);
+    d.item_lane = (uint8_t *)(b + o.item_lane);
     d.krp = (int64_t *)(b + o.krp);
     d.kci = (int32_t *)(b + o.kci);
     d.l_rows = (int32_t *)(b + o.l_rows);
@@ -2435,6 +2585,10 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.relptr, a.relptr, s));
     KKT_HIP(h, up(b, o.fsrc, a.fsrc, s));
     KKT_HIP(h, up(b, o.relpos, a.relpos, s));
+    KKT_HIP(h, up(b, o.relsrc, a.relsrc, s));
+    KKT_HIP(h, up(b, o.relslot, a.relslot, s));
+    KKT_HIP(h, up(b, o.item, a.ref_item, s));
+    KKT_HIP(h, up(b, o.item_lane, a.ref_item_lane, s));
     KKT_HIP(h, up(b, o.krp, a.rowptr, s));
     KKT_HIP(h, up(b, o.kci, a.colidx, s));
     KKT_HIP(h, up(b, o.l_rows, a.lsched.rows, s));
@@ -2467,8 +2621,9 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, hipMemsetAsync(d.T32, 0, a.t_size * sizeof(float), s));
     KKT_HIP(h, hipMemsetAsync(d.part, 0, (size_t)3 * kStreamGridMax * kPartStride * sizeof(double), s));
     KKT_HIP(h, hipStreamSynchronize(s));
-    h->grid_refactor64 = coop_grid((const void *)k_refactor<double>, h->device);
-    h->grid_refactor32 = coop_grid((const void *)k_refactor<float>, h->device);
+    // at least one block per hand-out queue
+    h->grid_refactor64 = std::max(kWorkQueues, coop_grid((const void *)k_refactor<double>, h->device));
+    h->grid_refactor32 = std::max(kWorkQueues, coop_grid((const void *)k_refactor<float>, h->device));
     h->grid_trsv64 = std::min(std::min(coop_grid((const void *)k_trsv<double, true, true>, h->device, h->tile_lds),
                                        coop_grid((const void *)k_trsv<double, false, true>, h->device, h->tile_lds)),
                               std::min(coop_grid((const void *)k_trsv<double, true, false>, h->device, h->tile_lds),
