@@ -226,17 +226,65 @@ __global__ void k_ingest(int64_t nnz, const double *vals, double *kval, int64_t 
     if (bad) atomicOr(&c->nonfinite, 1u);
 }
 
+// CSR row loops issue a row's loads kRowBatch at a time (index and value loads together, then
+// the gathers), so a short row costs one round of dependent loads instead of one per entry;
+// the terms are still combined one by one in ascending position.
+constexpr int kRowBatch = 8;
+
+// sum over p in [rp[i], rp[i+1]) of kval[p] * x[ci[p]], each product and sum rounded, in
+// ascending p
+__device__ __forceinline__ double row_dot(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                          const double *__restrict__ kval, const double *x, int64_t i) {
+    const int64_t e = rp[i + 1];
+    double s = 0.0;
+    for (int64_t p = rp[i]; p < e; p += kRowBatch) {
+        int c[kRowBatch];
+        double v[kRowBatch], xv[kRowBatch];
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) {
+            c[t] = p + t < e ? ci[p + t] : 0;
+            v[t] = p + t < e ? kval[p + t] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) xv[t] = p + t < e ? x[c[t]] : 0.0;
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) {
+            if (p + t < e) {
+                const double prod = v[t] * xv[t];
+                s = s + prod;
+            }
+        }
+    }
+    return s;
+}
+
 __global__ void k_rownorm(int64_t n, const int64_t *__restrict__ rp, const double *__restrict__ kval,
                           Control *c) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     double m = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double s = 0.0;
-        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += fabs(kval[p]);
+        const int64_t e = rp[i + 1];
+        for (int64_t p = rp[i]; p < e; p += kRowBatch) {
+            double v[kRowBatch];
+#pragma unroll
+            for (int t = 0; t < kRowBatch; ++t) v[t] = p + t < e ? kval[p + t] : 0.0;
+#pragma unroll
+            for (int t = 0; t < kRowBatch; ++t)
+                if (p + t < e) s += fabs(v[t]);
+        }
         m = fmax(m, s);
     }
+    // one atomic per block: atomics on one address serialize (one per wavefront cost about
+    // 100 us at 2M rows)
+    __shared__ double red[256 / 64];
     m = wave_max(m);
-    if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(&c->knorm_bits, __double_as_longlong(m));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+        if (m > 0.0) atomicMax(&c->knorm_bits, __double_as_longlong(m));
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1061,14 +1109,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_spmv_dots(KrylovArgs a, int j)
     int64_t r0, r1;
     block_rows(a.n, r0, r1);
     const double *z = a.Z + (int64_t)j * a.n;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        double s = 0.0;
-        for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
-            const double prod = a.kval[p] * z[a.ci[p]];
-            s = s + prod;
-        }
-        a.w[i] = s;
-    }
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) a.w[i] = row_dot(a.rp, a.ci, a.kval, z, i);
     __syncthreads();
     double *out = partbuf(a, 0) + (int64_t)blockIdx.x * kPartStride;
     for (int t = 0; t <= j + 1; ++t) {
@@ -1246,14 +1287,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_dcgs2_dots(KrylovArgs a, int j
     block_rows(a.n, r0, r1);
     if (matvec) {
         const double *z = a.Z + (int64_t)j * a.n;
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-            double s = 0.0;
-            for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
-                const double prod = a.kval[p] * z[a.ci[p]];
-                s = s + prod;
-            }
-            a.w[i] = s;
-        }
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) a.w[i] = row_dot(a.rp, a.ci, a.kval, z, i);
     }
     __syncthreads();
     const double *u = a.V + (int64_t)j * a.n;
@@ -1397,15 +1431,24 @@ template <bool kDD>
 __device__ __forceinline__ double resid_row(const KrylovArgs &a, const double *x, double bi, int64_t i) {
     if (kDD) {
         double hi = bi, lo = 0.0;
-        for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) dd_accumulate(hi, lo, a.kval[p], x[a.ci[p]]);
+        const int64_t e = a.rp[i + 1];
+        for (int64_t p = a.rp[i]; p < e; p += kRowBatch) {
+            int c[kRowBatch];
+            double v[kRowBatch], xv[kRowBatch];
+#pragma unroll
+            for (int t = 0; t < kRowBatch; ++t) {
+                c[t] = p + t < e ? a.ci[p + t] : 0;
+                v[t] = p + t < e ? a.kval[p + t] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < kRowBatch; ++t) xv[t] = p + t < e ? x[c[t]] : 0.0;
+#pragma unroll
+            for (int t = 0; t < kRowBatch; ++t)
+                if (p + t < e) dd_accumulate(hi, lo, v[t], xv[t]);
+        }
         return hi;
     }
-    double s = 0.0;
-    for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
-        const double prod = a.kval[p] * x[a.ci[p]];
-        s = s + prod;
-    }
-    return bi - s;
+    return bi - row_dot(a.rp, a.ci, a.kval, x, i);
 }
 
 // rho = b - K x; partials (buffer 0): ||rho||^2, ||x||^2, ||b||^2, non-finite b flag,
@@ -1902,7 +1945,7 @@ kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precisi
     const Analysis &a = h->an;
     const int64_t f = a.nnz_f();
     DevLayout &d = h->d;
-    const int rows_grid = (int)std::max<int64_t>(1, std::min<int64_t>((a.n + 255) / 256, 2048));
+    const int rows_grid = (int)std::max<int64_t>(1, std::min<int64_t>((a.n + 255) / 256, 1024));
     hipEvent_t e0 = prof_begin(h, KKT_K_INGEST, s);
     k_prep_refactor<<<1, 1, 0, s>>>(d.ctl);
     if (dev_values)
