@@ -218,9 +218,11 @@ kkt_status_t kkt_get_factor_pattern(kkt_handle_t h, int64_t *lp, int32_t *li, in
  * kkt_get_factor_pattern (host arrays, nnz_l and nnz_u entries). */
 kkt_status_t kkt_get_analysis_values(kkt_handle_t h, double *lx, double *ux);
 
-/* Device bytes needed by kkt_bind_workspace (factor values in FP64 and FP32, structure
- * arrays, Krylov basis V and Z for the restart length, scratch). */
-kkt_status_t kkt_workspace_size(kkt_handle_t h, size_t *bytes);
+/* Device bytes needed by kkt_bind_workspace for `batch` >= 1 handles of this analysis (each
+ * handle of a kkt_refactor_batch call binds a workspace of its own: factor values in FP64 and
+ * FP32, structure arrays, Krylov basis V and Z for the restart length, scratch), i.e. batch
+ * times the size of one.  Errors: KKT_EINVAL (batch < 1). */
+kkt_status_t kkt_workspace_size(kkt_handle_t h, int32_t batch, size_t *bytes);
 
 /* Bind caller-owned device memory (>= kkt_workspace_size bytes, 256-byte aligned) and upload
  * the structure arrays on `stream` (synchronous on return).  The current HIP device at this
@@ -233,6 +235,30 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
  * work completes.  Work is enqueued on `stream`; tiny-pivot guards are counted on the device
  * and reported by the next kkt_solve.  Errors: KKT_ESTATE (no workspace). */
 kkt_status_t kkt_refactor(kkt_handle_t h, const double *dev_values, void *stream);
+
+/* kkt_refactor for `count` (1..8) systems of one pattern in one refactorization launch: handle
+ * hs[b] refactors the values at DEVICE array dev_values[b] (nnz float64 each).  The handles
+ * must be distinct, bound, and share one analysis (kkt_clone copies of one handle, none of
+ * them re-pivoted since) with the same precision and guard policy.  Ingest runs per system;
+ * the columns of all systems are then handed out together, so each system's factors are the
+ * same bits as its own kkt_refactor.  Enqueued on `stream`.  Errors: KKT_EINVAL (count out of
+ * range, a handle twice, different analyses, options or devices), KKT_ESTATE (a handle not
+ * bound), KKT_EDEVICE. */
+kkt_status_t kkt_refactor_batch(const kkt_handle_t *hs, const double *const *dev_values, int32_t count,
+                                void *stream);
+
+/* kkt_refactor_batch through a HIP graph: the values are first copied into each handle's
+ * workspace (device to device, on `stream`); the ingest and refactorization kernels of the
+ * batch are captured once per (handles, their current workspace bindings, precision) and the
+ * instantiated graph is replayed on later calls with the same handles (no kernel launches from
+ * the host).  The result is the same as kkt_refactor_batch's, bit for bit.  A graph is dropped
+ * when one of its handles is released; rebinding a handle's workspace makes a new graph.
+ * Errors: those of kkt_refactor_batch. */
+kkt_status_t kkt_refactor_batch_graph(const kkt_handle_t *hs, const double *const *dev_values, int32_t count,
+                                      void *stream);
+
+/* Refactorizations of this handle replayed from a captured graph so far. */
+kkt_status_t kkt_graph_launches(kkt_handle_t h, int64_t *launches);
 
 /* Solve K x = b for the last refactored K: direct solve, refine decision, FGMRES-IR
  * (Section 2).  dev_b, dev_x: DEVICE arrays of n float64 (distinct).  tol <= 0 uses
@@ -358,6 +384,18 @@ kkt_status_t kkt_server_poll(kkt_server_t srv, int64_t ticket, int32_t *done);
 /* Counters: requests completed, slots created, slots evicted, pool bytes in use. */
 kkt_status_t kkt_server_stats(kkt_server_t srv, int64_t *completed, int64_t *slots_created,
                               int64_t *slots_evicted, int64_t *pool_in_use);
+
+/* Batching: a worker that admits a request also admits up to max_batch - 1 (1..8, default 4)
+ * queued requests of the same pattern that can get a slot, refactors them in one launch
+ * (kkt_refactor_batch, or kkt_refactor_batch_graph when use_graphs = 1, the default) and then
+ * solves them one after another on its stream.  A slot whose solve re-pivoted is retired, so
+ * that every request is served on its pattern's own analysis.  Errors: KKT_EINVAL. */
+kkt_status_t kkt_server_configure(kkt_server_t srv, int32_t max_batch, int32_t use_graphs);
+
+/* Batches of more than one request, the requests they held, and batch refactorizations
+ * launched through a graph (any batch size). */
+kkt_status_t kkt_server_batch_stats(kkt_server_t srv, int64_t *batches, int64_t *batched_requests,
+                                    int64_t *graph_launches);
 
 /* Finish every queued request, stop the workers, release all slots and patterns. */
 kkt_status_t kkt_server_destroy(kkt_server_t srv);

@@ -17,6 +17,7 @@ constexpr int kTileLds = 65536;        // default LDS bytes of a staged solve ti
 constexpr int kTileLdsMin = 16 * 1024;  // smallest and largest tile budgets (gfx950: 160 KiB of LDS
 constexpr int kTileLdsMax = 150 * 1024; // per compute unit, the rest for the kernel's own arrays)
 constexpr int kRefactorLds = 1024;     // factor entries staged in LDS per wavefront
+constexpr int kMaxBatch = 8;           // systems of one pattern refactored by one launch
 constexpr int kWorkQueues = 8;         // refactorization hand-out queues (one per XCD of MI355X: a
                                        // block's queue is its index mod 8, the XCD it runs on)
 // Spin limit of one dependency wait (iterations of a short sleep, a few seconds in all);

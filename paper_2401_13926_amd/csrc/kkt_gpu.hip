@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
@@ -628,8 +629,19 @@ __device__ void refactor_lanes(const RefactorArgs<T> &a, T *xs, int64_t cbeg, in
     }
 }
 
+// Several systems of one pattern refactored by one launch: slot b's value arrays and control
+// block; the structure arrays are shared (every slot is bound to the same analysis).
+template <typename T> struct RefactorBatch {
+    int nslots;
+    struct {
+        T *F, *Tv, *Ld;
+        Control *ctl;
+    } slot[kMaxBatch];
+};
+
 template <typename T>
-__global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(3))) k_refactor(RefactorArgs<T> a) {
+__global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(3)))
+k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
     __shared__ T lds[(kCoopBlock / 64) * kRefactorLds];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     T *xs = lds + wid * kRefactorLds;
@@ -647,14 +659,26 @@ __global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu
     // resident block: block b serves queue b % kWorkQueues (blocks are dispatched in index
     // order, so any 8 resident blocks cover every queue), and a block whose queue is exhausted
     // moves on to the next queue.
+    // With a batch of slots, hand-out position g is item g / nslots of slot g % nslots: the
+    // slots' items interleave in level order, taken from the first slot's counters.
     unsigned int queue = blockIdx.x % kWorkQueues;
     int exhausted = 0;
+    const int nslots = batch.nslots;
     for (;;) {
-        const unsigned int it = queue + kWorkQueues * grab(&a.ctl->work_refactor[queue * 64], 1u);
-        if ((int64_t)it >= a.nitems) {
+        const unsigned int g = queue + kWorkQueues * grab(&args.ctl->work_refactor[queue * 64], 1u);
+        if ((int64_t)g >= args.nitems * nslots) {
             if (++exhausted == kWorkQueues) break;
             queue = (queue + 1) % kWorkQueues;
             continue;
+        }
+        const unsigned int it = nslots > 1 ? g / nslots : g;
+        RefactorArgs<T> a = args;
+        if (nslots > 1) {
+            const int sb = (int)(g - it * nslots);
+            a.F = batch.slot[sb].F;
+            a.Tv = batch.slot[sb].Tv;
+            a.Ld = batch.slot[sb].Ld;
+            a.ctl = batch.slot[sb].ctl;
         }
         const int64_t cbeg = a.item[it], cend = a.item[it + 1];
         if (a.item_lane[it]) {
@@ -1664,6 +1688,9 @@ struct kkt_handle_s {
     int restart_alloc = 0;
     bool fp64_current = false;  // mixed mode: FP64 factors of the current system exist
     int64_t repivots = 0;       // re-pivoted factorizations so far
+    uint64_t analysis_id = 0;   // identifies the analysis (clones share it; a re-pivot gets a new one)
+    uint64_t bind_gen = 0;      // changes at every kkt_bind_workspace (graph cache validity)
+    int64_t graph_launches = 0; // refactorizations replayed from a captured graph
     unsigned long long step_token = 0;  // tag of the last Arnoldi step launched
     // per-launch timing (kkt_set_profiling)
     struct ProfRec {
@@ -1939,41 +1966,68 @@ template <typename T> void rearm(kkt_handle_t h, hipStream_t s) {
     prof_end(h, KKT_K_OTHER, e0, s);
 }
 
-// Enqueues ingest + numeric refactorization of the values at `vals` (device; when null, the
-// values already in the workspace are re-ingested).
-kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precision, hipStream_t s) {
+// Enqueues ingest + numeric refactorization of `count` systems of one pattern: handle hs[b]
+// (bound to the same analysis as hs[0]) gets the values at vals[b] (device; when null, the
+// values already in its workspace are re-ingested).  Ingest runs per system; the
+// refactorizations of all of them run in one launch, with hs[0]'s structure arrays.
+kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *vals, int count, int precision,
+                                 hipStream_t s) {
+    const kkt_handle_t h = hs[0];
     const Analysis &a = h->an;
     const int64_t f = a.nnz_f();
-    DevLayout &d = h->d;
     const int rows_grid = (int)std::max<int64_t>(1, std::min<int64_t>((a.n + 255) / 256, 1024));
+    auto fail_all = [&](const std::string &m) {
+        for (int b = 0; b < count; ++b) hs[b]->device_failed = true;
+        for (int b = 1; b < count; ++b) fail(hs[b], KKT_EDEVICE, m);
+        return fail(h, KKT_EDEVICE, m);
+    };
     hipEvent_t e0 = prof_begin(h, KKT_K_INGEST, s);
-    k_prep_refactor<<<1, 1, 0, s>>>(d.ctl);
-    if (dev_values)
-        k_ingest<<<2048, 256, 0, s>>>(a.nnz, dev_values, d.kval, f, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32,
-                                      precision, d.ctl);
-    else
-        k_ingest<<<2048, 256, 0, s>>>(a.nnz, d.kval, nullptr, f, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32,
-                                      precision, d.ctl);
-    k_rownorm<<<rows_grid, 256, 0, s>>>(a.n, d.krp, d.kval, d.ctl);
+    for (int b = 0; b < count; ++b) {
+        DevLayout &d = hs[b]->d;
+        k_prep_refactor<<<1, 1, 0, s>>>(d.ctl);
+        if (vals[b])
+            k_ingest<<<2048, 256, 0, s>>>(a.nnz, vals[b], d.kval, f, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32,
+                                          precision, d.ctl);
+        else
+            k_ingest<<<2048, 256, 0, s>>>(a.nnz, d.kval, nullptr, f, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32,
+                                          precision, d.ctl);
+        k_rownorm<<<rows_grid, 256, 0, s>>>(a.n, d.krp, d.kval, d.ctl);
+    }
     prof_end(h, KKT_K_INGEST, e0, s);
-    KKT_HIP(h, hipGetLastError());
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail_all(std::string("ingest: ") + hipGetErrorString(e));
     e0 = prof_begin(h, KKT_K_REFACTOR, s);
+    const DevLayout &d = h->d;
+    const int64_t nitems = (int64_t)a.ref_item.size() - 1;
     if (precision == KKT_PREC_MIXED) {
         RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.relsrc,
-                              d.relslot, d.item, d.item_lane, (int64_t)a.ref_item.size() - 1, d.F32, d.T32,
-                              d.Ld32, h->opts.guard_policy, d.ctl};
-        k_refactor<float><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r);
+                              d.relslot, d.item, d.item_lane, nitems, d.F32, d.T32, d.Ld32, h->opts.guard_policy,
+                              d.ctl};
+        RefactorBatch<float> bt{};
+        bt.nslots = count;
+        for (int b = 0; b < count; ++b) bt.slot[b] = {hs[b]->d.F32, hs[b]->d.T32, hs[b]->d.Ld32, hs[b]->d.ctl};
+        k_refactor<float><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r, bt);
     } else {
         RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.relsrc,
-                               d.relslot, d.item, d.item_lane, (int64_t)a.ref_item.size() - 1, d.F64, d.T64,
-                               d.Ld64, h->opts.guard_policy, d.ctl};
-        k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r);
+                               d.relslot, d.item, d.item_lane, nitems, d.F64, d.T64, d.Ld64, h->opts.guard_policy,
+                               d.ctl};
+        RefactorBatch<double> bt{};
+        bt.nslots = count;
+        for (int b = 0; b < count; ++b) bt.slot[b] = {hs[b]->d.F64, hs[b]->d.T64, hs[b]->d.Ld64, hs[b]->d.ctl};
+        k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r, bt);
     }
     prof_end(h, KKT_K_REFACTOR, e0, s);
-    KKT_HIP(h, hipGetLastError());
-    h->have_factors = true;
-    h->factor_precision = precision;
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_all(std::string("refactorization: ") + hipGetErrorString(e));
+    for (int b = 0; b < count; ++b) {
+        hs[b]->have_factors = true;
+        hs[b]->factor_precision = precision;
+    }
     return KKT_OK;
+}
+
+kkt_status_t refactor_impl(kkt_handle_t h, const double *dev_values, int precision, hipStream_t s) {
+    return refactor_batch_impl(&h, &dev_values, 1, precision, s);
 }
 
 void launch_resid(kkt_handle_t h, const KrylovArgs &ka, const double *b, const double *x, double *r, hipStream_t s) {
@@ -2315,6 +2369,11 @@ using namespace kkt;
 namespace kkt {
 namespace {
 
+uint64_t next_analysis_id() {
+    static std::atomic<uint64_t> next{1};
+    return next.fetch_add(1);
+}
+
 AnalysisOptions analysis_options(const kkt_opts_t &o, int64_t n) {
     AnalysisOptions ao;
     ao.ordering = o.ordering == KKT_ORDER_ND ? ORDER_ND : ORDER_MD;
@@ -2355,9 +2414,12 @@ kkt_status_t repivot_impl(kkt_handle_t h, hipStream_t s) {
         return fail(h, rc == AN_ESINGULAR ? KKT_ESINGULAR : KKT_EINVAL, "re-pivoting: " + msg);
     Analysis keep = std::move(h->an);
     h->an = std::move(na);
+    const uint64_t keep_id = h->analysis_id;
+    h->analysis_id = next_analysis_id();
     const size_t need = plan(h).total;
     if (need > h->ws_bytes) {
         h->an = std::move(keep);
+        h->analysis_id = keep_id;
         return fail(h, KKT_ENOMEM, "re-pivoting needs a workspace of " + std::to_string(need) + " bytes, " +
                                        std::to_string(h->ws_bytes) + " are bound");
     }
@@ -2377,6 +2439,52 @@ kkt_status_t repivot_impl(kkt_handle_t h, hipStream_t s) {
     h->factor_precision = h->opts.precision;
     h->repivots += 1;
     return KKT_OK;
+}
+
+// Validates a batch for kkt_refactor_batch(_graph): 1..kMaxBatch distinct bound handles of one
+// analysis with the same precision and guard policy, and a value array for each.
+kkt_status_t check_batch(const kkt_handle_t *hs, const double *const *dev_values, int32_t count) {
+    if (!hs || !dev_values || count < 1 || count > kMaxBatch)
+        return fail(hs && count > 0 ? hs[0] : nullptr, KKT_EINVAL, "need 1..8 handles and value arrays");
+    for (int b = 0; b < count; ++b) {
+        kkt_handle_t h = hs[b];
+        if (!h || !dev_values[b]) return fail(hs[0], KKT_EINVAL, "null handle or value array in the batch");
+        if (h->device_failed) return fail(h, KKT_EDEVICE, "handle unusable after a device error");
+        if (!h->bound) return fail(h, KKT_ESTATE, "no workspace bound");
+        if (h->analysis_id != hs[0]->analysis_id || h->opts.precision != hs[0]->opts.precision ||
+            h->opts.guard_policy != hs[0]->opts.guard_policy || h->device != hs[0]->device)
+            return fail(hs[0], KKT_EINVAL,
+                        "a batch needs handles of one analysis with the same precision, guard policy and device");
+        for (int c = 0; c < b; ++c)
+            if (hs[c] == h) return fail(hs[0], KKT_EINVAL, "a handle appears twice in the batch");
+    }
+    return KKT_OK;
+}
+
+// Graphs captured by kkt_refactor_batch_graph, one per (handles, their workspace bindings,
+// precision); an entry is dropped when one of its handles is released.
+struct BatchGraph {
+    std::vector<kkt_handle_t> hs;
+    std::vector<uint64_t> gens;
+    int precision = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+constexpr size_t kMaxGraphs = 128;
+std::mutex g_graph_mu;
+std::vector<BatchGraph> g_graphs;
+
+void drop_graphs_of(kkt_handle_t h) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (size_t i = 0; i < g_graphs.size();) {
+        if (std::find(g_graphs[i].hs.begin(), g_graphs[i].hs.end(), h) != g_graphs[i].hs.end()) {
+            (void)hipGraphExecDestroy(g_graphs[i].exec);
+            (void)hipGraphDestroy(g_graphs[i].graph);
+            g_graphs.erase(g_graphs.begin() + i);
+        } else {
+            ++i;
+        }
+    }
 }
 
 // Device address of `scratch` on the current device, looked up once per device (each GPU
@@ -2474,6 +2582,7 @@ kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowpt
     }
     AnalysisOptions ao = analysis_options(h->opts, n);
     h->tile_lds = (size_t)ao.tile_lds;
+    h->analysis_id = next_analysis_id();
     std::string msg;
     int rc = analyze(ao, n, rowptr, colidx, values_first, h->an, &msg);
     if (rc != AN_OK) {
@@ -2531,9 +2640,10 @@ kkt_status_t kkt_get_analysis_values(kkt_handle_t h, double *lx, double *ux) {
     return KKT_OK;
 }
 
-kkt_status_t kkt_workspace_size(kkt_handle_t h, size_t *bytes) {
+kkt_status_t kkt_workspace_size(kkt_handle_t h, int32_t batch, size_t *bytes) {
     if (!h || !bytes) return fail(h, KKT_EINVAL, "null argument");
-    *bytes = plan(h).total;
+    if (batch < 1) return fail(h, KKT_EINVAL, "batch must be at least 1");
+    *bytes = plan(h).total * (size_t)batch;
     return KKT_OK;
 }
 
@@ -2545,6 +2655,7 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     if (((uintptr_t)dev_ptr & 255) != 0) return fail(h, KKT_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     KKT_HIP(h, hipGetDevice(&h->device));
+    h->bind_gen = next_analysis_id();
     if (!h->host_ctl) {
         KKT_HIP(h, hipHostMalloc((void **)&h->host_ctl, sizeof(ControlSummary),
                                  hipHostMallocMapped | hipHostMallocCoherent));
@@ -2693,6 +2804,89 @@ kkt_status_t kkt_refactor(kkt_handle_t h, const double *dev_values, void *stream
     return refactor_impl(h, dev_values, h->opts.precision, (hipStream_t)stream);
 }
 
+kkt_status_t kkt_refactor_batch(const kkt_handle_t *hs, const double *const *dev_values, int32_t count,
+                                void *stream) {
+    const kkt_status_t st = check_batch(hs, dev_values, count);
+    if (st != KKT_OK) return st;
+    for (int b = 0; b < count; ++b) hs[b]->fp64_current = false;
+    return refactor_batch_impl(hs, dev_values, count, hs[0]->opts.precision, (hipStream_t)stream);
+}
+
+kkt_status_t kkt_refactor_batch_graph(const kkt_handle_t *hs, const double *const *dev_values, int32_t count,
+                                      void *stream) {
+    kkt_status_t st = check_batch(hs, dev_values, count);
+    if (st != KKT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // the values go into each workspace first; the graph re-ingests them from there
+    for (int b = 0; b < count; ++b)
+        KKT_HIP(hs[b], hipMemcpyAsync(hs[b]->d.kval, dev_values[b], hs[b]->an.nnz * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s));
+    const int precision = hs[0]->opts.precision;
+    std::vector<uint64_t> gens(count);
+    for (int b = 0; b < count; ++b) gens[b] = hs[b]->bind_gen;
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (const BatchGraph &g : g_graphs)
+            if (g.precision == precision && g.gens == gens &&
+                std::equal(g.hs.begin(), g.hs.end(), hs, hs + count) && (int)g.hs.size() == count)
+                exec = g.exec;
+    }
+    if (!exec) {
+        const std::vector<const double *> staged(count, nullptr);
+        // Capture only records the launches, so it runs on a private stream (the caller's may be
+        // the legacy default stream, which cannot capture); the graph is launched on the
+        // caller's stream below.  No per-launch timing events inside a graph.
+        hipStream_t cs = nullptr;
+        KKT_HIP(hs[0], hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        const uint32_t mask = hs[0]->prof_mask;
+        hs[0]->prof_mask = 0;
+        hipError_t eb = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        st = eb == hipSuccess ? refactor_batch_impl(hs, staged.data(), count, precision, cs) : KKT_OK;
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = eb == hipSuccess ? hipStreamEndCapture(cs, &graph) : eb;
+        hs[0]->prof_mask = mask;
+        (void)hipStreamDestroy(cs);
+        if (st != KKT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        KKT_HIP(hs[0], ec);
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            KKT_HIP(hs[0], ei);
+        }
+        BatchGraph g;
+        g.hs.assign(hs, hs + count);
+        g.gens = gens;
+        g.precision = precision;
+        g.graph = graph;
+        g.exec = exec;
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        if (g_graphs.size() >= kMaxGraphs) {  // the oldest goes
+            (void)hipGraphExecDestroy(g_graphs.front().exec);
+            (void)hipGraphDestroy(g_graphs.front().graph);
+            g_graphs.erase(g_graphs.begin());
+        }
+        g_graphs.push_back(g);
+    }
+    KKT_HIP(hs[0], hipGraphLaunch(exec, s));
+    for (int b = 0; b < count; ++b) {
+        hs[b]->fp64_current = false;
+        hs[b]->have_factors = true;
+        hs[b]->factor_precision = precision;
+        ++hs[b]->graph_launches;
+    }
+    return KKT_OK;
+}
+
+kkt_status_t kkt_graph_launches(kkt_handle_t h, int64_t *launches) {
+    if (!h || !launches) return fail(h, KKT_EINVAL, "null argument");
+    *launches = h->graph_launches;
+    return KKT_OK;
+}
+
 kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, double tol, kkt_solve_info_t *info,
                        void *stream) {
     if (!h || !dev_b || !dev_x) return fail(h, KKT_EINVAL, "null argument");
@@ -2832,6 +3026,7 @@ kkt_status_t kkt_clone(kkt_handle_t src, kkt_handle_t *out) {
         h->opts = src->opts;
         h->an = src->an;
         h->tile_lds = src->tile_lds;
+        h->analysis_id = src->analysis_id;
     } catch (const std::bad_alloc &) {
         delete h;
         return fail(src, KKT_ENOMEM, "out of host memory");
@@ -2842,6 +3037,7 @@ kkt_status_t kkt_clone(kkt_handle_t src, kkt_handle_t *out) {
 
 kkt_status_t kkt_release(kkt_handle_t h) {
     if (!h) return KKT_OK;
+    drop_graphs_of(h);
     for (auto &r : h->ev_pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);

@@ -1,7 +1,9 @@
 // Serving loop for KKT solves of several patterns (the C ABI in kkt.h, "Serving"): pattern
 // registry, resident solver slots carved from one device pool (admission by HBM footprint),
 // a FIFO queue that lets later requests overtake one that does not fit yet, and worker
-// threads that each drive one request at a time on their own HIP stream.
+// threads that each drive a batch of same-pattern requests on their own HIP stream: one
+// refactorization launch for the batch (kkt_refactor_batch), replayed from a HIP graph
+// captured once per set of slots, then the batch's FGMRES-IR solves.
 #include "kkt.h"
 
 #include <hip/hip_runtime.h>
@@ -97,6 +99,9 @@ struct Request {
 
 struct kkt_server_s {
     int device = 0;
+    int max_batch = 4;
+    bool use_graphs = true;
+    int64_t batches = 0, batched_requests = 0, graph_launches = 0;
     char *pool = nullptr;
     size_t pool_bytes = 0;
     std::unique_ptr<PoolAllocator> alloc;
@@ -114,9 +119,11 @@ struct kkt_server_s {
 
     // Picks the first queued request that can start now, reserving (or carving) its slot.
     // Called with mu held.  Returns nullptr when none can.
-    std::shared_ptr<Request> admit(int32_t *slot_index, bool *fresh) {
+    // With only >= 0, only requests of that pattern are considered (growing a batch).
+    std::shared_ptr<Request> admit(int32_t *slot_index, bool *fresh, int32_t only = -1) {
         for (auto it = queue.begin(); it != queue.end(); ++it) {
             const int32_t p = (*it)->pattern;
+            if (only >= 0 && p != only) continue;
             int32_t found = -1;
             for (size_t s = 0; s < slots.size(); ++s)
                 if (slots[s].h && !slots[s].busy && slots[s].pattern == p) {
@@ -178,44 +185,91 @@ struct kkt_server_s {
         hipStream_t stream = nullptr;
         const bool have_stream = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
         for (;;) {
-            std::shared_ptr<Request> r;
-            int32_t si = -1;
-            bool fresh = false;
-            kkt_handle_t h = nullptr;
-            size_t off = 0, bytes = 0;
+            struct Item {
+                std::shared_ptr<Request> r;
+                int32_t si;
+                bool fresh;
+                kkt_handle_t h;
+                size_t off, bytes;
+            };
+            std::vector<Item> batch;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 for (;;) {
-                    r = admit(&si, &fresh);
-                    if (r || (stopping && queue.empty())) break;
+                    int32_t si = -1;
+                    bool fresh = false;
+                    std::shared_ptr<Request> r = admit(&si, &fresh);
+                    if (r) {
+                        batch.push_back({r, si, fresh, slots[si].h, slots[si].off, slots[si].bytes});
+                        break;
+                    }
+                    if (stopping && queue.empty()) break;
                     work_cv.wait(lk);
                 }
-                if (!r) break;
-                h = slots[si].h;
-                off = slots[si].off;
-                bytes = slots[si].bytes;
+                if (batch.empty()) break;
+                // queued requests of the same pattern join the batch while slots are free or fit
+                while ((int)batch.size() < max_batch) {
+                    int32_t si = -1;
+                    bool fresh = false;
+                    std::shared_ptr<Request> r = admit(&si, &fresh, batch[0].r->pattern);
+                    if (!r) break;
+                    batch.push_back({r, si, fresh, slots[si].h, slots[si].off, slots[si].bytes});
+                }
+                if (batch.size() > 1) {
+                    ++batches;
+                    batched_requests += (int64_t)batch.size();
+                }
             }
-            r->started = Clock::now();
-            kkt_status_t st = have_stream ? KKT_OK : KKT_EDEVICE;
-            if (st == KKT_OK && fresh) st = kkt_bind_workspace(h, pool + off, bytes, stream);
-            if (st == KKT_OK) st = kkt_refactor(h, r->values, stream);
-            if (st == KKT_OK || st == KKT_ENOCONV) st = kkt_solve(h, r->b, r->x, r->tol, &r->info, stream);
-            if (have_stream && hipStreamSynchronize(stream) != hipSuccess && st == KKT_OK) st = KKT_EDEVICE;
-            r->finished = Clock::now();
+            const auto started = Clock::now();
+            std::vector<kkt_status_t> st(batch.size(), have_stream ? KKT_OK : KKT_EDEVICE);
+            std::vector<kkt_handle_t> hs;
+            std::vector<const double *> vals;
+            for (size_t b = 0; b < batch.size(); ++b) {
+                batch[b].r->started = started;
+                if (st[b] == KKT_OK && batch[b].fresh)
+                    st[b] = kkt_bind_workspace(batch[b].h, pool + batch[b].off, batch[b].bytes, stream);
+                if (st[b] == KKT_OK) {
+                    hs.push_back(batch[b].h);
+                    vals.push_back(batch[b].r->values);
+                }
+            }
+            kkt_status_t sr = KKT_OK;
+            if (!hs.empty()) {
+                sr = use_graphs ? kkt_refactor_batch_graph(hs.data(), vals.data(), (int32_t)hs.size(), stream)
+                                : kkt_refactor_batch(hs.data(), vals.data(), (int32_t)hs.size(), stream);
+                if (sr == KKT_OK && use_graphs) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    ++graph_launches;
+                }
+            }
+            for (size_t b = 0; b < batch.size(); ++b) {
+                Request &r = *batch[b].r;
+                if (st[b] == KKT_OK) st[b] = sr;
+                if (st[b] == KKT_OK) st[b] = kkt_solve(batch[b].h, r.b, r.x, r.tol, &r.info, stream);
+                if (have_stream && hipStreamSynchronize(stream) != hipSuccess && st[b] == KKT_OK) st[b] = KKT_EDEVICE;
+                r.finished = Clock::now();
+            }
             {
                 std::lock_guard<std::mutex> lk(mu);
-                r->status = st;
-                r->slot = si;
-                r->new_slot = fresh ? 1 : 0;
-                r->done = true;
-                if (st == KKT_EDEVICE) {  // the handle is unusable: drop the slot
-                    kkt_release(slots[si].h);
-                    alloc->give(slots[si].off, slots[si].bytes);
-                    slots[si] = Slot();
-                } else {
-                    slots[si].busy = false;
+                for (size_t b = 0; b < batch.size(); ++b) {
+                    Request &r = *batch[b].r;
+                    const int32_t si = batch[b].si;
+                    r.status = st[b];
+                    r.slot = si;
+                    r.new_slot = batch[b].fresh ? 1 : 0;
+                    r.done = true;
+                    // a slot whose handle failed, or that re-pivoted (its analysis now differs
+                    // from the pattern's), is retired: every request is served by a slot on the
+                    // pattern's own analysis, so a result does not depend on the slot's history
+                    if (st[b] == KKT_EDEVICE || r.info.repivoted) {
+                        kkt_release(slots[si].h);
+                        alloc->give(slots[si].off, slots[si].bytes);
+                        slots[si] = Slot();
+                    } else {
+                        slots[si].busy = false;
+                    }
+                    ++completed;
                 }
-                ++completed;
             }
             done_cv.notify_all();
             work_cv.notify_all();
@@ -263,7 +317,7 @@ kkt_status_t kkt_server_add_pattern(kkt_server_t s, const kkt_opts_t *opts, int6
     kkt_status_t st = kkt_analyze(opts, n, rowptr, colidx, values_first, &h);
     if (st != KKT_OK) return st;
     size_t bytes = 0;
-    st = kkt_workspace_size(h, &bytes);
+    st = kkt_workspace_size(h, 1, &bytes);
     if (st != KKT_OK) {
         kkt_release(h);
         return st;
@@ -341,6 +395,24 @@ kkt_status_t kkt_server_stats(kkt_server_t s, int64_t *completed, int64_t *slots
     if (slots_created) *slots_created = s->created;
     if (slots_evicted) *slots_evicted = s->evicted;
     if (pool_in_use) *pool_in_use = (int64_t)s->alloc->used();
+    return KKT_OK;
+}
+
+kkt_status_t kkt_server_configure(kkt_server_t s, int32_t max_batch, int32_t use_graphs) {
+    if (!s || max_batch < 1 || max_batch > 8 || (use_graphs != 0 && use_graphs != 1)) return KKT_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->max_batch = max_batch;
+    s->use_graphs = use_graphs != 0;
+    return KKT_OK;
+}
+
+kkt_status_t kkt_server_batch_stats(kkt_server_t s, int64_t *batches, int64_t *batched_requests,
+                                    int64_t *graph_launches) {
+    if (!s) return KKT_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (batches) *batches = s->batches;
+    if (batched_requests) *batched_requests = s->batched_requests;
+    if (graph_launches) *graph_launches = s->graph_launches;
     return KKT_OK;
 }
 

@@ -28,13 +28,15 @@ GS_CGS2, GS_DCGS2 = 0, 1
 #: every entry point declared in include/kkt.h
 EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
            "kkt_get_factor_pattern", "kkt_get_analysis_values", "kkt_workspace_size",
-           "kkt_bind_workspace", "kkt_refactor", "kkt_solve", "kkt_direct_solve", "kkt_direct_solve_noalloc",
+           "kkt_bind_workspace", "kkt_refactor", "kkt_refactor_batch", "kkt_refactor_batch_graph",
+           "kkt_graph_launches", "kkt_solve", "kkt_direct_solve", "kkt_direct_solve_noalloc",
            "kkt_residual",
            "kkt_get_factor_values", "kkt_set_profiling", "kkt_set_profiling_mask", "kkt_get_kernel_times",
            "kkt_release",
            "kkt_last_error",
            "kkt_clone", "kkt_server_create", "kkt_server_add_pattern", "kkt_server_submit",
-           "kkt_server_wait", "kkt_server_poll", "kkt_server_stats", "kkt_server_destroy"]
+           "kkt_server_wait", "kkt_server_poll", "kkt_server_stats", "kkt_server_configure",
+           "kkt_server_batch_stats", "kkt_server_destroy"]
 
 KERNEL_CLASSES = ["ingest", "refactor", "trsv_l", "trsv_u", "spmv", "cgs", "resid", "other"]
 
@@ -104,7 +106,10 @@ def lib():
         L.kkt_get_permutations.argtypes = [vp, i32p, i32p]
         L.kkt_get_factor_pattern.argtypes = [vp, i64p, i32p, i64p, i32p]
         L.kkt_get_analysis_values.argtypes = [vp, f64p, f64p]
-        L.kkt_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.kkt_workspace_size.argtypes = [vp, C.c_int32, C.POINTER(C.c_size_t)]
+        L.kkt_refactor_batch.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int32, vp]
+        L.kkt_refactor_batch_graph.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int32, vp]
+        L.kkt_graph_launches.argtypes = [vp, C.POINTER(C.c_int64)]
         L.kkt_bind_workspace.argtypes = [vp, vp, C.c_size_t, vp]
         L.kkt_refactor.argtypes = [vp, vp, vp]
         L.kkt_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(SolveInfo), vp]
@@ -124,6 +129,8 @@ def lib():
         L.kkt_server_poll.argtypes = [vp, i64, i32p]
         L.kkt_server_stats.argtypes = [vp, i64p, i64p, i64p, i64p]
         L.kkt_server_destroy.argtypes = [vp]
+        L.kkt_server_configure.argtypes = [vp, C.c_int32, C.c_int32]
+        L.kkt_server_batch_stats.argtypes = [vp, i64p, i64p, i64p]
         L.kkt_last_error.argtypes = [vp]
         L.kkt_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -172,6 +179,22 @@ class Solver:
         self._h = h
         self.workspace = None
 
+    def graph_launches(self) -> int:
+        n = C.c_int64()
+        self._check(lib().kkt_graph_launches(self._h, C.byref(n)))
+        return n.value
+
+    def clone(self):
+        """kkt_clone: a new unbound Solver on the same analysis (for kkt_refactor_batch)."""
+        h = C.c_void_p()
+        self._check(lib().kkt_clone(self._h, C.byref(h)))
+        c = Solver.__new__(Solver)
+        c._h = h
+        c.n = self.n
+        c.opts = self.opts
+        c.workspace = None
+        return c
+
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.kkt_release(self._h)
@@ -211,9 +234,9 @@ class Solver:
         self._check(lib().kkt_get_analysis_values(self._h, _p(lx, C.c_double), _p(ux, C.c_double)))
         return lx, ux
 
-    def workspace_size(self) -> int:
+    def workspace_size(self, batch: int = 1) -> int:
         s = C.c_size_t()
-        self._check(lib().kkt_workspace_size(self._h, C.byref(s)))
+        self._check(lib().kkt_workspace_size(self._h, int(batch), C.byref(s)))
         return s.value
 
     # --- device -------------------------------------------------------------------------
@@ -310,12 +333,31 @@ class Solver:
         return {name: (int(t.launches[i]), float(t.ms[i])) for i, name in enumerate(KERNEL_CLASSES)}
 
 
+def refactor_batch(solvers, values, stream=None, graph=False):
+    """kkt_refactor_batch (graph=True: kkt_refactor_batch_graph): one refactorization launch for
+    several bound Solvers of one analysis (clones of one Solver); values: float64 CUDA tensors
+    (nnz each), one per solver."""
+    solvers, values = list(solvers), list(values)
+    if len(solvers) != len(values) or not solvers:
+        raise ValueError("one value tensor per solver")
+    for v in values:
+        assert v.is_cuda and v.element_size() == 8 and v.is_contiguous()
+    hs = (C.c_void_p * len(solvers))(*[s_._h for s_ in solvers])
+    vs = (C.c_void_p * len(values))(*[v.data_ptr() for v in values])
+    fn = lib().kkt_refactor_batch_graph if graph else lib().kkt_refactor_batch
+    rc = fn(hs, vs, len(solvers), _stream_ptr(stream))
+    if rc != KKT_OK:
+        raise KKTError(rc, lib().kkt_last_error(solvers[0]._h).decode(errors="replace"))
+    for s_, v in zip(solvers, values):
+        s_._values_ref = v
+
+
 class Server:
     """Serving loop (kkt_server_*): patterns are registered once; requests (device values, b,
     x) are queued and solved by `workers` concurrent host threads on their own streams, with
     solver slots carved from one device pool (a torch tensor of pool_bytes)."""
 
-    def __init__(self, pool_bytes: int, workers: int = 4, device=None):
+    def __init__(self, pool_bytes: int, workers: int = 4, device=None, max_batch: int = 4, graphs: bool = True):
         import torch
         dev = torch.device("cuda" if device is None else device)
         self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=dev)
@@ -327,6 +369,10 @@ class Server:
             raise KKTError(rc, "kkt_server_create failed")
         self._h = h
         self._keep = {}  # ticket -> tensors that must outlive the request
+        rc = lib().kkt_server_configure(h, int(max_batch), 1 if graphs else 0)
+        if rc != KKT_OK:
+            self.close()
+            raise KKTError(rc, "kkt_server_configure: max_batch must be 1..8")
 
     def add_pattern(self, rowptr, colidx, values_first, **opts) -> int:
         o = default_opts(**opts)
@@ -371,8 +417,11 @@ class Server:
     def stats(self) -> dict:
         v = [C.c_int64() for _ in range(4)]
         lib().kkt_server_stats(self._h, *[C.byref(x) for x in v])
+        w = [C.c_int64() for _ in range(3)]
+        lib().kkt_server_batch_stats(self._h, *[C.byref(x) for x in w])
         return dict(completed=v[0].value, slots_created=v[1].value, slots_evicted=v[2].value,
-                    pool_in_use=v[3].value)
+                    pool_in_use=v[3].value, batches=w[0].value, batched_requests=w[1].value,
+                    graph_launches=w[2].value)
 
     def close(self):
         if getattr(self, "_h", None):
