@@ -400,6 +400,91 @@ kkt_status_t kkt_server_batch_stats(kkt_server_t srv, int64_t *batches, int64_t 
 /* Finish every queued request, stop the workers, release all slots and patterns. */
 kkt_status_t kkt_server_destroy(kkt_server_t srv);
 
+/* ------------------------------------------------------------------------------------------
+ * HyKKT (Section 5, eq. (kktlineargamma)): for KKT systems [[H + D, J^T], [J, 0]] with a zero
+ * (2,2) block (eq. (kktlinear)).  Adding gamma J^T times the second block row to the first
+ * leaves the solution unchanged and gives H_gamma = H + D + gamma J^T J, symmetric positive
+ * definite; the multipliers solve S dl = J H_gamma^-1 (r_x + gamma J^T r_l) - r_l with the SPD
+ * Schur complement S = J H_gamma^-1 J^T by conjugate gradients (S applied as products, never
+ * formed), then dx = H_gamma^-1 (r_x + gamma J^T r_l - J^T dl).  The pattern of H_gamma and the
+ * map from K's values to its entries are built once (a sparse product with a fixed pattern);
+ * H_gamma is refactored per system with the analysis of the first (diagonal pivots: Cholesky
+ * up to the diagonal scaling) and applied with the staged triangular solves.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct kkt_hykkt_s *kkt_hykkt_t;
+
+typedef struct {
+    double gamma;        /* > 0: this gamma; 0 (default): gamma_scale * max_i (H + D)_ii /
+                            max_i (J^T J)_ii of the first system, kept for the sequence */
+    double gamma_scale;  /* 1e4 (the paper asks for a gamma "large enough"; CG on S converges in
+                            a few tens of iterations once gamma J^T J dominates H + D) */
+    double cg_tol;       /* stop when ||r_k||_2 <= cg_tol ||r_0||_2 (1e-12) */
+    int32_t cg_max_iter; /* iteration cap (1000); reaching it gives KKT_ENOCONV */
+    int32_t reserved;
+    kkt_opts_t lu;       /* options of the H_gamma factorization (ordering, tile budget, ...) */
+} kkt_hykkt_opts_t;
+
+typedef struct {
+    int32_t converged;      /* 1 if the CG met cg_tol */
+    int32_t cg_iterations;
+    double gamma;
+    double cg_rel_resid;    /* ||r_k|| / ||r_0|| of the CG on S */
+    double nrbe;            /* eq. (nbre) of x = [dx; dl] for the original K */
+    double rel_resid;       /* ||b - K x||_2 / ||b||_2 */
+    double true_resid;      /* ||b - K x||_2 */
+    double knorm_inf;       /* ||K||_inf */
+} kkt_hykkt_info_t;
+
+/* Fill *opts with the defaults above (lu: kkt_opts_default). */
+void kkt_hykkt_opts_default(kkt_hykkt_opts_t *opts);
+
+/* Analyse a KKT pattern with n_primal primal rows (rows and columns 0..n_primal-1 hold H + D,
+ * the rest the constraints) and the values of the first system: J, J^T and the H_gamma pattern,
+ * gamma, and the factorization analysis of H_gamma (kkt_analyze).  HOST arrays in the CSR
+ * conventions above.  Errors: KKT_EINVAL (bad CSR, 1 <= n_primal < n violated, non-finite
+ * value, a nonzero in the (2,2) block, J zero), KKT_ESINGULAR (from the H_gamma analysis),
+ * KKT_ENOMEM. */
+kkt_status_t kkt_hykkt_analyze(const kkt_hykkt_opts_t *opts, int64_t n, int64_t n_primal, const int64_t *rowptr,
+                               const int32_t *colidx, const double *values_first, kkt_hykkt_t *out);
+
+/* Device bytes for kkt_hykkt_bind_workspace (HyKKT arrays plus the H_gamma factorization's
+ * workspace). */
+kkt_status_t kkt_hykkt_workspace_size(kkt_hykkt_t h, size_t *bytes);
+
+/* Bind caller-owned device memory (>= kkt_hykkt_workspace_size bytes, 256-byte aligned) and
+ * upload the structure (synchronous on return). */
+kkt_status_t kkt_hykkt_bind_workspace(kkt_hykkt_t h, void *dev_ptr, size_t bytes, void *stream);
+
+/* New values (DEVICE, nnz float64 in the pattern's CSR order): H_gamma's entries formed on the
+ * device, then its refactorization.  Enqueued on `stream`.  Errors: KKT_ESTATE (no workspace),
+ * those of kkt_refactor. */
+kkt_status_t kkt_hykkt_refactor(kkt_hykkt_t h, const double *dev_values, void *stream);
+
+/* x = K^-1 b by HyKKT for the last refactored K.  DEVICE arrays of n float64 (distinct).
+ * Synchronizes `stream` once per 8 CG iterations and before returning; *info (may be NULL) is
+ * filled.  Errors: KKT_ESTATE (no refactorization), KKT_EINVAL (non-finite K), KKT_ENOCONV (the
+ * CG reached cg_max_iter; x holds the solution recovered from the last iterate). */
+kkt_status_t kkt_hykkt_solve(kkt_hykkt_t h, const double *dev_b, double *dev_x, kkt_hykkt_info_t *info,
+                             void *stream);
+
+/* H_gamma's pattern (HOST rp: n_primal+1, ci: nnz_hgamma), gamma, and (vals != NULL) its current
+ * values after kkt_hykkt_refactor (HOST, synchronizes `stream`). */
+kkt_status_t kkt_hykkt_get_hgamma(kkt_hykkt_t h, int64_t *rp, int32_t *ci, double *vals, double *gamma,
+                                  void *stream);
+
+/* Entries of H_gamma and products in its entries' sums (sizes of the map). */
+kkt_status_t kkt_hykkt_sizes(kkt_hykkt_t h, int64_t *nnz_hgamma, int64_t *pairs);
+
+/* The handle of the H_gamma factorization (owned by h: do not release; its getters give the
+ * permutations, factor pattern and values). */
+kkt_status_t kkt_hykkt_factor_handle(kkt_hykkt_t h, kkt_handle_t *lu);
+
+/* Message for the last failing call on h (h may be NULL for kkt_hykkt_analyze failures). */
+const char *kkt_hykkt_last_error(kkt_hykkt_t h);
+
+/* Free the handle, its H_gamma factorization handle and host memory. */
+kkt_status_t kkt_hykkt_release(kkt_hykkt_t h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,4 +4,4 @@ from .kkt import (KKTError, Solver, default_opts, lib, PREC_FP64, PREC_MIXED, GU
                   GUARD_FAIL, STOP_PAPER, STOP_NRBE, KKT_OK, KKT_EINVAL, KKT_ENOMEM, KKT_ESINGULAR,
                   KKT_ENOCONV, KKT_EDEVICE, KKT_ESTATE, EXPORTS, ORDER_MD, ORDER_ND,
                   IR_FGMRES, IR_RICHARDSON, IR_ERROR_FGMRES, RESID_FP64, RESID_DD, GS_CGS2, GS_DCGS2, Server,
-                  refactor_batch)
+                  refactor_batch, HyKKT)

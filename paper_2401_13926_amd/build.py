@@ -9,7 +9,8 @@ import sys
 PKG = pathlib.Path(__file__).resolve().parent
 ROOT = PKG.parent
 LIB = PKG / "libkkt.so"
-SOURCES = [PKG / "csrc" / "kkt_gpu.hip", PKG / "csrc" / "analysis.cpp", PKG / "csrc" / "server.cpp"]
+SOURCES = [PKG / "csrc" / "kkt_gpu.hip", PKG / "csrc" / "analysis.cpp", PKG / "csrc" / "server.cpp",
+           PKG / "csrc" / "hykkt.hip"]
 HEADERS = [PKG / "csrc" / "analysis.hpp", PKG / "csrc" / "kernels.hpp", ROOT / "include" / "kkt.h"]
 ARCH = os.environ.get("KKT_OFFLOAD_ARCH", "gfx950")
 

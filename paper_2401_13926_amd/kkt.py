@@ -36,7 +36,10 @@ EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_
            "kkt_last_error",
            "kkt_clone", "kkt_server_create", "kkt_server_add_pattern", "kkt_server_submit",
            "kkt_server_wait", "kkt_server_poll", "kkt_server_stats", "kkt_server_configure",
-           "kkt_server_batch_stats", "kkt_server_destroy"]
+           "kkt_server_batch_stats", "kkt_server_destroy",
+           "kkt_hykkt_opts_default", "kkt_hykkt_analyze", "kkt_hykkt_workspace_size", "kkt_hykkt_bind_workspace",
+           "kkt_hykkt_refactor", "kkt_hykkt_solve", "kkt_hykkt_get_hgamma", "kkt_hykkt_sizes",
+           "kkt_hykkt_factor_handle", "kkt_hykkt_last_error", "kkt_hykkt_release"]
 
 KERNEL_CLASSES = ["ingest", "refactor", "trsv_l", "trsv_u", "spmv", "cgs", "resid", "other"]
 
@@ -74,6 +77,20 @@ class SolveInfo(C.Structure):
                 ("rel_resid", C.c_double), ("rr", C.c_double), ("est_resid", C.c_double),
                 ("true_resid", C.c_double), ("knorm_inf", C.c_double), ("nsr", C.c_double),
                 ("precond_applications", C.c_int64), ("repivoted", C.c_int32), ("restored_best", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class HyOpts(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("gamma_scale", C.c_double), ("cg_tol", C.c_double),
+                ("cg_max_iter", C.c_int32), ("reserved", C.c_int32), ("lu", Opts)]
+
+
+class HyInfo(C.Structure):
+    _fields_ = [("converged", C.c_int32), ("cg_iterations", C.c_int32), ("gamma", C.c_double),
+                ("cg_rel_resid", C.c_double), ("nrbe", C.c_double), ("rel_resid", C.c_double),
+                ("true_resid", C.c_double), ("knorm_inf", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -130,11 +147,24 @@ def lib():
         L.kkt_server_stats.argtypes = [vp, i64p, i64p, i64p, i64p]
         L.kkt_server_destroy.argtypes = [vp]
         L.kkt_server_configure.argtypes = [vp, C.c_int32, C.c_int32]
+        L.kkt_hykkt_opts_default.argtypes = [C.POINTER(HyOpts)]
+        L.kkt_hykkt_opts_default.restype = None
+        L.kkt_hykkt_analyze.argtypes = [C.POINTER(HyOpts), i64, i64, i64p, i32p, f64p, C.POINTER(vp)]
+        L.kkt_hykkt_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.kkt_hykkt_bind_workspace.argtypes = [vp, vp, C.c_size_t, vp]
+        L.kkt_hykkt_refactor.argtypes = [vp, vp, vp]
+        L.kkt_hykkt_solve.argtypes = [vp, vp, vp, C.POINTER(HyInfo), vp]
+        L.kkt_hykkt_get_hgamma.argtypes = [vp, i64p, i32p, f64p, f64p, vp]
+        L.kkt_hykkt_sizes.argtypes = [vp, i64p, i64p]
+        L.kkt_hykkt_factor_handle.argtypes = [vp, C.POINTER(vp)]
+        L.kkt_hykkt_last_error.argtypes = [vp]
+        L.kkt_hykkt_last_error.restype = C.c_char_p
+        L.kkt_hykkt_release.argtypes = [vp]
         L.kkt_server_batch_stats.argtypes = [vp, i64p, i64p, i64p]
         L.kkt_last_error.argtypes = [vp]
         L.kkt_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("kkt_opts_default", "kkt_last_error"):
+            if name not in ("kkt_opts_default", "kkt_last_error", "kkt_hykkt_opts_default", "kkt_hykkt_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -434,3 +464,98 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class HyKKT:
+    """HyKKT handle (kkt_hykkt_*): KKT systems with a zero (2,2) block solved through
+    H_gamma = H + D + gamma J^T J and CG on the Schur complement; n_primal primal rows."""
+
+    def __init__(self, rowptr, colidx, values_first, n_primal, gamma=0.0, gamma_scale=1e4, cg_tol=1e-12,
+                 cg_max_iter=1000, **lu_opts):
+        self._h = None
+        rp = np.ascontiguousarray(rowptr, np.int64)
+        ci = np.ascontiguousarray(colidx, np.int32)
+        v = np.ascontiguousarray(values_first, np.float64)
+        self.n = rp.size - 1
+        self.n_primal = int(n_primal)
+        o = HyOpts()
+        lib().kkt_hykkt_opts_default(C.byref(o))
+        o.gamma, o.gamma_scale, o.cg_tol, o.cg_max_iter = float(gamma), float(gamma_scale), float(cg_tol), int(cg_max_iter)
+        o.lu = default_opts(**lu_opts)
+        h = C.c_void_p()
+        rc = lib().kkt_hykkt_analyze(C.byref(o), self.n, self.n_primal, _p(rp, C.c_int64), _p(ci, C.c_int32),
+                                     _p(v, C.c_double), C.byref(h))
+        if rc != KKT_OK:
+            raise KKTError(rc, lib().kkt_hykkt_last_error(None).decode())
+        self._h = h
+        self.workspace = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.kkt_hykkt_release(self._h)
+            self._h = None
+
+    def _check(self, rc, allow=()):
+        if rc != KKT_OK and rc not in allow:
+            raise KKTError(rc, lib().kkt_hykkt_last_error(self._h).decode())
+        return rc
+
+    def sizes(self):
+        a, b = C.c_int64(), C.c_int64()
+        self._check(lib().kkt_hykkt_sizes(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def bind(self, device=None, stream=None):
+        import torch
+        dev = torch.device("cuda" if device is None else device)
+        nb = C.c_size_t()
+        self._check(lib().kkt_hykkt_workspace_size(self._h, C.byref(nb)))
+        ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
+        base = ws.data_ptr()
+        off = (-base) % 256
+        self._check(lib().kkt_hykkt_bind_workspace(self._h, C.c_void_p(base + off), nb.value, _stream_ptr(stream)))
+        self.workspace = ws
+        return self
+
+    def refactor(self, values, stream=None):
+        assert values.is_cuda and values.element_size() == 8 and values.is_contiguous()
+        self._check(lib().kkt_hykkt_refactor(self._h, C.c_void_p(values.data_ptr()), _stream_ptr(stream)))
+        self._values_ref = values
+        return self
+
+    def solve(self, b, x=None, stream=None, allow_noconv=False):
+        import torch
+        assert b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == self.n
+        if x is None:
+            x = torch.empty_like(b)
+        info = HyInfo()
+        rc = lib().kkt_hykkt_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), C.byref(info),
+                                   _stream_ptr(stream))
+        self._check(rc, allow=(KKT_ENOCONV,) if allow_noconv else ())
+        d = info.as_dict()
+        d["status"] = rc
+        return x, d
+
+    def hgamma(self, with_values=True, stream=None):
+        """(rowptr, colidx, values or None, gamma) of H_gamma."""
+        nh, _ = self.sizes()
+        rp = np.empty(self.n_primal + 1, np.int64)
+        ci = np.empty(nh, np.int32)
+        vals = np.empty(nh) if with_values else None
+        g = C.c_double()
+        self._check(lib().kkt_hykkt_get_hgamma(self._h, _p(rp, C.c_int64), _p(ci, C.c_int32),
+                                               _p(vals, C.c_double) if with_values else None, C.byref(g),
+                                               _stream_ptr(stream) if with_values else None))
+        return rp, ci, vals, g.value
+
+    def factor_values(self, stream=None):
+        """(L, U) of H_gamma in the layout of kkt_get_factor_pattern."""
+        h = C.c_void_p()
+        self._check(lib().kkt_hykkt_factor_handle(self._h, C.byref(h)))
+        inner = Solver.__new__(Solver)
+        inner._h = h
+        inner.n = self.n_primal
+        try:
+            return inner.factor_values(0, stream)
+        finally:
+            inner._h = None  # owned by the HyKKT handle

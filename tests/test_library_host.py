@@ -203,3 +203,43 @@ def test_noalloc_direct_solve_rejects_oversize_before_device_calls():
     rc = K.lib().kkt_direct_solve_noalloc(s._h, C.c_void_p(8), C.c_void_p(16), None)
     assert rc == K.KKT_EINVAL
     assert b"static scratch" in K.lib().kkt_last_error(s._h)
+
+
+@pytest.mark.parametrize("size", [(60, 35, 41), (3500, 2500, 42)])
+def test_hykkt_analysis_matches_oracle(size):
+    # HyKKT (zero (2,2) block): gamma, the pattern of H_gamma and the factorization of system 1's
+    # H_gamma match the oracle's (the factors depend on every entry of H_gamma, so the entries
+    # match too)
+    from oracle import hykkt as hy
+    n, m, seed = size
+    p = ks.small_kkt(n, m, seed, dlog=(-8.0, 8.0), delta=0.0)
+    v, _ = p.system(1)
+    g = P.HyKKT(p.rowptr, p.colidx, v, n_primal=p.n)
+    f = hy.HyKKT(p.rowptr, p.colidx, v, n=p.n)
+    rp, ci, _, gamma = g.hgamma(with_values=False)
+    assert gamma == f.gamma
+    assert np.array_equal(rp, f.hrp) and np.array_equal(ci, f.hci)
+    h = K.C.c_void_p()
+    assert K.lib().kkt_hykkt_factor_handle(g._h, K.C.byref(h)) == 0
+    inner = P.Solver.__new__(P.Solver)
+    inner._h, inner.n = h, p.n
+    try:
+        lx, ux = inner.analysis_values()
+        prow, q = inner.permutations()
+    finally:
+        inner._h = None
+    assert np.array_equal(lx, f.lu.Lx) and np.array_equal(ux, f.lu.Ux)
+    assert np.array_equal(q, f.lu.Q) and np.array_equal(prow, f.lu.prow)
+
+
+def test_hykkt_rejects_nonzero_22_block_and_bad_sizes():
+    p = ks.small_kkt(40, 25, 9)  # delta = 1e-8 on the (2,2) block
+    v, _ = p.system(1)
+    with pytest.raises(P.KKTError) as e:
+        P.HyKKT(p.rowptr, p.colidx, v, n_primal=p.n)
+    assert e.value.code == P.KKT_EINVAL and "(2,2)" in str(e.value)
+    q = ks.small_kkt(40, 25, 9, delta=0.0)
+    w, _ = q.system(1)
+    for bad in (0, q.N):
+        with pytest.raises(P.KKTError):
+            P.HyKKT(q.rowptr, q.colidx, w, n_primal=bad)
