@@ -58,7 +58,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 # kernel-name prefixes of each class in the counter summary (the solve kernels carry a second
 # template flag: dense segments on or off)
 KERNEL_NAMES = {"trsv_l": "kkt::k_trsv<double,true", "trsv_u": "kkt::k_trsv<double,false",
-                "refactor": "kkt::k_refactor<double>", "spmv": "kkt::k_spmv_dots"}
+                "refactor": "kkt::k_refactor<double", "spmv": "kkt::k_spmv_dots"}
 
 
 def source_digest() -> str:
@@ -294,7 +294,8 @@ def run_serving(P, torch, args):
         vals.append([torch.as_tensor(v, device=dev) for v, _ in sys_k])
         rhs.append([torch.as_tensor(b, device=dev) for _, b in sys_k])
     gen_s = time.perf_counter() - t0
-    srv = P.Server(int(args.pool_gb * (1 << 30)), workers=args.workers, device=dev)
+    srv = P.Server(int(args.pool_gb * (1 << 30)), workers=args.workers, device=dev, max_batch=args.max_batch,
+                   graphs=not args.no_graphs)
     t0 = time.perf_counter()
     pids = [srv.add_pattern(p.rowptr, p.colidx, p.system(1)[0]) for p in pats]
     analysis_s = time.perf_counter() - t0
@@ -353,8 +354,61 @@ def run_serving(P, torch, args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded KKT generator, %d systems per pattern cycled)" % steps,
         "config": {"workload": "kkt_serving_8_patterns", "dims": list(ks.SERVING_DIMS), "requests": args.requests,
-                   "rate_per_s": args.rate, "workers": args.workers, "pool_gb": args.pool_gb},
+                   "rate_per_s": args.rate, "workers": args.workers, "pool_gb": args.pool_gb,
+                   "max_batch": args.max_batch, "graphs": not args.no_graphs},
         "poisson": poisson, "saturation": sat, "server": st, "analysis_s": analysis_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_hykkt(P, torch, args):
+    """HyKKT on the same workload with a zero (2,2) block: per step, the refactorization of
+    H_gamma and the CG solve of the next system; the FGMRES-IR path is timed on the same
+    systems for comparison (its (2,2) block is exactly zero as well)."""
+    import kkt_synth as ks
+    dev = torch.device("cuda:0")
+    cfg = args.config
+    pattern = ks.make_pattern(cfg, delta=0.0)
+    nsys = ks.CONFIGS[cfg]["steps"]
+    systems = [pattern.system(k) for k in range(1, nsys + 1)]
+    vals = [torch.as_tensor(v, device=dev) for v, _ in systems]
+    rhs = [torch.as_tensor(b, device=dev) for _, b in systems]
+    t0 = time.perf_counter()
+    h = P.HyKKT(pattern.rowptr, pattern.colidx, systems[0][0], n_primal=pattern.n).bind(dev)
+    analysis_s = time.perf_counter() - t0
+    print("hykkt: analysis %.1f s" % analysis_s, file=sys.stderr, flush=True)
+    steps = max(1, args.steps)
+    infos, lat = [], []
+    for i in range(args.warmup + steps):
+        k = i % nsys
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        h.refactor(vals[k])
+        _, info = h.solve(rhs[k], allow_noconv=True)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            lat.append(1e3 * (time.perf_counter() - s0))
+            infos.append(info)
+        print("hykkt step %d: %.1f ms, CG %d" % (i, 1e3 * (time.perf_counter() - s0), info["cg_iterations"]),
+              file=sys.stderr, flush=True)
+    wall = 1e-3 * sum(lat)
+    wname, restart = WORKLOADS[cfg]
+    r64 = run_gpu(P, torch, pattern, systems, min(steps, 10), 1, P.PREC_FP64, False, restart)
+    out = {
+        "metric": "KKT solves/s by HyKKT (H_gamma refactor + CG on the Schur complement, NRBE<=1e-12)",
+        "value": steps / wall, "unit": "solves/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded KKT generator with a zero (2,2) block)",
+        "config": {"workload": wname + "_delta0", "N": pattern.N, "nnz": pattern.nnz, "systems": nsys,
+                   "gamma": infos[0]["gamma"], "cg_tol": 1e-12},
+        "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+        "cg_iterations": [int(i["cg_iterations"]) for i in infos],
+        "all_converged": all(i["converged"] == 1 for i in infos),
+        "max_nrbe": max(i["nrbe"] for i in infos), "analysis_s": analysis_s,
+        "hgamma_nnz_and_factor": list(h.sizes()),
+        "fgmres_ir_same_systems": {"solves_per_s": min(steps, 10) / r64["wall"],
+                                   "iterations": [int(i["iterations"]) for i in r64["infos"]],
+                                   "max_nrbe": max(i["nrbe"] for i in r64["infos"])},
     }
     print(json.dumps(out), flush=True)
 
@@ -387,6 +441,12 @@ def main():
                     help="serving worker threads, one stream each (4: 187 solves/s, 8: 206, 16: 199 "
                          "at 200/s offered)")
     ap.add_argument("--pool-gb", type=float, default=32.0)
+    ap.add_argument("--max-batch", type=int, default=4,
+                    help="serving: most same-pattern requests refactored in one launch (1: no batching)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="serving: launch batched refactorizations directly instead of from HIP graphs")
+    ap.add_argument("--hykkt", action="store_true",
+                    help="HyKKT on the workload with a zero (2,2) block, FGMRES-IR on the same systems")
     ap.add_argument("--serve-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB device buffer 4 times (reference kernel for the "
@@ -411,6 +471,9 @@ def main():
         sys.exit(1)
     if args.serve:
         run_serving(P, torch, args)
+        return
+    if args.hykkt:
+        run_hykkt(P, torch, args)
         return
     if args.calibrate_copy:
         nbytes = 256 << 20

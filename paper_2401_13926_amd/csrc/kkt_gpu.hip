@@ -442,7 +442,7 @@ __device__ void refactor_flat(const RefactorArgs<T> &a, int64_t rp, int64_t re, 
             starts &= starts - 1;
             const int ge = starts ? __builtin_ctzll(starts) : cnt;
             if (lane >= g && lane < ge) {
-                if (is_sentinel(lv)) lv = load_ready(a.Ld + csrc, hang);
+                if (is_sentinel(lv)) lv = load_ready<T, 1>(a.Ld + csrc, hang);
                 const T u = x[cslot];
                 const T prod = lv * u;
                 x[cpos] = x[cpos] - prod;
@@ -639,7 +639,11 @@ template <typename T> struct RefactorBatch {
     } slot[kMaxBatch];
 };
 
-template <typename T>
+// kFlat: the analysis built the flat update list (every factor of fewer than 2^31 entries);
+// its columns run as lane items, from the flat list in LDS, or (longer than the LDS stage)
+// from HBM.  Without it: lane groups, the per-source chain in LDS, or from HBM.  The two
+// variants are separate kernels so that each is register-allocated for its own paths.
+template <typename T, bool kFlat>
 __global__ void __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(3)))
 k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
     __shared__ T lds[(kCoopBlock / 64) * kRefactorLds];
@@ -674,14 +678,20 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
         const unsigned int it = nslots > 1 ? g / nslots : g;
         RefactorArgs<T> a = args;
         if (nslots > 1) {
+            // selected by uniform compares, not by a dynamic index into the argument array
+            // (which the compiler would copy to per-lane scratch memory)
             const int sb = (int)(g - it * nslots);
-            a.F = batch.slot[sb].F;
-            a.Tv = batch.slot[sb].Tv;
-            a.Ld = batch.slot[sb].Ld;
-            a.ctl = batch.slot[sb].ctl;
+#pragma unroll
+            for (int q = 1; q < kMaxBatch; ++q)
+                if (q == sb) {
+                    a.F = batch.slot[q].F;
+                    a.Tv = batch.slot[q].Tv;
+                    a.Ld = batch.slot[q].Ld;
+                    a.ctl = batch.slot[q].ctl;
+                }
         }
         const int64_t cbeg = a.item[it], cend = a.item[it + 1];
-        if (a.item_lane[it]) {
+        if (kFlat && a.item_lane[it]) {
             refactor_lanes<T>(a, xs, cbeg, cend);
             continue;
         }
@@ -700,7 +710,7 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
         }
         for (int64_t t = cbeg; t < cend;) {
         const int src = (int)(t - cbeg);
-        {
+        if (!kFlat) {
             // a run of small columns of one level goes to lane groups, kGroups at a time
             const int lev0 = __shfl(lev_l, src, 64);
             int b = 0;
@@ -710,7 +720,7 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
                 if (__shfl(lev_l, sb, 64) != lev0 || lenb > kGroupLen) break;
                 ++b;
             }
-            if (b >= 2 && !a.relsrc) {
+            if (b >= 2) {
                 refactor_group<T>(a, xs, src, b, c0_l, end_l, nu_l, rp_l);
                 t += b;
                 continue;
@@ -731,7 +741,7 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
         cm = wave_max(cm);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        if (in_lds && a.relsrc) refactor_flat<T>(a, rpj, __shfl(rpe_l, src, 64), xs);
+        if (kFlat && in_lds) refactor_flat<T>(a, rpj, __shfl(rpe_l, src, 64), xs);
         else if (in_lds) refactor_chain<T, true>(a, rpj, c0, nu, xs);
         else refactor_chain<T, false>(a, rpj, c0, nu, a.F + c0);
         const T *x = in_lds ? xs : a.F + c0;
@@ -2006,7 +2016,8 @@ kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *va
         RefactorBatch<float> bt{};
         bt.nslots = count;
         for (int b = 0; b < count; ++b) bt.slot[b] = {hs[b]->d.F32, hs[b]->d.T32, hs[b]->d.Ld32, hs[b]->d.ctl};
-        k_refactor<float><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r, bt);
+        if (!a.relsrc.empty()) k_refactor<float, true><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r, bt);
+        else k_refactor<float, false><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r, bt);
     } else {
         RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.relsrc,
                                d.relslot, d.item, d.item_lane, nitems, d.F64, d.T64, d.Ld64, h->opts.guard_policy,
@@ -2014,7 +2025,8 @@ kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *va
         RefactorBatch<double> bt{};
         bt.nslots = count;
         for (int b = 0; b < count; ++b) bt.slot[b] = {hs[b]->d.F64, hs[b]->d.T64, hs[b]->d.Ld64, hs[b]->d.ctl};
-        k_refactor<double><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r, bt);
+        if (!a.relsrc.empty()) k_refactor<double, true><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r, bt);
+        else k_refactor<double, false><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r, bt);
     }
     prof_end(h, KKT_K_REFACTOR, e0, s);
     e = hipGetLastError();
@@ -2776,8 +2788,11 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, hipMemsetAsync(d.part, 0, (size_t)3 * kStreamGridMax * kPartStride * sizeof(double), s));
     KKT_HIP(h, hipStreamSynchronize(s));
     // at least one block per hand-out queue
-    h->grid_refactor64 = std::max(kWorkQueues, coop_grid((const void *)k_refactor<double>, h->device));
-    h->grid_refactor32 = std::max(kWorkQueues, coop_grid((const void *)k_refactor<float>, h->device));
+    const bool flat = !h->an.relsrc.empty();
+    h->grid_refactor64 = std::max(kWorkQueues, coop_grid(flat ? (const void *)k_refactor<double, true>
+                                                              : (const void *)k_refactor<double, false>, h->device));
+    h->grid_refactor32 = std::max(kWorkQueues, coop_grid(flat ? (const void *)k_refactor<float, true>
+                                                              : (const void *)k_refactor<float, false>, h->device));
     h->grid_trsv64 = std::min(std::min(coop_grid((const void *)k_trsv<double, true, true>, h->device, h->tile_lds),
                                        coop_grid((const void *)k_trsv<double, false, true>, h->device, h->tile_lds)),
                               std::min(coop_grid((const void *)k_trsv<double, true, false>, h->device, h->tile_lds),
