@@ -253,6 +253,112 @@ class Dissector {
 };
 
 // ---------------------------------------------------------------------------------------
+// Reverse Cuthill-McKee order of the graph of A + A^T without its diagonal (the order of the
+// vectors inside a solve; it only decides where the matrix-vector products find their
+// operands, never an operation or its order).  Components by their smallest vertex; in each,
+// the start is pseudo-peripheral (least degree in the component, ties: smallest index, then
+// the least-degree vertex of the last BFS level, ties: smallest, while the eccentricity
+// grows); BFS visits the unvisited neighbours of a vertex by ascending (degree, index); the
+// concatenated order is reversed.  perm[k] = vertex at position k.
+// ---------------------------------------------------------------------------------------
+void rcm_order(int64_t n, const int64_t *rp, const int32_t *ci, std::vector<int32_t> &perm) {
+    std::vector<int64_t> gp(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] != i) {
+                ++gp[i + 1];
+                ++gp[ci[p] + 1];
+            }
+    for (int64_t i = 0; i < n; ++i) gp[i + 1] += gp[i];
+    std::vector<int32_t> gi(gp[n]);
+    {
+        std::vector<int64_t> w(gp.begin(), gp.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+                if (ci[p] != i) {
+                    gi[w[i]++] = ci[p];
+                    gi[w[ci[p]]++] = (int32_t)i;
+                }
+    }
+    // sorted, duplicates (entries present in both triangles) removed
+    std::vector<int64_t> deg(n);
+    {
+        int64_t out = 0, beg = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t end = gp[i + 1];
+            std::sort(gi.begin() + beg, gi.begin() + end);
+            const int64_t start = out;
+            for (int64_t p = beg; p < end; ++p)
+                if (p == beg || gi[p] != gi[p - 1]) gi[out++] = gi[p];
+            gp[i] = start;
+            beg = end;
+            deg[i] = out - start;
+        }
+        gp[n] = out;
+        gi.resize(out);
+    }
+    std::vector<int32_t> level(n, -1), comp;
+    std::vector<uint8_t> done(n, 0);
+    // BFS levels from r inside the component (level[] reset for `comp` afterwards); returns the
+    // eccentricity and leaves the last level's least-(degree, index) vertex in *far
+    auto bfs = [&](int32_t r, int32_t *far) {
+        std::vector<int32_t> q{r};
+        level[r] = 0;
+        for (size_t h = 0; h < q.size(); ++h) {
+            const int32_t v = q[h];
+            for (int64_t p = gp[v]; p < gp[v + 1]; ++p)
+                if (level[gi[p]] < 0) {
+                    level[gi[p]] = level[v] + 1;
+                    q.push_back(gi[p]);
+                }
+        }
+        const int32_t ecc = level[q.back()];
+        int32_t best = q.back();
+        for (const int32_t v : q)
+            if (level[v] == ecc && (deg[v] < deg[best] || (deg[v] == deg[best] && v < best))) best = v;
+        *far = best;
+        for (const int32_t v : q) level[v] = -1;
+        return std::make_pair(ecc, std::move(q));
+    };
+    perm.clear();
+    perm.reserve(n);
+    std::vector<int32_t> nb;
+    for (int64_t s0 = 0; s0 < n; ++s0) {
+        if (done[s0]) continue;
+        int32_t far = 0;
+        const std::vector<int32_t> members = bfs((int32_t)s0, &far).second;
+        int32_t r = members[0];
+        for (const int32_t v : members)
+            if (deg[v] < deg[r] || (deg[v] == deg[r] && v < r)) r = v;
+        int32_t ecc = bfs(r, &far).first;
+        for (;;) {
+            int32_t far2 = 0;
+            const int32_t e2 = bfs(far, &far2).first;
+            if (e2 <= ecc) break;
+            r = far;
+            ecc = e2;
+            far = far2;
+        }
+        const size_t head0 = perm.size();
+        perm.push_back(r);
+        done[r] = 1;
+        for (size_t h = head0; h < perm.size(); ++h) {
+            const int32_t v = perm[h];
+            nb.clear();
+            for (int64_t p = gp[v]; p < gp[v + 1]; ++p)
+                if (!done[gi[p]]) {
+                    done[gi[p]] = 1;
+                    nb.push_back(gi[p]);
+                }
+            std::sort(nb.begin(), nb.end(),
+                      [&](int32_t x, int32_t y) { return deg[x] < deg[y] || (deg[x] == deg[y] && x < y); });
+            perm.insert(perm.end(), nb.begin(), nb.end());
+        }
+    }
+    std::reverse(perm.begin(), perm.end());
+}
+
+// ---------------------------------------------------------------------------------------
 // Exact minimum degree: n times, take the live vertex whose current elimination-graph
 // degree is smallest (ties: smallest index), make its live neighbours pairwise adjacent and
 // remove it.  Priority: an ordered set of (degree, vertex); adjacency kept sorted.
@@ -992,7 +1098,45 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
     return AN_OK;
 }
 
+// The Krylov side's copy of K in the vector order vperm (reverse Cuthill-McKee): row k is
+// original row vperm[k] with its entries in their original order and columns renumbered, the
+// source position of every entry, the factor entries' sources in that copy, and the pivot
+// permutations composed with it.
+void build_vector_order(Analysis &a) {
+    const int64_t n = a.n, nnz = a.nnz;
+    rcm_order(n, a.rowptr.data(), a.colidx.data(), a.vperm);
+    a.vpinv.assign(n, 0);
+    for (int64_t k = 0; k < n; ++k) a.vpinv[a.vperm[k]] = (int32_t)k;
+    a.krp.assign(n + 1, 0);
+    a.kci.resize(nnz);
+    a.ksrc.resize(nnz);
+    std::vector<int64_t> epos(nnz);
+    int64_t w = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const int32_t i = a.vperm[k];
+        a.krp[k] = w;
+        for (int64_t p = a.rowptr[i]; p < a.rowptr[i + 1]; ++p) {
+            a.kci[w] = a.vpinv[a.colidx[p]];
+            a.ksrc[w] = p;
+            epos[p] = w++;
+        }
+    }
+    a.krp[n] = w;
+    a.fsrc_k.resize(a.fsrc.size());
+    for (size_t t = 0; t < a.fsrc.size(); ++t) a.fsrc_k[t] = a.fsrc[t] >= 0 ? epos[a.fsrc[t]] : -1;
+    a.prow_k.resize(n);
+    a.q_k.resize(n);
+    for (int64_t k = 0; k < n; ++k) {
+        a.prow_k[k] = a.vpinv[a.prow[k]];
+        a.q_k[k] = a.vpinv[a.q[k]];
+    }
+}
+
 }  // namespace
+
+void vector_order(int64_t n, const int64_t *rowptr, const int32_t *colidx, std::vector<int32_t> &perm) {
+    rcm_order(n, rowptr, colidx, perm);
+}
 
 int nested_dissection(int64_t n, const int64_t *rowptr, const int32_t *colidx, int64_t leaf,
                       std::vector<int32_t> &q) {
@@ -1032,6 +1176,7 @@ int analyze(const AnalysisOptions &opt, int64_t n, const int64_t *rowptr, const 
         if (rc != AN_OK) return rc;
         rc = build_layouts(opt, a, msg);
         if (rc != AN_OK) return rc;
+        build_vector_order(a);
     } catch (const std::bad_alloc &) {
         *msg = "out of host memory";
         return AN_ENOMEM;

@@ -154,6 +154,19 @@ struct Analysis {
     // Exchange layout -> F position (for copying device values back).
     std::vector<int64_t> l2f, u2f;
 
+    // Order of the vectors inside a solve (the Krylov basis, residuals, iterates): position k
+    // holds original index vperm[k], a reverse Cuthill-McKee order of K + K^T, so that the rows
+    // one block of the matrix-vector products handles reference nearby entries.  The Krylov
+    // kernels' copy of K is in that order: row k is original row vperm[k], its entries in their
+    // original order with columns renumbered by vpinv (each row's terms are still summed in
+    // ascending original column), ksrc the original CSR position of each entry.  fsrc_k is
+    // fsrc in terms of that copy; prow_k, q_k are prow and q renumbered by vpinv.
+    std::vector<int32_t> vperm, vpinv;
+    std::vector<int64_t> krp;
+    std::vector<int32_t> kci;
+    std::vector<int64_t> ksrc, fsrc_k;
+    std::vector<int32_t> prow_k, q_k;
+
     double seconds = 0.0;
 
     int64_t nnz_l() const { return (int64_t)li.size(); }
@@ -168,7 +181,8 @@ enum AnalysisStatus { AN_OK = 0, AN_EINVAL = 1, AN_ENOMEM = 2, AN_ESINGULAR = 3 
 int analyze(const AnalysisOptions &opt, int64_t n, const int64_t *rowptr, const int32_t *colidx,
             const double *values, Analysis &out, std::string *msg);
 
-// Exposed for tests of the ordering alone.
+// Exposed for tests of the orderings alone.
+void vector_order(int64_t n, const int64_t *rowptr, const int32_t *colidx, std::vector<int32_t> &perm);
 int nested_dissection(int64_t n, const int64_t *rowptr, const int32_t *colidx, int64_t leaf,
                       std::vector<int32_t> &q);
 

@@ -199,23 +199,26 @@ __global__ void k_prep_refactor(Control *c) {
     c->counter = 0;
 }
 
-// kval == nullptr: the values are already in the workspace (re-ingest for a fallback).
-// Also arms the finished-value array of the refactorization with sentinels.
-__global__ void k_ingest(int64_t nnz, const double *vals, double *kval, int64_t f,
-                         const int64_t *__restrict__ fsrc, double *__restrict__ F64,
-                         float *__restrict__ F32, double *__restrict__ Ld64, float *__restrict__ Ld32,
-                         int mixed, Control *c) {
+// New values: K's values (original CSR order, vals) into the Krylov side's copy in the vector
+// order (entry e of the copy is vals[ksrc[e]]; each row a contiguous run of vals).
+__global__ void k_ingest_k(int64_t nnz, const double *__restrict__ vals, const int64_t *__restrict__ ksrc,
+                           double *__restrict__ kval) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) kval[e] = vals[ksrc[e]];
+}
+
+// Factor storage from the copy (fill = 0) and the finiteness of every value of K (each is the
+// source of exactly one factor entry); arms the finished-value array of the refactorization
+// with sentinels.
+__global__ void k_ingest(int64_t f, const double *__restrict__ kval, const int64_t *__restrict__ fsrc,
+                         double *__restrict__ F64, float *__restrict__ F32, double *__restrict__ Ld64,
+                         float *__restrict__ Ld32, int mixed, Control *c) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     bool bad = false;
-    if (kval)
-        for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += stride) {
-            const double v = vals[p];
-            kval[p] = v;
-            bad |= !isfinite(v);
-        }
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < f; t += stride) {
         const int64_t s = fsrc[t];
-        const double v = s >= 0 ? vals[s] : 0.0;
+        const double v = s >= 0 ? kval[s] : 0.0;
+        bad |= !isfinite(v);
         if (mixed) {
             F32[t] = (float)v;
             Ld32[t] = sentinel<float>();
@@ -225,6 +228,19 @@ __global__ void k_ingest(int64_t nnz, const double *vals, double *kval, int64_t 
         }
     }
     if (bad) atomicOr(&c->nonfinite, 1u);
+}
+
+// Vectors between the caller's (original) order and the vector order of a solve:
+// out[k] = in[perm[k]] (gather) and out[perm[k]] = in[k] (scatter).
+__global__ void k_vgather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ in,
+                          double *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) out[k] = in[perm[k]];
+}
+__global__ void k_vscatter(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ in,
+                           double *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) out[perm[k]] = in[k];
 }
 
 // CSR row loops issue a row's loads kRowBatch at a time (index and value loads together, then
@@ -1652,6 +1668,10 @@ struct DevLayout {
     int64_t *krp;
     int32_t *lci, *uci, *kci;
     int32_t *prow, *q;
+    // the vector order of a solve: its permutation, the copy of K's entry sources, and the
+    // pivot permutations composed with it
+    int32_t *vperm, *prow_k, *q_k;
+    int64_t *ksrc;
     // triangular-solve schedules (L, U): rows, level starts, lanes, tiles, references
     int32_t *l_rows, *l_seg, *l_tseg, *l_ref, *l_text, *l_esrc;
     int32_t *u_rows, *u_seg, *u_tseg, *u_ref, *u_text, *u_esrc;
@@ -1665,7 +1685,7 @@ struct DevLayout {
     double *Ld64;
     float *Ld32;
     // vectors
-    double *V, *Z, *w, *r, *y64, *z64, *dv, *rr, *xb;
+    double *V, *Z, *w, *r, *y64, *z64, *dv, *rr, *xb, *bi, *xi;
     float *y32, *z32;
     double *part;
     Control *ctl;
@@ -1797,8 +1817,8 @@ struct Planner {
 struct Offsets {
     size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, relsrc, relslot, item, item_lane, krp, kci, l_rows, l_seg, l_tseg,
         l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, l_tden, l_sdof, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
-        u_rent, u_tlds, u_tden, u_sdof, prow, q, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
-        z32, dv, rr, xb, part, ctl, total;
+        u_rent, u_tlds, u_tden, u_sdof, prow, q, vperm, prow_k, q_k, ksrc, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
+        z32, dv, rr, xb, bi, xi, part, ctl, total;
 };
 
 Offsets plan(const kkt_handle_t h) {
@@ -1846,6 +1866,10 @@ Offsets plan(const kkt_handle_t h) {
     o.u_slg = p.take<int32_t>(a.usched.seg_lg.size());
     o.prow = p.take<int32_t>(n);
     o.q = p.take<int32_t>(n);
+    o.vperm = p.take<int32_t>(n);
+    o.prow_k = p.take<int32_t>(n);
+    o.q_k = p.take<int32_t>(n);
+    o.ksrc = p.take<int64_t>(a.nnz);
     o.kval = p.take<double>(a.nnz);
     o.F64 = p.take<double>(f);
     o.T64 = p.take<double>(a.t_size);
@@ -1864,6 +1888,8 @@ Offsets plan(const kkt_handle_t h) {
     o.dv = p.take<double>(n);
     o.rr = p.take<double>(n);
     o.xb = p.take<double>(n);
+    o.bi = p.take<double>(n);
+    o.xi = p.take<double>(n);
     o.part = p.take<double>((size_t)3 * kStreamGridMax * kPartStride);
     o.ctl = p.take<Control>(1);
     o.total = p.off;
@@ -1906,8 +1932,10 @@ int stream_blocks(int64_t n) {
 }
 
 template <typename T>
+// vorder: the right-hand side and the solution are in the vector order of a solve (else in
+// the caller's original order)
 hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T *rhs_step, T *out, double *xout,
-                       const Control *stopflag, hipStream_t s, unsigned int *work = nullptr,
+                       const Control *stopflag, hipStream_t s, bool vorder, unsigned int *work = nullptr,
                        unsigned int *hang = nullptr) {
     const Analysis &a = h->an;
     TrsvArgs<T> t{};
@@ -1930,13 +1958,13 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     if (lower) {
         t.val = base;
         t.rhs64 = rhs64;
-        t.prow = d.prow;
+        t.prow = vorder ? d.prow_k : d.prow;
     } else {
         t.val = base + a.lsched.values();
         t.diag = base + a.lsched.values() + a.usched.values();
         t.rhs_step = rhs_step;
         t.xout = xout;
-        t.q = d.q;
+        t.q = vorder ? d.q_k : d.q;
     }
     t.out = out;
     t.stopflag = stopflag;
@@ -1952,17 +1980,18 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     return hipGetLastError();
 }
 
-// x = Q U^-1 L^-1 P b with the current factors of precision T (sentinels armed before).
+// x = Q U^-1 L^-1 P b with the current factors of precision T (sentinels armed before); b and
+// x in the vector order of a solve (vorder) or in the original order.
 template <typename T>
-hipError_t precond(kkt_handle_t h, const double *b, double *x, const Control *ctl, hipStream_t s) {
+hipError_t precond(kkt_handle_t h, const double *b, double *x, const Control *ctl, hipStream_t s, bool vorder) {
     T *y = (T *)(sizeof(T) == 8 ? (void *)h->d.y64 : (void *)h->d.y32);
     T *z = (T *)(sizeof(T) == 8 ? (void *)h->d.z64 : (void *)h->d.z32);
     hipEvent_t e0 = prof_begin(h, KKT_K_TRSV_L, s);
-    hipError_t e = launch_trsv<T>(h, true, b, nullptr, y, nullptr, ctl, s);
+    hipError_t e = launch_trsv<T>(h, true, b, nullptr, y, nullptr, ctl, s, vorder);
     prof_end(h, KKT_K_TRSV_L, e0, s);
     if (e != hipSuccess) return e;
     e0 = prof_begin(h, KKT_K_TRSV_U, s);
-    e = launch_trsv<T>(h, false, nullptr, y, z, x, ctl, s);
+    e = launch_trsv<T>(h, false, nullptr, y, z, x, ctl, s, vorder);
     prof_end(h, KKT_K_TRSV_U, e0, s);
     return e;
 }
@@ -1995,12 +2024,8 @@ kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *va
     for (int b = 0; b < count; ++b) {
         DevLayout &d = hs[b]->d;
         k_prep_refactor<<<1, 1, 0, s>>>(d.ctl);
-        if (vals[b])
-            k_ingest<<<2048, 256, 0, s>>>(a.nnz, vals[b], d.kval, f, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32,
-                                          precision, d.ctl);
-        else
-            k_ingest<<<2048, 256, 0, s>>>(a.nnz, d.kval, nullptr, f, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32,
-                                          precision, d.ctl);
+        if (vals[b]) k_ingest_k<<<2048, 256, 0, s>>>(a.nnz, vals[b], d.ksrc, d.kval);
+        k_ingest<<<2048, 256, 0, s>>>(f, d.kval, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32, precision, d.ctl);
         k_rownorm<<<rows_grid, 256, 0, s>>>(a.n, d.krp, d.kval, d.ctl);
     }
     prof_end(h, KKT_K_INGEST, e0, s);
@@ -2078,7 +2103,7 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
     prof_end(h, KKT_K_OTHER, e0, s);
     rearm<T>(h, s);
-    KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
+    KKT_HIP(h, precond<T>(h, b, x, nullptr, s, true));
     e0 = prof_begin(h, KKT_K_RESID, s);
     launch_resid(h, ka, b, x, d.r, s);
     k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G, h->dev_ctl_sum);
@@ -2140,7 +2165,7 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
         const int steps = dcgs2 ? R + 1 : R;
         for (int j = 0; j < steps; ++j) {
             const size_t step_mark = h->ev_pending.size();
-            if (j < R) KKT_HIP(h, precond<T>(h, d.V + (int64_t)j * a.n, d.Z + (int64_t)j * a.n, d.ctl, s));
+            if (j < R) KKT_HIP(h, precond<T>(h, d.V + (int64_t)j * a.n, d.Z + (int64_t)j * a.n, d.ctl, s, true));
             e0 = prof_begin(h, KKT_K_SPMV, s);
             if (dcgs2) k_dcgs2_dots<<<G, kStreamBlock, 0, s>>>(ka, j, j < R ? 1 : 0);
             else k_spmv_dots<<<G, kStreamBlock, 0, s>>>(ka, j);
@@ -2254,7 +2279,7 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
     k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
     prof_end(h, KKT_K_OTHER, e0, s);
     rearm<T>(h, s);
-    KKT_HIP(h, precond<T>(h, b, x, nullptr, s));
+    KKT_HIP(h, precond<T>(h, b, x, nullptr, s, true));
     auto residual = [&]() -> kkt_status_t {
         hipEvent_t r0 = prof_begin(h, KKT_K_RESID, s);
         launch_resid(h, ka, b, x, d.r, s);
@@ -2305,7 +2330,7 @@ kkt_status_t richardson_impl(kkt_handle_t h, const double *b, double *x, double 
             inf.iterations += in.iterations;
         } else {
             rearm<T>(h, s);
-            KKT_HIP(h, precond<T>(h, d.r, d.dv, nullptr, s));
+            KKT_HIP(h, precond<T>(h, d.r, d.dv, nullptr, s, true));
             inf.precond_applications += 1;
         }
         hipEvent_t x0 = prof_begin(h, KKT_K_OTHER, s);
@@ -2413,9 +2438,11 @@ AnalysisOptions analysis_options(const kkt_opts_t &o, int64_t n) {
 // system's pivoted factorization; this repeats it for the current one).
 kkt_status_t repivot_impl(kkt_handle_t h, hipStream_t s) {
     const Analysis &old = h->an;
-    std::vector<double> vals(old.nnz);
-    KKT_HIP(h, hipMemcpyAsync(vals.data(), h->d.kval, old.nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+    // the workspace's copy of K is in the vector order: back to the original CSR order
+    std::vector<double> kv(old.nnz), vals(old.nnz);
+    KKT_HIP(h, hipMemcpyAsync(kv.data(), h->d.kval, old.nnz * sizeof(double), hipMemcpyDeviceToHost, s));
     KKT_HIP(h, hipStreamSynchronize(s));
+    for (int64_t e = 0; e < old.nnz; ++e) vals[old.ksrc[e]] = kv[e];
     AnalysisOptions ao = analysis_options(h->opts, old.n);
     const std::vector<int32_t> q = old.q;
     ao.fixed_order = q.data();
@@ -2437,7 +2464,9 @@ kkt_status_t repivot_impl(kkt_handle_t h, hipStream_t s) {
     }
     kkt_status_t st = kkt_bind_workspace(h, h->ws, h->ws_bytes, s);
     if (st != KKT_OK) return st;
-    KKT_HIP(h, hipMemcpyAsync(h->d.kval, vals.data(), h->an.nnz * sizeof(double), hipMemcpyHostToDevice, s));
+    for (int64_t e = 0; e < h->an.nnz; ++e) kv[e] = vals[h->an.ksrc[e]];
+    KKT_HIP(h, hipMemcpyAsync(h->d.kval, kv.data(), h->an.nnz * sizeof(double), hipMemcpyHostToDevice, s));
+    KKT_HIP(h, hipStreamSynchronize(s));
     // mixed precision: the FP32 factors of the old layout are meaningless now, so the FP32
     // refactorization runs in the new layout as well (kkt_direct_solve and the factor getters
     // read them); the FP64 factors, refactored last, serve this system's remaining solves
@@ -2529,13 +2558,16 @@ hipError_t direct_solve_scratch(kkt_handle_t h, const double *b, double *x, unsi
                                                                 &head->hang);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_trsv<T>(h, true, b, nullptr, y, nullptr, nullptr, s, &head->work_lower, &head->hang);
+    e = launch_trsv<T>(h, true, b, nullptr, y, nullptr, nullptr, s, false, &head->work_lower, &head->hang);
     if (e != hipSuccess) return e;
-    return launch_trsv<T>(h, false, nullptr, y, z, x, nullptr, s, &head->work_upper, &head->hang);
+    return launch_trsv<T>(h, false, nullptr, y, z, x, nullptr, s, false, &head->work_upper, &head->hang);
 }
 
 }  // namespace
 }  // namespace kkt
+
+static kkt_status_t solve_vorder(kkt_handle_t h, const double *dev_b, double tol, kkt_solve_info_t *info,
+                                 hipStream_t s);
 
 extern "C" {
 
@@ -2722,6 +2754,10 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.u_slg = (int32_t *)(b + o.u_slg);
     d.prow = (int32_t *)(b + o.prow);
     d.q = (int32_t *)(b + o.q);
+    d.vperm = (int32_t *)(b + o.vperm);
+    d.prow_k = (int32_t *)(b + o.prow_k);
+    d.q_k = (int32_t *)(b + o.q_k);
+    d.ksrc = (int64_t *)(b + o.ksrc);
     d.kval = (double *)(b + o.kval);
     d.F64 = (double *)(b + o.F64);
     d.T64 = (double *)(b + o.T64);
@@ -2740,6 +2776,8 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.dv = (double *)(b + o.dv);
     d.rr = (double *)(b + o.rr);
     d.xb = (double *)(b + o.xb);
+    d.bi = (double *)(b + o.bi);
+    d.xi = (double *)(b + o.xi);
     d.part = (double *)(b + o.part);
     d.ctl = (Control *)(b + o.ctl);
     KKT_HIP(h, up(b, o.fp, a.fp, s));
@@ -2749,14 +2787,18 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.clev, a.col_level, s));
     KKT_HIP(h, up(b, o.f2t, a.f2t, s));
     KKT_HIP(h, up(b, o.relptr, a.relptr, s));
-    KKT_HIP(h, up(b, o.fsrc, a.fsrc, s));
+    KKT_HIP(h, up(b, o.fsrc, a.fsrc_k, s));
     KKT_HIP(h, up(b, o.relpos, a.relpos, s));
     KKT_HIP(h, up(b, o.relsrc, a.relsrc, s));
     KKT_HIP(h, up(b, o.relslot, a.relslot, s));
     KKT_HIP(h, up(b, o.item, a.ref_item, s));
     KKT_HIP(h, up(b, o.item_lane, a.ref_item_lane, s));
-    KKT_HIP(h, up(b, o.krp, a.rowptr, s));
-    KKT_HIP(h, up(b, o.kci, a.colidx, s));
+    KKT_HIP(h, up(b, o.krp, a.krp, s));
+    KKT_HIP(h, up(b, o.kci, a.kci, s));
+    KKT_HIP(h, up(b, o.ksrc, a.ksrc, s));
+    KKT_HIP(h, up(b, o.vperm, a.vperm, s));
+    KKT_HIP(h, up(b, o.prow_k, a.prow_k, s));
+    KKT_HIP(h, up(b, o.q_k, a.q_k, s));
     KKT_HIP(h, up(b, o.l_rows, a.lsched.rows, s));
     KKT_HIP(h, up(b, o.l_seg, a.lsched.seg_row, s));
     KKT_HIP(h, up(b, o.l_tseg, a.lsched.tile_seg, s));
@@ -2832,10 +2874,11 @@ kkt_status_t kkt_refactor_batch_graph(const kkt_handle_t *hs, const double *cons
     kkt_status_t st = check_batch(hs, dev_values, count);
     if (st != KKT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    // the values go into each workspace first; the graph re-ingests them from there
-    for (int b = 0; b < count; ++b)
-        KKT_HIP(hs[b], hipMemcpyAsync(hs[b]->d.kval, dev_values[b], hs[b]->an.nnz * sizeof(double),
-                                      hipMemcpyDeviceToDevice, s));
+    // the values go into each workspace's copy of K first; the graph ingests them from there
+    for (int b = 0; b < count; ++b) {
+        k_ingest_k<<<2048, 256, 0, s>>>(hs[b]->an.nnz, dev_values[b], hs[b]->d.ksrc, hs[b]->d.kval);
+        KKT_HIP(hs[b], hipGetLastError());
+    }
     const int precision = hs[0]->opts.precision;
     std::vector<uint64_t> gens(count);
     for (int b = 0; b < count; ++b) gens[b] = hs[b]->bind_gen;
@@ -2910,11 +2953,34 @@ kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, doubl
     if (!h->bound || !h->have_factors) return fail(h, KKT_ESTATE, "refactor before solve");
     if (tol <= 0.0) tol = h->opts.delta_tol;
     hipStream_t s = (hipStream_t)stream;
+    // the solve runs in the vector order: b in, then x out (the best iterate also when the
+    // refinement misses the tolerance)
+    const kkt_status_t st = solve_vorder(h, dev_b, tol, info, s);
+    if (st == KKT_OK || st == KKT_ENOCONV) {
+        k_vscatter<<<h->grid_stream, kStreamBlock, 0, s>>>(h->an.n, h->d.vperm, h->d.xi, dev_x);
+        KKT_HIP(h, hipGetLastError());
+    }
+    return st;
+}
+
+}  // extern "C"
+
+// kkt_solve in the vector order of the handle's analysis: b (the caller's, original order)
+// is gathered into the workspace's b, the solution is left in its x.  A re-pivot re-lays out
+// the workspace, so both are taken from the layout after it (and b gathered again).
+static kkt_status_t solve_vorder(kkt_handle_t h, const double *dev_b, double tol, kkt_solve_info_t *info,
+                                 hipStream_t s) {
+    auto gather_b = [&]() -> kkt_status_t {
+        k_vgather<<<h->grid_stream, kStreamBlock, 0, s>>>(h->an.n, h->d.vperm, dev_b, h->d.bi);
+        KKT_HIP(h, hipGetLastError());
+        return KKT_OK;
+    };
+    if (gather_b() != KKT_OK) return KKT_EDEVICE;
     const int cycles = h->opts.max_restarts + 1;
     if (h->factor_precision == KKT_PREC_MIXED && !h->fp64_current) {
         const int mixed_cycles = h->opts.mixed_fallback ? std::min(cycles, std::max(1, h->opts.mixed_max_cycles))
                                                         : cycles;
-        kkt_status_t st = solve_impl<float>(h, dev_b, dev_x, tol, info, s, mixed_cycles);
+        kkt_status_t st = solve_impl<float>(h, h->d.bi, h->d.xi, tol, info, s, mixed_cycles);
         if (st != KKT_ENOCONV || !h->opts.mixed_fallback) return st;
         // FP64 fallback: refactor the values already in the workspace in FP64 (the FP32
         // factors stay valid); later solves of this system go straight to FP64
@@ -2925,20 +2991,24 @@ kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, doubl
     }
     kkt_status_t st;
     if (h->opts.ir_method == KKT_IR_RICHARDSON || h->opts.ir_method == KKT_IR_ERROR_FGMRES) {
-        st = richardson_impl<double>(h, dev_b, dev_x, tol, info, s, h->opts.ir_method == KKT_IR_ERROR_FGMRES);
+        st = richardson_impl<double>(h, h->d.bi, h->d.xi, tol, info, s, h->opts.ir_method == KKT_IR_ERROR_FGMRES);
     } else {
         const bool rp = h->opts.repivot_cycles > 0;
-        st = solve_impl<double>(h, dev_b, dev_x, tol, info, s, rp ? std::min(cycles, h->opts.repivot_cycles) : cycles);
+        st = solve_impl<double>(h, h->d.bi, h->d.xi, tol, info, s,
+                                rp ? std::min(cycles, h->opts.repivot_cycles) : cycles);
         if (st == KKT_ENOCONV && rp) {
             st = repivot_impl(h, s);
             if (st != KKT_OK) return st;
-            st = solve_impl<double>(h, dev_b, dev_x, tol, info, s, cycles);
+            if (gather_b() != KKT_OK) return KKT_EDEVICE;
+            st = solve_impl<double>(h, h->d.bi, h->d.xi, tol, info, s, cycles);
             if (info) info->repivoted = 1;
         }
     }
     if (info && h->fp64_current) info->fallback = 1;
     return st;
 }
+
+extern "C" {
 
 kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x, void *stream) {
     if (!h || !dev_b || !dev_x) return fail(h, KKT_EINVAL, "null argument");
@@ -2947,10 +3017,10 @@ kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x
     hipStream_t s = (hipStream_t)stream;
     if (h->factor_precision == KKT_PREC_MIXED) {
         rearm<float>(h, s);
-        KKT_HIP(h, precond<float>(h, dev_b, dev_x, nullptr, s));
+        KKT_HIP(h, precond<float>(h, dev_b, dev_x, nullptr, s, false));
     } else {
         rearm<double>(h, s);
-        KKT_HIP(h, precond<double>(h, dev_b, dev_x, nullptr, s));
+        KKT_HIP(h, precond<double>(h, dev_b, dev_x, nullptr, s, false));
     }
     return KKT_OK;
 }
@@ -2982,7 +3052,11 @@ kkt_status_t kkt_residual(kkt_handle_t h, const double *dev_b, const double *dev
     if (dev_r == dev_b || dev_r == dev_x) return fail(h, KKT_EINVAL, "dev_r must be distinct from dev_b and dev_x");
     hipStream_t s = (hipStream_t)stream;
     const KrylovArgs ka = kargs<double>(h);
-    launch_resid(h, ka, dev_b, dev_x, dev_r, s);
+    const int G = h->grid_stream;
+    k_vgather<<<G, kStreamBlock, 0, s>>>(h->an.n, h->d.vperm, dev_b, h->d.bi);
+    k_vgather<<<G, kStreamBlock, 0, s>>>(h->an.n, h->d.vperm, dev_x, h->d.xi);
+    launch_resid(h, ka, h->d.bi, h->d.xi, h->d.r, s);
+    k_vscatter<<<G, kStreamBlock, 0, s>>>(h->an.n, h->d.vperm, h->d.r, dev_r);
     KKT_HIP(h, hipGetLastError());
     return KKT_OK;
 }
