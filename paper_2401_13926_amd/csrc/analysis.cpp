@@ -984,7 +984,7 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
                     }
                     if (flat) {
                         a.relsrc[r] = (int32_t)s;
-                        a.relslot[r] = (uint16_t)std::min<int64_t>(t - a.fp[j], 65535);
+                        a.relslot[r] = (int32_t)(t - a.fp[j]);
                     }
                     a.relpos[r++] = pos;
                 }
@@ -994,12 +994,18 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
         }
         a.relptr[n] = r;
         // columns by (level, lane-sized first, index)
+        // (lane-sized columns of a level by ascending update count, so that the 64 lanes of an
+        // item have about the same work; columns of one level are independent, so their order
+        // is free)
         auto lane_sized = [&](int32_t j) { return flat && a.fp[j + 1] - a.fp[j] <= kLaneLen; };
         a.col_order.resize(n);
         for (int64_t j = 0; j < n; ++j) a.col_order[j] = (int32_t)j;
         std::stable_sort(a.col_order.begin(), a.col_order.end(), [&](int32_t x, int32_t y) {
             if (level[x] != level[y]) return level[x] < level[y];
-            return lane_sized(x) && !lane_sized(y);
+            const bool lx = lane_sized(x), ly = lane_sized(y);
+            if (lx != ly) return lx;
+            if (lx) return a.relptr[x + 1] - a.relptr[x] < a.relptr[y + 1] - a.relptr[y];
+            return false;
         });
         a.col_level.resize(n);
         for (int64_t t = 0; t < n; ++t) a.col_level[t] = (int32_t)level[a.col_order[t]];
@@ -1132,6 +1138,50 @@ void build_vector_order(Analysis &a) {
     }
 }
 
+// The device layout of the flat refactorization (see Analysis::phys): F positions and update
+// lists renumbered in col_order.
+void build_phys_layout(Analysis &a) {
+    const int64_t n = a.n, f = a.nnz_f();
+    std::vector<int64_t> phys(f);
+    a.pc.assign(n + 1, 0);
+    a.pu.assign(n + 1, 0);
+    a.pnu.assign(n, 0);
+    int64_t w = 0, u = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        const int32_t j = a.col_order[p];
+        a.pc[p] = w;
+        a.pu[p] = u;
+        a.pnu[p] = a.fdiag[j];
+        for (int64_t t = a.fp[j]; t < a.fp[j + 1]; ++t) phys[t] = w++;
+        u += a.relptr[j + 1] - a.relptr[j];
+    }
+    a.pc[n] = w;
+    a.pu[n] = u;
+    std::vector<int32_t> rpos(a.relpos.size()), rsrc(a.relsrc.size()), rslot(a.relslot.size());
+    for (int64_t p = 0; p < n; ++p) {
+        const int32_t j = a.col_order[p];
+        for (int64_t k = a.relptr[j], d = a.pu[p]; k < a.relptr[j + 1]; ++k, ++d) {
+            rpos[d] = a.relpos[k];
+            rsrc[d] = (int32_t)phys[a.relsrc[k]];
+            rslot[d] = a.relslot[k];
+        }
+    }
+    a.relpos.swap(rpos);
+    a.relsrc.swap(rsrc);
+    a.relslot.swap(rslot);
+    std::vector<int32_t> f2t(f);
+    std::vector<int64_t> fsrc(f);
+    for (int64_t t = 0; t < f; ++t) {
+        f2t[phys[t]] = a.f2t[t];
+        fsrc[phys[t]] = a.fsrc_k[t];
+    }
+    a.f2t.swap(f2t);
+    a.fsrc_k.swap(fsrc);
+    for (auto &t : a.l2f) t = phys[t];
+    for (auto &t : a.u2f) t = phys[t];
+    a.phys = true;
+}
+
 }  // namespace
 
 void vector_order(int64_t n, const int64_t *rowptr, const int32_t *colidx, std::vector<int32_t> &perm) {
@@ -1177,6 +1227,7 @@ int analyze(const AnalysisOptions &opt, int64_t n, const int64_t *rowptr, const 
         rc = build_layouts(opt, a, msg);
         if (rc != AN_OK) return rc;
         build_vector_order(a);
+        if (!a.relsrc.empty()) build_phys_layout(a);
     } catch (const std::bad_alloc &) {
         *msg = "out of host memory";
         return AN_ENOMEM;

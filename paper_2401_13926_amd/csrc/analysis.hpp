@@ -117,13 +117,11 @@ struct Analysis {
     // entry of column k in order: offset (inside column j) of that row.
     std::vector<int64_t> relptr;  // n+1
     std::vector<int32_t> relpos;  // sum of updates
-    // The same updates as a flat list (the refactorization's lane and one-column-per-wave
-    // paths for columns staged in LDS): the F index of the L entry each update applies, and
-    // the position in column j of its source's U entry (65535 when that position does not fit
-    // 16 bits; such columns are longer than the LDS stage and never use the list).  Empty when
-    // the factor has 2^31 entries or more.
+    // The same updates as a flat list (the refactorization's paths when it exists): the F
+    // index of the L entry each update applies, and the position in column j of its source's
+    // U entry.  Empty when the factor has 2^31 entries or more.
     std::vector<int32_t> relsrc;
-    std::vector<uint16_t> relslot;
+    std::vector<int32_t> relslot;
 
     // Refactorization schedule: columns sorted by (DAG level, index).
     std::vector<int32_t> col_order;
@@ -166,6 +164,17 @@ struct Analysis {
     std::vector<int32_t> kci;
     std::vector<int64_t> ksrc, fsrc_k;
     std::vector<int32_t> prow_k, q_k;
+
+    // Device layout with the flat list (phys): F's columns are stored in col_order, so the
+    // columns of one hand-out item (the 64 of a lane item in particular) are side by side, and
+    // the update lists follow the same order.  pc[p] / pu[p] (n + 1 each, ascending) are the
+    // first F position / first update of the column at col_order position p, pnu[p] its
+    // diagonal offset.  relpos, relsrc and relslot are then in that order, and relsrc, f2t,
+    // fsrc_k, l2f and u2f hold these F positions.  Without the flat list F keeps the column
+    // order of fp.
+    bool phys = false;
+    std::vector<int64_t> pc, pu;
+    std::vector<int32_t> pnu;
 
     double seconds = 0.0;
 

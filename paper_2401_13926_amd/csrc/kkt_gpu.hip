@@ -319,7 +319,11 @@ template <typename T> struct RefactorArgs {
     const int32_t *clev;  // level of each order position
     const int32_t *f2t;
     const int32_t *relsrc;   // per update: F index of the L entry it applies
-    const uint16_t *relslot; // per update: position of its source's U entry in the column
+    const int32_t *relslot;  // per update: position of its source's U entry in the column
+    // flat list only (F and the update lists stored in col_order): first F position, first
+    // update (n + 1 each) and diagonal offset of the column at each col_order position
+    const int64_t *pc, *pu;
+    const int32_t *pnu;
     const int32_t *item;     // hand-out items: first col_order position of each (nitems + 1)
     const uint8_t *item_lane;  // 1: one column per lane
     int64_t nitems;
@@ -429,7 +433,7 @@ __device__ void refactor_chain(const RefactorArgs<T> &a, int64_t rp, int64_t c0,
 // metadata is in flight while a round is applied.
 static_assert(kRefactorLds <= 65535, "update-list slots of LDS-staged columns fit 16 bits");
 
-template <typename T>
+template <typename T, bool kLds>
 __device__ void refactor_flat(const RefactorArgs<T> &a, int64_t rp, int64_t re, T *x) {
     const int lane = threadIdx.x & 63;
     unsigned int *hang = &a.ctl->hang;
@@ -463,7 +467,8 @@ __device__ void refactor_flat(const RefactorArgs<T> &a, int64_t rp, int64_t re, 
                 const T prod = lv * u;
                 x[cpos] = x[cpos] - prod;
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (kLds) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
     }
@@ -571,12 +576,13 @@ __device__ void refactor_lanes(const RefactorArgs<T> &a, T *xs, int64_t cbeg, in
     int64_t c0 = 0, rp = 0, re = 0;
     int len = 0, nu = 0;
     if (act) {
-        const int j = a.order[cbeg + lane];
-        c0 = a.fp[j];
-        len = (int)(a.fp[j + 1] - c0);
-        nu = a.fdiag[j];
-        rp = a.relptr[j];
-        re = a.relptr[j + 1];
+        // the item's columns and update lists are side by side (col_order layout)
+        const int64_t p = cbeg + lane;
+        c0 = a.pc[p];
+        len = (int)(a.pc[p + 1] - c0);
+        nu = a.pnu[p];
+        rp = a.pu[p];
+        re = a.pu[p + 1];
     }
     T *x = xs + lane;
     T cm = 0;
@@ -715,7 +721,14 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
         // most 16 columns): one dependent round trip per grab instead of two per column
         int nu_l = 0, lev_l = -1;
         long long c0_l = 0, end_l = 0, rp_l = 0, rpe_l = 0;
-        if (lane < cend - cbeg) {
+        if (lane < cend - cbeg && kFlat) {
+            const int64_t p = cbeg + lane;
+            c0_l = a.pc[p];
+            end_l = a.pc[p + 1];
+            nu_l = a.pnu[p];
+            rp_l = a.pu[p];
+            rpe_l = a.pu[p + 1];
+        } else if (lane < cend - cbeg) {
             const int j_l = a.order[cbeg + lane];
             lev_l = a.clev[cbeg + lane];
             c0_l = a.fp[j_l];
@@ -757,7 +770,8 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
         cm = wave_max(cm);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        if (kFlat && in_lds) refactor_flat<T>(a, rpj, __shfl(rpe_l, src, 64), xs);
+        if (kFlat && in_lds) refactor_flat<T, true>(a, rpj, __shfl(rpe_l, src, 64), xs);
+        else if (kFlat) refactor_flat<T, false>(a, rpj, __shfl(rpe_l, src, 64), a.F + c0);
         else if (in_lds) refactor_chain<T, true>(a, rpj, c0, nu, xs);
         else refactor_chain<T, false>(a, rpj, c0, nu, a.F + c0);
         const T *x = in_lds ? xs : a.F + c0;
@@ -1662,8 +1676,8 @@ struct DevLayout {
     int64_t *fp;
     int32_t *fi, *fdiag, *order, *clev, *f2t;
     int64_t *relptr, *fsrc;
-    int32_t *relpos, *relsrc, *item;
-    uint16_t *relslot;
+    int32_t *relpos, *relsrc, *item, *relslot, *pnu;
+    int64_t *pc, *pu;
     uint8_t *item_lane;
     int64_t *krp;
     int32_t *lci, *uci, *kci;
@@ -1815,7 +1829,7 @@ struct Planner {
 
 // Offsets of every array inside the workspace (also gives the total size).
 struct Offsets {
-    size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, relsrc, relslot, item, item_lane, krp, kci, l_rows, l_seg, l_tseg,
+    size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, relsrc, relslot, pc, pu, pnu, item, item_lane, krp, kci, l_rows, l_seg, l_tseg,
         l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, l_tden, l_sdof, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
         u_rent, u_tlds, u_tden, u_sdof, prow, q, vperm, prow_k, q_k, ksrc, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
         z32, dv, rr, xb, bi, xi, part, ctl, total;
@@ -1837,7 +1851,10 @@ Offsets plan(const kkt_handle_t h) {
     o.fsrc = p.take<int64_t>(f);
     o.relpos = p.take<int32_t>(a.relpos.size());
     o.relsrc = p.take<int32_t>(a.relsrc.size());
-    o.relslot = p.take<uint16_t>(a.relslot.size());
+    o.relslot = p.take<int32_t>(a.relslot.size());
+    o.pc = p.take<int64_t>(a.pc.size());
+    o.pu = p.take<int64_t>(a.pu.size());
+    o.pnu = p.take<int32_t>(a.pnu.size());
     o.item = p.take<int32_t>(a.ref_item.size());
     o.item_lane = p.take<uint8_t>(a.ref_item_lane.size());
     o.krp = p.take<int64_t>(n + 1);
@@ -2036,7 +2053,8 @@ kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *va
     const int64_t nitems = (int64_t)a.ref_item.size() - 1;
     if (precision == KKT_PREC_MIXED) {
         RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.relsrc,
-                              d.relslot, d.item, d.item_lane, nitems, d.F32, d.T32, d.Ld32, h->opts.guard_policy,
+                              d.relslot, d.pc, d.pu, d.pnu, d.item, d.item_lane, nitems, d.F32, d.T32, d.Ld32,
+                              h->opts.guard_policy,
                               d.ctl};
         RefactorBatch<float> bt{};
         bt.nslots = count;
@@ -2045,7 +2063,8 @@ kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *va
         else k_refactor<float, false><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r, bt);
     } else {
         RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.relsrc,
-                               d.relslot, d.item, d.item_lane, nitems, d.F64, d.T64, d.Ld64, h->opts.guard_policy,
+                               d.relslot, d.pc, d.pu, d.pnu, d.item, d.item_lane, nitems, d.F64, d.T64, d.Ld64,
+                               h->opts.guard_policy,
                                d.ctl};
         RefactorBatch<double> bt{};
         bt.nslots = count;
@@ -2725,7 +2744,10 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.fsrc = (int64_t *)(b + o.fsrc);
     d.relpos = (int32_t *)(b + o.relpos);
     d.relsrc = (int32_t *)(b + o.relsrc);
-    d.relslot = (uint16_t *)(b + o.relslot);
+    d.relslot = (int32_t *)(b + o.relslot);
+    d.pc = (int64_t *)(b + o.pc);
+    d.pu = (int64_t *)(b + o.pu);
+    d.pnu = (int32_t *)(b + o.pnu);
     d.item = (int32_t *)(b + o.item);
     d.item_lane = (uint8_t *)(b + o.item_lane);
     d.krp = (int64_t *)(b + o.krp);
@@ -2791,6 +2813,9 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.relpos, a.relpos, s));
     KKT_HIP(h, up(b, o.relsrc, a.relsrc, s));
     KKT_HIP(h, up(b, o.relslot, a.relslot, s));
+    KKT_HIP(h, up(b, o.pc, a.pc, s));
+    KKT_HIP(h, up(b, o.pu, a.pu, s));
+    KKT_HIP(h, up(b, o.pnu, a.pnu, s));
     KKT_HIP(h, up(b, o.item, a.ref_item, s));
     KKT_HIP(h, up(b, o.item_lane, a.ref_item_lane, s));
     KKT_HIP(h, up(b, o.krp, a.krp, s));
@@ -2831,10 +2856,17 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, hipStreamSynchronize(s));
     // at least one block per hand-out queue
     const bool flat = !h->an.relsrc.empty();
-    h->grid_refactor64 = std::max(kWorkQueues, coop_grid(flat ? (const void *)k_refactor<double, true>
-                                                              : (const void *)k_refactor<double, false>, h->device));
-    h->grid_refactor32 = std::max(kWorkQueues, coop_grid(flat ? (const void *)k_refactor<float, true>
-                                                              : (const void *)k_refactor<float, false>, h->device));
+    // at most 3 blocks per compute unit: the flat variant fits 4, which measured slower (more
+    // waiting columns in flight, 2M refactorization 0.98 against 1.02 ms)
+    int cus = 0;
+    KKT_HIP(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    const int cap = 3 * std::max(cus, 1);
+    h->grid_refactor64 = std::max(kWorkQueues, std::min(cap, coop_grid(flat ? (const void *)k_refactor<double, true>
+                                                                            : (const void *)k_refactor<double, false>,
+                                                                       h->device)));
+    h->grid_refactor32 = std::max(kWorkQueues, std::min(cap, coop_grid(flat ? (const void *)k_refactor<float, true>
+                                                                            : (const void *)k_refactor<float, false>,
+                                                                       h->device)));
     h->grid_trsv64 = std::min(std::min(coop_grid((const void *)k_trsv<double, true, true>, h->device, h->tile_lds),
                                        coop_grid((const void *)k_trsv<double, false, true>, h->device, h->tile_lds)),
                               std::min(coop_grid((const void *)k_trsv<double, true, false>, h->device, h->tile_lds),
