@@ -996,7 +996,8 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
         // columns by (level, lane-sized first, index)
         // (lane-sized columns of a level by ascending update count, so that the 64 lanes of an
         // item have about the same work; columns of one level are independent, so their order
-        // is free)
+        // is free.  Ordering them by their position in the vector order, for locality, measured
+        // no faster at 2M unknowns and slower at 60k.)
         auto lane_sized = [&](int32_t j) { return flat && a.fp[j + 1] - a.fp[j] <= kLaneLen; };
         a.col_order.resize(n);
         for (int64_t j = 0; j < n; ++j) a.col_order[j] = (int32_t)j;
@@ -1110,9 +1111,6 @@ int build_layouts(const AnalysisOptions &opt, Analysis &a, std::string *msg) {
 // permutations composed with it.
 void build_vector_order(Analysis &a) {
     const int64_t n = a.n, nnz = a.nnz;
-    rcm_order(n, a.rowptr.data(), a.colidx.data(), a.vperm);
-    a.vpinv.assign(n, 0);
-    for (int64_t k = 0; k < n; ++k) a.vpinv[a.vperm[k]] = (int32_t)k;
     a.krp.assign(n + 1, 0);
     a.kci.resize(nnz);
     a.ksrc.resize(nnz);
@@ -1224,6 +1222,9 @@ int analyze(const AnalysisOptions &opt, int64_t n, const int64_t *rowptr, const 
         }
         rc = pivoted_lu(n, rowptr, colidx, values, opt.pivot_tau, a, msg);
         if (rc != AN_OK) return rc;
+        rcm_order(n, rowptr, colidx, a.vperm);
+        a.vpinv.assign(n, 0);
+        for (int64_t k = 0; k < n; ++k) a.vpinv[a.vperm[k]] = (int32_t)k;
         rc = build_layouts(opt, a, msg);
         if (rc != AN_OK) return rc;
         build_vector_order(a);

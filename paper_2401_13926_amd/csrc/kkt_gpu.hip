@@ -7,7 +7,8 @@
 // Section 2.2: NRBE (eq. (nbre)); Section 2.3: the refine decision.
 //
 // Kernels (all wave64):
-//   k_ingest / k_rownorm     new values -> factor storage (fill = 0), ||K||_inf, finiteness
+//   k_ingest_rows / k_arm    new values -> the solve's copy of K, ||K||_inf, finiteness;
+//                            sentinels (and, without the flat list, the factor storage)
 //   k_refactor<T>            eager left-looking numeric LU, one wavefront per column, columns
 //                            handed out in dependency-level order; a column starts its update
 //                            chain at once and waits per entry of each source column (every
@@ -84,7 +85,7 @@ template <typename T> __device__ __forceinline__ void store_ready(T *p, T v) {
 // after it lands (the refactorization's waits, which sit on its critical chain).
 // kInFlight = 1: one load at a time (the triangular solves' staging waits, which overlap
 // other tiles' loads: less polling traffic measured faster there).
-template <typename T, int kInFlight = 4>
+template <typename T, int kInFlight = 4, int kSleep = 1>
 __device__ __forceinline__ T load_ready(const T *p, unsigned int *hang) {
     static_assert(kInFlight == 4 || kInFlight == 1, "4 or 1 loads in flight");
     using U = typename Bits<T>::U;
@@ -102,7 +103,7 @@ __device__ __forceinline__ T load_ready(const T *p, unsigned int *hang) {
                 __hip_atomic_store(hang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return T(0);
             }
-            __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_s_sleep(kSleep);
         }
     }
     U b0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -189,45 +190,90 @@ __global__ void k_prep_solve(Control *c) {
     c->stop = 0;
 }
 
+// Before the values of a new system: the row-norm maximum and the finiteness flag.
+__global__ void k_prep_values(Control *c) {
+    c->knorm_bits = 0;
+    c->nonfinite = 0;
+}
+
+// Before a refactorization (of new values or of the ones already ingested).
 __global__ void k_prep_refactor(Control *c) {
     for (int q = 0; q < kWorkQueues; ++q) c->work_refactor[q * 64] = 0;
     c->hang = 0;
-    c->knorm_bits = 0;
-    c->nonfinite = 0;
     c->guard_fail = 0;
     c->nguard = 0;
     c->counter = 0;
 }
 
 // New values: K's values (original CSR order, vals) into the Krylov side's copy in the vector
-// order (entry e of the copy is vals[ksrc[e]]; each row a contiguous run of vals).
-__global__ void k_ingest_k(int64_t nnz, const double *__restrict__ vals, const int64_t *__restrict__ ksrc,
-                           double *__restrict__ kval) {
+// order, one thread per row of the copy (row k is an original row whose entries start at
+// ostart[k] and keep their order); also ||K||_inf (each row's absolute values summed in
+// order, one atomic maximum per block) and the finiteness of every value.
+__global__ void k_ingest_rows(int64_t n, const int64_t *__restrict__ ostart, const int64_t *__restrict__ krp,
+                              const double *__restrict__ vals, double *__restrict__ kval, Control *c) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) kval[e] = vals[ksrc[e]];
+    double m = 0.0;
+    bool bad = false;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const int64_t s = ostart[k], e0 = krp[k];
+        const int len = (int)(krp[k + 1] - e0);
+        double sum = 0.0;
+        for (int t0 = 0; t0 < len; t0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = t0 + t < len ? vals[s + t0 + t] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (t0 + t < len) {
+                    kval[e0 + t0 + t] = v[t];
+                    sum += fabs(v[t]);
+                    bad |= !isfinite(v[t]);
+                }
+        }
+        m = fmax(m, sum);
+    }
+    // one atomic per block: atomics on one address serialize
+    __shared__ double red[256 / 64];
+    __shared__ int redb[256 / 64];
+    m = wave_max(m);
+    const bool wbad = __any(bad);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = m;
+        redb[threadIdx.x >> 6] = wbad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool b = redb[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            m = fmax(m, red[w]);
+            b = b || redb[w];
+        }
+        if (m > 0.0) atomicMax(&c->knorm_bits, __double_as_longlong(m));
+        if (b) atomicOr(&c->nonfinite, 1u);
+    }
 }
 
-// Factor storage from the copy (fill = 0) and the finiteness of every value of K (each is the
-// source of exactly one factor entry); arms the finished-value array of the refactorization
-// with sentinels.
-__global__ void k_ingest(int64_t f, const double *__restrict__ kval, const int64_t *__restrict__ fsrc,
-                         double *__restrict__ F64, float *__restrict__ F32, double *__restrict__ Ld64,
-                         float *__restrict__ Ld32, int mixed, Control *c) {
+// Arms the finished-value array of the refactorization with sentinels; without the flat list
+// also the factor storage from the copy of K (fill = 0), which that refactorization updates in
+// place (with it, the columns are staged from K's values directly).
+__global__ void k_arm(int64_t f, const int64_t *__restrict__ fsrc, const double *__restrict__ kval,
+                      double *__restrict__ F64, float *__restrict__ F32, double *__restrict__ Ld64,
+                      float *__restrict__ Ld32, int mixed) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    bool bad = false;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < f; t += stride) {
-        const int64_t s = fsrc[t];
-        const double v = s >= 0 ? kval[s] : 0.0;
-        bad |= !isfinite(v);
+        double v = 0.0;
+        if (fsrc) {
+            const int64_t s = fsrc[t];
+            v = s >= 0 ? kval[s] : 0.0;
+        }
         if (mixed) {
-            F32[t] = (float)v;
+            if (fsrc) F32[t] = (float)v;
             Ld32[t] = sentinel<float>();
         } else {
-            F64[t] = v;
+            if (fsrc) F64[t] = v;
             Ld64[t] = sentinel<double>();
         }
     }
-    if (bad) atomicOr(&c->nonfinite, 1u);
 }
 
 // Vectors between the caller's (original) order and the vector order of a solve:
@@ -275,6 +321,8 @@ __device__ __forceinline__ double row_dot(const int64_t *__restrict__ rp, const 
     return s;
 }
 
+// ||K||_inf of the values already in the workspace's copy of K (after a re-pivot, which
+// uploads them from the host).
 __global__ void k_rownorm(int64_t n, const int64_t *__restrict__ rp, const double *__restrict__ kval,
                           Control *c) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -324,6 +372,8 @@ template <typename T> struct RefactorArgs {
     // update (n + 1 each) and diagonal offset of the column at each col_order position
     const int64_t *pc, *pu;
     const int32_t *pnu;
+    const int32_t *fsrc;   // flat list only: per F position, its value's entry in kval, or -1
+    const double *kval;    // flat list only: K's values (the column staging reads them)
     const int32_t *item;     // hand-out items: first col_order position of each (nitems + 1)
     const uint8_t *item_lane;  // 1: one column per lane
     int64_t nitems;
@@ -589,8 +639,11 @@ __device__ void refactor_lanes(const RefactorArgs<T> &a, T *xs, int64_t cbeg, in
 #pragma unroll
     for (int h = 0; h < kLaneLen; h += 8) {
         T v[8];
+        int sx[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = h + e < len ? a.F[c0 + h + e] : T(0);
+        for (int e = 0; e < 8; ++e) sx[e] = h + e < len ? a.fsrc[c0 + h + e] : -1;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = sx[e] >= 0 ? (T)a.kval[sx[e]] : T(0);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             x[(h + e) * 64] = v[e];
@@ -658,6 +711,7 @@ template <typename T> struct RefactorBatch {
     struct {
         T *F, *Tv, *Ld;
         Control *ctl;
+        const double *kval;
     } slot[kMaxBatch];
 };
 
@@ -710,6 +764,7 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
                     a.Tv = batch.slot[q].Tv;
                     a.Ld = batch.slot[q].Ld;
                     a.ctl = batch.slot[q].ctl;
+                    a.kval = batch.slot[q].kval;
                 }
         }
         const int64_t cbeg = a.item[it], cend = a.item[it + 1];
@@ -763,7 +818,15 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
         const bool in_lds = len <= kRefactorLds;
         T cm = 0;
         for (int e = lane; e < len; e += 64) {
-            const T v = a.F[c0 + e];
+            T v;
+            if (kFlat) {
+                // the column's values come straight from K (F is not initialized by the ingest)
+                const int sx = a.fsrc[c0 + e];
+                v = sx >= 0 ? (T)a.kval[sx] : T(0);
+                if (!in_lds) a.F[c0 + e] = v;
+            } else {
+                v = a.F[c0 + e];
+            }
             if (in_lds) xs[e] = v;
             cm = fmax(cm, fabs(v));
         }
@@ -1684,8 +1747,8 @@ struct DevLayout {
     int32_t *prow, *q;
     // the vector order of a solve: its permutation, the copy of K's entry sources, and the
     // pivot permutations composed with it
-    int32_t *vperm, *prow_k, *q_k;
-    int64_t *ksrc;
+    int32_t *vperm, *prow_k, *q_k, *fsrc32;
+    int64_t *ostart;
     // triangular-solve schedules (L, U): rows, level starts, lanes, tiles, references
     int32_t *l_rows, *l_seg, *l_tseg, *l_ref, *l_text, *l_esrc;
     int32_t *u_rows, *u_seg, *u_tseg, *u_ref, *u_text, *u_esrc;
@@ -1831,7 +1894,7 @@ struct Planner {
 struct Offsets {
     size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, relsrc, relslot, pc, pu, pnu, item, item_lane, krp, kci, l_rows, l_seg, l_tseg,
         l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, l_tden, l_sdof, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
-        u_rent, u_tlds, u_tden, u_sdof, prow, q, vperm, prow_k, q_k, ksrc, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
+        u_rent, u_tlds, u_tden, u_sdof, prow, q, vperm, prow_k, q_k, ostart, fsrc32, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
         z32, dv, rr, xb, bi, xi, part, ctl, total;
 };
 
@@ -1848,7 +1911,10 @@ Offsets plan(const kkt_handle_t h) {
     o.clev = p.take<int32_t>(n);
     o.f2t = p.take<int32_t>(f);
     o.relptr = p.take<int64_t>(n + 1);
-    o.fsrc = p.take<int64_t>(f);
+    // F positions' value sources: 32-bit for the flat refactorization (which reads them), 64-bit
+    // for the other one (whose ingest initializes F)
+    o.fsrc = p.take<int64_t>(a.phys ? 0 : f);
+    o.fsrc32 = p.take<int32_t>(a.phys ? f : 0);
     o.relpos = p.take<int32_t>(a.relpos.size());
     o.relsrc = p.take<int32_t>(a.relsrc.size());
     o.relslot = p.take<int32_t>(a.relslot.size());
@@ -1886,7 +1952,7 @@ Offsets plan(const kkt_handle_t h) {
     o.vperm = p.take<int32_t>(n);
     o.prow_k = p.take<int32_t>(n);
     o.q_k = p.take<int32_t>(n);
-    o.ksrc = p.take<int64_t>(a.nnz);
+    o.ostart = p.take<int64_t>(n);
     o.kval = p.take<double>(a.nnz);
     o.F64 = p.take<double>(f);
     o.T64 = p.take<double>(a.t_size);
@@ -1942,6 +2008,10 @@ template <typename T> KrylovArgs kargs(kkt_handle_t h) {
     k.ctl = h->d.ctl;
     return k;
 }
+
+// Blocks of 256 threads for the row-wise ingest: one row per thread up to 4,096 blocks (its
+// rows' loads are two dependent rounds, so more rows in flight hide their latency).
+int ingest_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
 
 int stream_blocks(int64_t n) {
     int64_t b = (n + kStreamBlock - 1) / kStreamBlock;
@@ -2040,10 +2110,12 @@ kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *va
     hipEvent_t e0 = prof_begin(h, KKT_K_INGEST, s);
     for (int b = 0; b < count; ++b) {
         DevLayout &d = hs[b]->d;
+        if (vals[b]) {
+            k_prep_values<<<1, 1, 0, s>>>(d.ctl);
+            k_ingest_rows<<<ingest_grid(a.n), 256, 0, s>>>(a.n, d.ostart, d.krp, vals[b], d.kval, d.ctl);
+        }
         k_prep_refactor<<<1, 1, 0, s>>>(d.ctl);
-        if (vals[b]) k_ingest_k<<<2048, 256, 0, s>>>(a.nnz, vals[b], d.ksrc, d.kval);
-        k_ingest<<<2048, 256, 0, s>>>(f, d.kval, d.fsrc, d.F64, d.F32, d.Ld64, d.Ld32, precision, d.ctl);
-        k_rownorm<<<rows_grid, 256, 0, s>>>(a.n, d.krp, d.kval, d.ctl);
+        k_arm<<<2048, 256, 0, s>>>(f, a.phys ? nullptr : d.fsrc, d.kval, d.F64, d.F32, d.Ld64, d.Ld32, precision);
     }
     prof_end(h, KKT_K_INGEST, e0, s);
     hipError_t e = hipGetLastError();
@@ -2053,22 +2125,26 @@ kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *va
     const int64_t nitems = (int64_t)a.ref_item.size() - 1;
     if (precision == KKT_PREC_MIXED) {
         RefactorArgs<float> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.relsrc,
-                              d.relslot, d.pc, d.pu, d.pnu, d.item, d.item_lane, nitems, d.F32, d.T32, d.Ld32,
+                              d.relslot, d.pc, d.pu, d.pnu, d.fsrc32, d.kval, d.item, d.item_lane, nitems, d.F32,
+                              d.T32, d.Ld32,
                               h->opts.guard_policy,
                               d.ctl};
         RefactorBatch<float> bt{};
         bt.nslots = count;
-        for (int b = 0; b < count; ++b) bt.slot[b] = {hs[b]->d.F32, hs[b]->d.T32, hs[b]->d.Ld32, hs[b]->d.ctl};
+        for (int b = 0; b < count; ++b)
+            bt.slot[b] = {hs[b]->d.F32, hs[b]->d.T32, hs[b]->d.Ld32, hs[b]->d.ctl, hs[b]->d.kval};
         if (!a.relsrc.empty()) k_refactor<float, true><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r, bt);
         else k_refactor<float, false><<<h->grid_refactor32, kCoopBlock, 0, s>>>(r, bt);
     } else {
         RefactorArgs<double> r{a.n, d.fp, d.fi, d.fdiag, d.relptr, d.relpos, d.order, d.clev, d.f2t, d.relsrc,
-                               d.relslot, d.pc, d.pu, d.pnu, d.item, d.item_lane, nitems, d.F64, d.T64, d.Ld64,
+                               d.relslot, d.pc, d.pu, d.pnu, d.fsrc32, d.kval, d.item, d.item_lane, nitems, d.F64,
+                               d.T64, d.Ld64,
                                h->opts.guard_policy,
                                d.ctl};
         RefactorBatch<double> bt{};
         bt.nslots = count;
-        for (int b = 0; b < count; ++b) bt.slot[b] = {hs[b]->d.F64, hs[b]->d.T64, hs[b]->d.Ld64, hs[b]->d.ctl};
+        for (int b = 0; b < count; ++b)
+            bt.slot[b] = {hs[b]->d.F64, hs[b]->d.T64, hs[b]->d.Ld64, hs[b]->d.ctl, hs[b]->d.kval};
         if (!a.relsrc.empty()) k_refactor<double, true><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r, bt);
         else k_refactor<double, false><<<h->grid_refactor64, kCoopBlock, 0, s>>>(r, bt);
     }
@@ -2486,6 +2562,10 @@ kkt_status_t repivot_impl(kkt_handle_t h, hipStream_t s) {
     for (int64_t e = 0; e < h->an.nnz; ++e) kv[e] = vals[h->an.ksrc[e]];
     KKT_HIP(h, hipMemcpyAsync(h->d.kval, kv.data(), h->an.nnz * sizeof(double), hipMemcpyHostToDevice, s));
     KKT_HIP(h, hipStreamSynchronize(s));
+    k_prep_values<<<1, 1, 0, s>>>(h->d.ctl);
+    k_rownorm<<<(int)std::max<int64_t>(1, std::min<int64_t>((h->an.n + 255) / 256, 1024)), 256, 0, s>>>(
+        h->an.n, h->d.krp, h->d.kval, h->d.ctl);
+    KKT_HIP(h, hipGetLastError());
     // mixed precision: the FP32 factors of the old layout are meaningless now, so the FP32
     // refactorization runs in the new layout as well (kkt_direct_solve and the factor getters
     // read them); the FP64 factors, refactored last, serve this system's remaining solves
@@ -2779,7 +2859,8 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.vperm = (int32_t *)(b + o.vperm);
     d.prow_k = (int32_t *)(b + o.prow_k);
     d.q_k = (int32_t *)(b + o.q_k);
-    d.ksrc = (int64_t *)(b + o.ksrc);
+    d.ostart = (int64_t *)(b + o.ostart);
+    d.fsrc32 = (int32_t *)(b + o.fsrc32);
     d.kval = (double *)(b + o.kval);
     d.F64 = (double *)(b + o.F64);
     d.T64 = (double *)(b + o.T64);
@@ -2809,7 +2890,13 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.clev, a.col_level, s));
     KKT_HIP(h, up(b, o.f2t, a.f2t, s));
     KKT_HIP(h, up(b, o.relptr, a.relptr, s));
-    KKT_HIP(h, up(b, o.fsrc, a.fsrc_k, s));
+    if (a.phys) {
+        const std::vector<int32_t> f32(a.fsrc_k.begin(), a.fsrc_k.end());
+        KKT_HIP(h, up(b, o.fsrc32, f32, s));
+        KKT_HIP(h, hipStreamSynchronize(s));  // f32 is a local
+    } else {
+        KKT_HIP(h, up(b, o.fsrc, a.fsrc_k, s));
+    }
     KKT_HIP(h, up(b, o.relpos, a.relpos, s));
     KKT_HIP(h, up(b, o.relsrc, a.relsrc, s));
     KKT_HIP(h, up(b, o.relslot, a.relslot, s));
@@ -2820,7 +2907,12 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.item_lane, a.ref_item_lane, s));
     KKT_HIP(h, up(b, o.krp, a.krp, s));
     KKT_HIP(h, up(b, o.kci, a.kci, s));
-    KKT_HIP(h, up(b, o.ksrc, a.ksrc, s));
+    {
+        std::vector<int64_t> ost(a.n);
+        for (int64_t k = 0; k < a.n; ++k) ost[k] = a.rowptr[a.vperm[k]];
+        KKT_HIP(h, up(b, o.ostart, ost, s));
+        KKT_HIP(h, hipStreamSynchronize(s));  // ost is a local
+    }
     KKT_HIP(h, up(b, o.vperm, a.vperm, s));
     KKT_HIP(h, up(b, o.prow_k, a.prow_k, s));
     KKT_HIP(h, up(b, o.q_k, a.q_k, s));
@@ -2906,9 +2998,13 @@ kkt_status_t kkt_refactor_batch_graph(const kkt_handle_t *hs, const double *cons
     kkt_status_t st = check_batch(hs, dev_values, count);
     if (st != KKT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    // the values go into each workspace's copy of K first; the graph ingests them from there
+    // the values go into each workspace's copy of K first (with ||K||_inf and their
+    // finiteness); the graph refactors from there
     for (int b = 0; b < count; ++b) {
-        k_ingest_k<<<2048, 256, 0, s>>>(hs[b]->an.nnz, dev_values[b], hs[b]->d.ksrc, hs[b]->d.kval);
+        const DevLayout &d = hs[b]->d;
+        k_prep_values<<<1, 1, 0, s>>>(d.ctl);
+        k_ingest_rows<<<ingest_grid(hs[b]->an.n), 256, 0, s>>>(hs[b]->an.n, d.ostart, d.krp, dev_values[b], d.kval,
+                                                             d.ctl);
         KKT_HIP(hs[b], hipGetLastError());
     }
     const int precision = hs[0]->opts.precision;
