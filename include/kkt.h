@@ -114,9 +114,11 @@ typedef struct {
                                instead of 4, the same Krylov basis, and one preconditioner
                                application more per cycle that converges before its restart */
     int32_t tile_lds_kib;   /* LDS budget of one staged triangular-solve tile in KiB, 16..150
-                               (0: 64).  Larger tiles hold more levels of the elimination tree,
+                               (0: 32).  Larger tiles hold more levels of the elimination tree,
                                so fewer cross-block hands-offs lie on a solve's critical path;
-                               above 80 KiB one solve block occupies a compute unit alone */
+                               smaller ones let more blocks share a compute unit (measured
+                               faster at 32 than at 64 on 60k and 2M unknowns); above 80 KiB
+                               one solve block occupies a compute unit alone */
     int32_t narrow_columns; /* refactorization levels with at most this many columns are handed
                                out one column per wavefront, wider ones up to 8 columns per
                                grab (0: automatic, n/64 clamped to 1024..16384; measured best

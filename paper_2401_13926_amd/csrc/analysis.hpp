@@ -23,7 +23,7 @@ struct AnalysisOptions {
     double pivot_tau = 1e-10;
     int tile_threads = 256;      // threads of a triangular-solve block
     int tile_rows = 2048;        // rows of a tile at most
-    int64_t tile_lds = 65536;    // LDS bytes of a staged tile at most (tile_lds_bytes)
+    int64_t tile_lds = 32768;    // LDS bytes of a staged tile at most (tile_lds_bytes)
     // LDS that tiles keep free for dense blocks (0: no dense segments), per triangle.  The top
     // of L's DAG is many levels of few long rows, where fusing pays; measured on the 60k
     // sequence, fusing in U (shorter rows, wider levels) cost more than it saved.

@@ -13,7 +13,7 @@ constexpr int kStreamGridMax = 1024;   // blocks of the streaming kernels (parti
 constexpr int kCoopBlock = 256;        // threads per block of the refactorization
 constexpr int kTileThreads = 256;      // threads per block of the triangular solves
 constexpr int kTileRows = 2048;        // rows of a multi-level solve tile (values in LDS)
-constexpr int kTileLds = 65536;        // default LDS bytes of a staged solve tile
+constexpr int kTileLds = 32768;        // default LDS bytes of a staged solve tile
 constexpr int kTileLdsMin = 16 * 1024;  // smallest and largest tile budgets (gfx950: 160 KiB of LDS
 constexpr int kTileLdsMax = 150 * 1024; // per compute unit, the rest for the kernel's own arrays)
 constexpr int kRefactorLds = 1024;     // factor entries staged in LDS per wavefront

@@ -868,29 +868,60 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
 
 template <typename T> struct TrsvArgs {
     int64_t ntiles;
-    const int32_t *tile_seg;  // first segment of each tile (ntiles + 1)
     const int32_t *seg_row;   // segment start in rows
     const int32_t *seg_lg;    // log2 lanes per row of each segment
     const int32_t *rows;      // solve order
     const int64_t *row_ent;   // first packed entry of each position of rows
     const int32_t *ent_ref;   // LDS slot (staged tile) or source row (unstaged tile)
-    const int32_t *tile_ext;  // first external of each tile
     const int32_t *ext_src;   // source row of each external
-    const uint8_t *tile_lds;  // 1: staged tile
-    const int64_t *tile_dense;  // first dense-block value of each tile (index into val)
     const int32_t *seg_dofs;  // dense segment: its block's offset in the tile's dense values
     const T *val;             // packed entry values, then dense blocks
     const T *diag;            // upper only: diagonal of U in step order
-    const double *rhs64;      // lower: right-hand side in original order (gathered by prow)
-    const int32_t *prow;      // lower: pivot rows
+    const int32_t *tdesc;     // per tile, kTileDesc ints: its segments, rows, entries, externals,
+                              // dense values and staged flag (one scalar load per tile)
+    const double *rhs64;      // lower: right-hand side (gathered by rsrc)
+    const int32_t *rsrc;      // lower: per position of rows, the right-hand-side entry it reads
     const T *rhs_step;        // upper: L-solve result (step order)
     T *out;                   // step-order result; sentinel on entry
-    double *xout;             // upper: solution scattered to original order by q
-    const int32_t *q;
+    double *xout;             // upper: solution, scattered by qpos
+    const int32_t *qpos;      // upper: per position of rows, the solution entry it writes
     const Control *stopflag;  // when non-null, skip if the FGMRES cycle has stopped
     unsigned int *work;       // tile counter (zeroed before the launch)
     unsigned int *hang;
 };
+
+// A lane's share of a row from LDS: acc + vals[e] * xs[refs[e]] for e = e0, e0 + g, ... < e1,
+// added in that order; four entries at a time, their references, values and operands loaded
+// together (two dependent LDS rounds per four entries).
+template <typename T>
+__device__ __forceinline__ T lane_row_sum(T acc, int e0, int e1, int g, const T *vals, const uint16_t *refs,
+                                          const T *xs) {
+    for (int e = e0; e < e1; e += 4 * g) {
+        int c[4];
+        T v[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int eu = e + u * g;
+            c[u] = eu < e1 ? refs[eu] : 0;
+            v[u] = eu < e1 ? vals[eu] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = e + u * g < e1 ? xs[c[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e + u * g < e1) {
+                const T prod = v[u] * x[u];
+                acc = acc + prod;
+            }
+    }
+    return acc;
+}
+
+// Per tile descriptor: s0, s1, rb, re, eb (lo, hi), ne, xb, nx, db (lo, hi), nd, staged.
+constexpr int kTileDesc = 16;
+// Staging loads per thread and pass (a pass covers 2,048 entries, 512 rows, 512 externals and
+// 1,024 dense values).
+constexpr int kStageEnt = 8, kStageRow = 2, kStageExt = 2, kStageDense = 4;
 
 // Triangular solve by tiles.  Tiles are handed out in order to running blocks; a tile's
 // references point to earlier tiles or to earlier segments of the same tile, so the earliest
@@ -961,16 +992,14 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
         const int t = __builtin_amdgcn_readfirstlane((int)tile_sh);
         __syncthreads();
         if ((int64_t)t >= a.ntiles) break;
-        const auto tile_seg = uniform_ro(a.tile_seg);
         const auto seg_row = uniform_ro(a.seg_row);
         const auto seg_lg = uniform_ro(a.seg_lg);
-        const auto row_ent = uniform_ro(a.row_ent);
-        const int s0 = tile_seg[t], s1 = tile_seg[t + 1];
-        const int rb = seg_row[s0], re = seg_row[s1];
+        const auto td = uniform_ro(a.tdesc) + (int64_t)kTileDesc * t;
+        const int s0 = td[0], s1 = td[1], rb = td[2], re = td[3];
         const int nr = re - rb;
-        const int64_t eb = row_ent[rb];
-        const int ne = (int)(row_ent[re] - eb);
-        if (!uniform_ro(a.tile_lds)[t]) {
+        const int64_t eb = (int64_t)(((uint64_t)(uint32_t)td[5] << 32) | (uint32_t)td[4]);
+        const int ne = td[6];
+        if (!td[12]) {
             // one row, one wavefront, entries and sources in global memory
             if (tid < 64) {
                 const int i = a.rows[rb];
@@ -985,19 +1014,18 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
                 for (int o = 1; o < 64; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
                 if (tid == 0) {
                     T res;
-                    if (kLower) res = (T)a.rhs64[a.prow[i]] - acc;
+                    if (kLower) res = (T)a.rhs64[a.rsrc[rb]] - acc;
                     else res = (a.rhs_step[i] - acc) / a.diag[i];
                     store_ready(a.out + i, res);
-                    if (!kLower) a.xout[a.q[i]] = (double)res;
+                    if (!kLower) a.xout[a.qpos[rb]] = (double)res;
                 }
             }
             __syncthreads();
             continue;
         }
-        const int xb = uniform_ro(a.tile_ext)[t];
-        const int nx = uniform_ro(a.tile_ext)[t + 1] - xb;
-        const int64_t db = uniform_ro(a.tile_dense)[t];
-        const int nd = (int)(uniform_ro(a.tile_dense)[t + 1] - db);
+        const int xb = td[7], nx = td[8];
+        const int64_t db = (int64_t)(((uint64_t)(uint32_t)td[10] << 32) | (uint32_t)td[9]);
+        const int nd = td[11];
         const auto seg_dofs = uniform_ro(a.seg_dofs);
         // LDS carve-up: 8-byte arrays first, then 4-byte, then 2-byte
         T *xs = reinterpret_cast<T *>(smem);       // nr + nx solution slots
@@ -1009,45 +1037,97 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
         int32_t *qid = rid + nr;                   // nr (upper)
         int32_t *roff = qid + nr;                  // nr + 1
         uint16_t *refs = reinterpret_cast<uint16_t *>(roff + nr + 1);  // ne
-        // four loads in flight per thread before the LDS writes
-        for (int k0 = tid; k0 < ne; k0 += 4 * kTileThreads) {
-            T v[4];
-            int c[4];
+        // Staging in passes: a pass issues every first-level load it covers (kStageEnt entries,
+        // kStageRow rows, kStageExt externals and kStageDense dense values per thread), then the
+        // dependent ones (right-hand sides, diagonals, externals' values), then writes LDS, so a
+        // tile of the usual size is staged in two rounds of memory latency.
+        for (int pe = 0, pr = 0, px = 0, pd = 0; pe < ne || pr < nr || px < nx || pd < nd;
+             pe += kStageEnt * kTileThreads, pr += kStageRow * kTileThreads, px += kStageExt * kTileThreads,
+             pd += kStageDense * kTileThreads) {
+            T v[kStageEnt], dv[kStageDense], rv[kStageRow], gv[kStageRow], xv[kStageExt];
+            int c[kStageEnt], ri[kStageRow], rs[kStageRow], xc[kStageExt];
+            int64_t ro[kStageRow];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = k0 + u * kTileThreads;
+            for (int u = 0; u < kStageEnt; ++u) {
+                const int k = pe + tid + u * kTileThreads;
                 v[u] = k < ne ? a.val[eb + k] : T(0);
                 c[u] = k < ne ? a.ent_ref[eb + k] : 0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = k0 + u * kTileThreads;
+            for (int u = 0; u < kStageDense; ++u) {
+                const int k = pd + tid + u * kTileThreads;
+                dv[u] = k < nd ? a.val[db + k] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kStageRow; ++u) {
+                const int r = pr + tid + u * kTileThreads;
+                ri[u] = r < nr ? a.rows[rb + r] : 0;
+                ro[u] = r < nr ? a.row_ent[rb + r] : eb;
+                rs[u] = r < nr ? (kLower ? a.rsrc[rb + r] : a.qpos[rb + r]) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageExt; ++u) {
+                const int k = px + tid + u * kTileThreads;
+                xc[u] = k < nx ? a.ext_src[xb + k] : 0;
+            }
+            // dependent loads
+#pragma unroll
+            for (int u = 0; u < kStageRow; ++u) {
+                const int r = pr + tid + u * kTileThreads;
+                rv[u] = T(0);
+                gv[u] = T(1);
+                if (r < nr) {
+                    if (kLower) {
+                        rv[u] = (T)a.rhs64[rs[u]];
+                    } else {
+                        rv[u] = a.rhs_step[ri[u]];
+                        gv[u] = a.diag[ri[u]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStageExt; ++u) {
+                const int k = px + tid + u * kTileThreads;
+                xv[u] = k < nx ? a.out[xc[u]] : T(0);
+            }
+            // LDS
+#pragma unroll
+            for (int u = 0; u < kStageEnt; ++u) {
+                const int k = pe + tid + u * kTileThreads;
                 if (k < ne) {
                     vals[k] = v[u];
                     refs[k] = (uint16_t)c[u];
                 }
             }
-        }
-        for (int k = tid; k < nd; k += kTileThreads) dvs[k] = a.val[db + k];
-        for (int r = tid; r < nr; r += kTileThreads) {
-            const int i = a.rows[rb + r];
-            rid[r] = i;
-            roff[r] = (int32_t)(a.row_ent[rb + r] - eb);
-            if (kLower) {
-                rhs[r] = (T)a.rhs64[a.prow[i]];
-            } else {
-                rhs[r] = a.rhs_step[i];
-                dg[r] = T(1) / a.diag[i];  // reciprocal: one multiply per row in the segments
-                qid[r] = a.q[i];
+#pragma unroll
+            for (int u = 0; u < kStageDense; ++u) {
+                const int k = pd + tid + u * kTileThreads;
+                if (k < nd) dvs[k] = dv[u];
+            }
+#pragma unroll
+            for (int u = 0; u < kStageRow; ++u) {
+                const int r = pr + tid + u * kTileThreads;
+                if (r < nr) {
+                    rid[r] = ri[u];
+                    roff[r] = (int32_t)(ro[u] - eb);
+                    rhs[r] = rv[u];
+                    if (!kLower) {
+                        dg[r] = T(1) / gv[u];  // reciprocal: one multiply per row in the segments
+                        qid[r] = rs[u];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStageExt; ++u) {
+                const int k = px + tid + u * kTileThreads;
+                if (k < nx) {
+                    T x = xv[u];
+                    if (is_sentinel(x)) x = load_ready<T, 1>(a.out + xc[u], a.hang);
+                    xs[nr + k] = x;
+                }
             }
         }
         if (tid == 0) roff[nr] = ne;
-        for (int k = tid; k < nx; k += kTileThreads) {
-            const int c = a.ext_src[xb + k];
-            T v = a.out[c];
-            if (is_sentinel(v)) v = load_ready<T, 1>(a.out + c, a.hang);
-            xs[nr + k] = v;
-        }
         __syncthreads();
         // A wavefront segment is solved by wavefront 0 alone: between two such segments no
         // block barrier is needed (a wavefront's LDS accesses complete in order).
@@ -1750,12 +1830,11 @@ struct DevLayout {
     int32_t *vperm, *prow_k, *q_k, *fsrc32;
     int64_t *ostart;
     // triangular-solve schedules (L, U): rows, level starts, lanes, tiles, references
-    int32_t *l_rows, *l_seg, *l_tseg, *l_ref, *l_text, *l_esrc;
-    int32_t *u_rows, *u_seg, *u_tseg, *u_ref, *u_text, *u_esrc;
-    int64_t *l_rent, *u_rent, *l_tden, *u_tden;
+    int32_t *l_rows, *l_seg, *l_tdesc, *l_ref, *l_esrc, *l_src, *l_src_k;
+    int32_t *u_rows, *u_seg, *u_tdesc, *u_ref, *u_esrc, *u_q, *u_q_k;
+    int64_t *l_rent, *u_rent;
     int32_t *l_sdof, *u_sdof;
     int32_t *l_slg, *u_slg;
-    uint8_t *l_tlds, *u_tlds;
     // values
     double *kval, *F64, *T64;
     float *F32, *T32;
@@ -1892,9 +1971,9 @@ struct Planner {
 
 // Offsets of every array inside the workspace (also gives the total size).
 struct Offsets {
-    size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, relsrc, relslot, pc, pu, pnu, item, item_lane, krp, kci, l_rows, l_seg, l_tseg,
-        l_ref, l_slg, l_text, l_esrc, l_rent, l_tlds, l_tden, l_sdof, u_rows, u_seg, u_tseg, u_ref, u_slg, u_text, u_esrc,
-        u_rent, u_tlds, u_tden, u_sdof, prow, q, vperm, prow_k, q_k, ostart, fsrc32, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
+    size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, relsrc, relslot, pc, pu, pnu, item, item_lane, krp, kci, l_rows, l_seg, l_tdesc,
+        l_ref, l_slg, l_esrc, l_rent, l_sdof, l_src, l_src_k, u_rows, u_seg, u_tdesc, u_ref, u_slg, u_esrc,
+        u_rent, u_sdof, u_q, u_q_k, prow, q, vperm, prow_k, q_k, ostart, fsrc32, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
         z32, dv, rr, xb, bi, xi, part, ctl, total;
 };
 
@@ -1927,24 +2006,22 @@ Offsets plan(const kkt_handle_t h) {
     o.kci = p.take<int32_t>(a.nnz);
     o.l_rows = p.take<int32_t>(n);
     o.l_seg = p.take<int32_t>(a.lsched.seg_row.size());
-    o.l_tseg = p.take<int32_t>(a.lsched.tile_seg.size());
+    o.l_tdesc = p.take<int32_t>(kTileDesc * a.lsched.tiles());
+    o.l_src = p.take<int32_t>(n);
+    o.l_src_k = p.take<int32_t>(n);
     o.l_ref = p.take<int32_t>(a.lsched.ent_ref.size());
-    o.l_text = p.take<int32_t>(a.lsched.tile_ext.size());
     o.l_esrc = p.take<int32_t>(a.lsched.ext_src.size());
     o.l_rent = p.take<int64_t>(a.lsched.row_ent.size());
-    o.l_tlds = p.take<uint8_t>(a.lsched.tile_lds.size());
-    o.l_tden = p.take<int64_t>(a.lsched.tile_dense.size());
     o.l_sdof = p.take<int32_t>(a.lsched.seg_dofs.size());
     o.l_slg = p.take<int32_t>(a.lsched.seg_lg.size());
     o.u_rows = p.take<int32_t>(n);
     o.u_seg = p.take<int32_t>(a.usched.seg_row.size());
-    o.u_tseg = p.take<int32_t>(a.usched.tile_seg.size());
+    o.u_tdesc = p.take<int32_t>(kTileDesc * a.usched.tiles());
+    o.u_q = p.take<int32_t>(n);
+    o.u_q_k = p.take<int32_t>(n);
     o.u_ref = p.take<int32_t>(a.usched.ent_ref.size());
-    o.u_text = p.take<int32_t>(a.usched.tile_ext.size());
     o.u_esrc = p.take<int32_t>(a.usched.ext_src.size());
     o.u_rent = p.take<int64_t>(a.usched.row_ent.size());
-    o.u_tlds = p.take<uint8_t>(a.usched.tile_lds.size());
-    o.u_tden = p.take<int64_t>(a.usched.tile_dense.size());
     o.u_sdof = p.take<int32_t>(a.usched.seg_dofs.size());
     o.u_slg = p.take<int32_t>(a.usched.seg_lg.size());
     o.prow = p.take<int32_t>(n);
@@ -1982,6 +2059,31 @@ Offsets plan(const kkt_handle_t h) {
 template <typename T> hipError_t up(char *base, size_t off, const std::vector<T> &v, hipStream_t s) {
     if (v.empty()) return hipSuccess;
     return hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+// Per-tile descriptors of a solve schedule (kTileDesc ints each, the layout k_trsv reads).
+std::vector<int32_t> tile_descriptors(const TriSchedule &sc) {
+    std::vector<int32_t> d((size_t)kTileDesc * sc.tiles(), 0);
+    for (int64_t t = 0; t < sc.tiles(); ++t) {
+        int32_t *x = d.data() + kTileDesc * t;
+        const int32_t s0 = sc.tile_seg[t], s1 = sc.tile_seg[t + 1];
+        const int32_t rb = sc.seg_row[s0], re = sc.seg_row[s1];
+        const int64_t eb = sc.row_ent[rb], db = sc.tile_dense[t];
+        x[0] = s0;
+        x[1] = s1;
+        x[2] = rb;
+        x[3] = re;
+        x[4] = (int32_t)(uint32_t)(uint64_t)eb;
+        x[5] = (int32_t)(uint32_t)((uint64_t)eb >> 32);
+        x[6] = (int32_t)(sc.row_ent[re] - eb);
+        x[7] = sc.tile_ext[t];
+        x[8] = sc.tile_ext[t + 1] - sc.tile_ext[t];
+        x[9] = (int32_t)(uint32_t)(uint64_t)db;
+        x[10] = (int32_t)(uint32_t)((uint64_t)db >> 32);
+        x[11] = (int32_t)(sc.tile_dense[t + 1] - db);
+        x[12] = sc.tile_lds[t];
+    }
+    return d;
 }
 
 // Blocks of 256 threads that fit on the device at once (a persistent grid size).
@@ -2030,28 +2132,25 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     const TriSchedule &sc = lower ? a.lsched : a.usched;
     t.ntiles = sc.tiles();
     const DevLayout &d = h->d;
-    t.tile_seg = lower ? d.l_tseg : d.u_tseg;
     t.seg_row = lower ? d.l_seg : d.u_seg;
     t.seg_lg = lower ? d.l_slg : d.u_slg;
     t.rows = lower ? d.l_rows : d.u_rows;
     t.row_ent = lower ? d.l_rent : d.u_rent;
     t.ent_ref = lower ? d.l_ref : d.u_ref;
-    t.tile_ext = lower ? d.l_text : d.u_text;
     t.ext_src = lower ? d.l_esrc : d.u_esrc;
-    t.tile_lds = lower ? d.l_tlds : d.u_tlds;
-    t.tile_dense = lower ? d.l_tden : d.u_tden;
+    t.tdesc = lower ? d.l_tdesc : d.u_tdesc;
     t.seg_dofs = lower ? d.l_sdof : d.u_sdof;
     const T *base = (const T *)(is64 ? (void *)d.T64 : (void *)d.T32);
     if (lower) {
         t.val = base;
         t.rhs64 = rhs64;
-        t.prow = vorder ? d.prow_k : d.prow;
+        t.rsrc = vorder ? d.l_src_k : d.l_src;
     } else {
         t.val = base + a.lsched.values();
         t.diag = base + a.lsched.values() + a.usched.values();
         t.rhs_step = rhs_step;
         t.xout = xout;
-        t.q = vorder ? d.q_k : d.q;
+        t.qpos = vorder ? d.u_q_k : d.u_q;
     }
     t.out = out;
     t.stopflag = stopflag;
@@ -2834,24 +2933,22 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.kci = (int32_t *)(b + o.kci);
     d.l_rows = (int32_t *)(b + o.l_rows);
     d.l_seg = (int32_t *)(b + o.l_seg);
-    d.l_tseg = (int32_t *)(b + o.l_tseg);
+    d.l_tdesc = (int32_t *)(b + o.l_tdesc);
+    d.l_src = (int32_t *)(b + o.l_src);
+    d.l_src_k = (int32_t *)(b + o.l_src_k);
     d.l_ref = (int32_t *)(b + o.l_ref);
-    d.l_text = (int32_t *)(b + o.l_text);
     d.l_esrc = (int32_t *)(b + o.l_esrc);
     d.l_rent = (int64_t *)(b + o.l_rent);
-    d.l_tlds = (uint8_t *)(b + o.l_tlds);
-    d.l_tden = (int64_t *)(b + o.l_tden);
     d.l_sdof = (int32_t *)(b + o.l_sdof);
     d.l_slg = (int32_t *)(b + o.l_slg);
     d.u_rows = (int32_t *)(b + o.u_rows);
     d.u_seg = (int32_t *)(b + o.u_seg);
-    d.u_tseg = (int32_t *)(b + o.u_tseg);
+    d.u_tdesc = (int32_t *)(b + o.u_tdesc);
+    d.u_q = (int32_t *)(b + o.u_q);
+    d.u_q_k = (int32_t *)(b + o.u_q_k);
     d.u_ref = (int32_t *)(b + o.u_ref);
-    d.u_text = (int32_t *)(b + o.u_text);
     d.u_esrc = (int32_t *)(b + o.u_esrc);
     d.u_rent = (int64_t *)(b + o.u_rent);
-    d.u_tlds = (uint8_t *)(b + o.u_tlds);
-    d.u_tden = (int64_t *)(b + o.u_tden);
     d.u_sdof = (int32_t *)(b + o.u_sdof);
     d.u_slg = (int32_t *)(b + o.u_slg);
     d.prow = (int32_t *)(b + o.prow);
@@ -2918,24 +3015,34 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.q_k, a.q_k, s));
     KKT_HIP(h, up(b, o.l_rows, a.lsched.rows, s));
     KKT_HIP(h, up(b, o.l_seg, a.lsched.seg_row, s));
-    KKT_HIP(h, up(b, o.l_tseg, a.lsched.tile_seg, s));
+    // per-tile descriptors and the per-position right-hand-side sources / solution targets
+    {
+        const std::vector<int32_t> ld = tile_descriptors(a.lsched), ud = tile_descriptors(a.usched);
+        std::vector<int32_t> ls(a.n), lsk(a.n), uq(a.n), uqk(a.n);
+        for (int64_t p = 0; p < a.n; ++p) {
+            ls[p] = a.prow[a.lsched.rows[p]];
+            lsk[p] = a.prow_k[a.lsched.rows[p]];
+            uq[p] = a.q[a.usched.rows[p]];
+            uqk[p] = a.q_k[a.usched.rows[p]];
+        }
+        KKT_HIP(h, up(b, o.l_tdesc, ld, s));
+        KKT_HIP(h, up(b, o.u_tdesc, ud, s));
+        KKT_HIP(h, up(b, o.l_src, ls, s));
+        KKT_HIP(h, up(b, o.l_src_k, lsk, s));
+        KKT_HIP(h, up(b, o.u_q, uq, s));
+        KKT_HIP(h, up(b, o.u_q_k, uqk, s));
+        KKT_HIP(h, hipStreamSynchronize(s));  // the vectors are locals
+    }
     KKT_HIP(h, up(b, o.l_ref, a.lsched.ent_ref, s));
-    KKT_HIP(h, up(b, o.l_text, a.lsched.tile_ext, s));
     KKT_HIP(h, up(b, o.l_esrc, a.lsched.ext_src, s));
     KKT_HIP(h, up(b, o.l_rent, a.lsched.row_ent, s));
-    KKT_HIP(h, up(b, o.l_tlds, a.lsched.tile_lds, s));
-    KKT_HIP(h, up(b, o.l_tden, a.lsched.tile_dense, s));
     KKT_HIP(h, up(b, o.l_sdof, a.lsched.seg_dofs, s));
     KKT_HIP(h, up(b, o.l_slg, a.lsched.seg_lg, s));
     KKT_HIP(h, up(b, o.u_rows, a.usched.rows, s));
     KKT_HIP(h, up(b, o.u_seg, a.usched.seg_row, s));
-    KKT_HIP(h, up(b, o.u_tseg, a.usched.tile_seg, s));
     KKT_HIP(h, up(b, o.u_ref, a.usched.ent_ref, s));
-    KKT_HIP(h, up(b, o.u_text, a.usched.tile_ext, s));
     KKT_HIP(h, up(b, o.u_esrc, a.usched.ext_src, s));
     KKT_HIP(h, up(b, o.u_rent, a.usched.row_ent, s));
-    KKT_HIP(h, up(b, o.u_tlds, a.usched.tile_lds, s));
-    KKT_HIP(h, up(b, o.u_tden, a.usched.tile_dense, s));
     KKT_HIP(h, up(b, o.u_sdof, a.usched.seg_dofs, s));
     KKT_HIP(h, up(b, o.u_slg, a.usched.seg_lg, s));
     KKT_HIP(h, up(b, o.prow, a.prow, s));

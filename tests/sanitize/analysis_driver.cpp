@@ -34,7 +34,7 @@ int main(int argc, char **argv) {
     opt.pivot_tau = tau;
     opt.tile_threads = 256;
     opt.tile_rows = 2048;
-    opt.tile_lds = tile_kib > 0 ? tile_kib * 1024 : 65536;
+    opt.tile_lds = tile_kib > 0 ? tile_kib * 1024 : 32768;  // the library default
     opt.dense_reserve_l = opt.tile_lds / 2;
     opt.narrow_columns = 1024;
     kkt::Analysis a;

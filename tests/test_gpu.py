@@ -125,7 +125,7 @@ def check_solve_backward_error(f, lx, ux, b, x, unit):
 @pytest.mark.parametrize("cfg", [1, 2])
 @pytest.mark.parametrize("step", [1, 2])
 def test_direct_solve_backward_error(dev, cfg, step, tile_kib):
-    # tile_kib: the default 64 KiB solve tiles, and the largest budget (one block per CU)
+    # tile_kib: the default 32 KiB solve tiles, and the largest budget (one block per CU)
     say("direct solve config", cfg, "step", step, "tile KiB", tile_kib)
     p, s, f = make(cfg, dev, tile_lds_kib=tile_kib)
     v, b = p.system(step)
