@@ -120,9 +120,11 @@ typedef struct {
                                faster at 32 than at 64 on 60k and 2M unknowns); above 80 KiB
                                one solve block occupies a compute unit alone */
     int32_t narrow_columns; /* refactorization levels with at most this many columns are handed
-                               out one column per wavefront, wider ones up to 8 columns per
-                               grab (0: automatic, n/64 clamped to 1024..16384; measured best
-                               at 60k, 500k and 2M unknowns); negative values are rejected
+                               out one column per wavefront, wider ones as lane items (64
+                               short columns, one per lane) and chunks of 8 longer columns (0:
+                               automatic, the larger of 3,072 (the refactorization's resident
+                               wavefronts) and n/64 capped at 16,384; measured best at 60k,
+                               500k and 2M unknowns); negative values are rejected
                                (KKT_EINVAL).  The factors do not depend on it. */
     int32_t reserved;
 } kkt_opts_t;

@@ -16,6 +16,9 @@ constexpr int kTileRows = 2048;        // rows of a multi-level solve tile (valu
 constexpr int kTileLds = 32768;        // default LDS bytes of a staged solve tile
 constexpr int kTileLdsMin = 16 * 1024;  // smallest and largest tile budgets (gfx950: 160 KiB of LDS
 constexpr int kTileLdsMax = 150 * 1024; // per compute unit, the rest for the kernel's own arrays)
+// Wavefronts the refactorization keeps resident on an MI355X: 3 blocks of 4 per compute unit,
+// 256 compute units.
+constexpr int kResidentRefactorWaves = 3 * 4 * 256;
 constexpr int kRefactorLds = 1024;     // factor entries staged in LDS per wavefront
 constexpr int kMaxBatch = 8;           // systems of one pattern refactored by one launch
 constexpr int kWorkQueues = 8;         // refactorization hand-out queues (one per XCD of MI355X: a

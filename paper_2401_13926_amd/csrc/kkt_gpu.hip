@@ -2614,15 +2614,16 @@ AnalysisOptions analysis_options(const kkt_opts_t &o, int64_t n) {
     ao.tile_rows = kTileRows;
     ao.tile_lds = o.tile_lds_kib > 0 ? o.tile_lds_kib * 1024 : kTileLds;
     ao.dense_reserve_l = ao.tile_lds / 2;  // half the tile for dense blocks (60k L solve 123.9 -> 119.7 us against a quarter)
-    // Wide levels go 16 columns per grab, narrow ones a column at a time.  A grab's columns
-    // run in sequence on one wavefront, which only pays while their sources are long done
-    // (the leaves); past that, a source queued behind others in someone's grab delays every
-    // column above it.  The width where this turns was measured to grow with n: 1,024 best at
-    // 60k unknowns, ~8,192 at 500k and 8,192-16,384 at 2M (refactorization 6.7 -> 2.8 ms and
-    // 19.3 -> 7.5 ms against a fixed 1,024).
+    // Wide levels run as lane items (64 short columns, one per lane) and chunks, narrow ones a
+    // column per wavefront.  A lane walks its column's updates alone, which pays while a level
+    // has many more columns than there are wavefronts; a level that one wavefront per column
+    // covers in a single round is faster on the one-column path.  Hence at least the resident
+    // wavefronts of the refactorization (3 blocks of 4 per compute unit, 256 compute units),
+    // and n/64 up to 16,384 beyond that: measured best at 60k (3,072: 187 -> 145 us), 500k
+    // (~8,192-12,288) and 2M (16,384) unknowns.
     ao.narrow_columns = o.narrow_columns > 0
                             ? o.narrow_columns
-                            : (int)std::min<int64_t>(16384, std::max<int64_t>(1024, n / 64));
+                            : (int)std::max<int64_t>(kResidentRefactorWaves, std::min<int64_t>(16384, n / 64));
     return ao;
 }
 
