@@ -24,6 +24,11 @@ def test_exports_every_declared_symbol():
     lib = P.lib()
     for name in declared:
         assert hasattr(lib, name), name
+    # every entry point that takes arguments has its ctypes argument types declared (a float
+    # argument without them cannot be passed)
+    for name in declared:
+        if "(void)" not in header.split(name + "(")[1][:8]:
+            assert getattr(lib, name).argtypes is not None, name
 
 
 def check_parity(rowptr, colidx, values, leaf=64, tau=0.1, method="md"):
