@@ -173,7 +173,7 @@ WORKLOADS = {1: ("kkt_single_7k", 10), 2: ("kkt_sequence_60k", 10), 3: ("kkt_seq
 
 
 def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, restart=10, gram_schmidt=0,
-            tile_lds_kib=0, cold_steps=0, separate=False):
+            tile_lds_kib=0, cold_steps=0):
     dev = torch.device("cuda:0")
     v1, _ = systems[0]
     t0 = time.perf_counter()
@@ -185,17 +185,9 @@ def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, resta
     rhs = [torch.as_tensor(b, device=dev) for _, b in systems]
     x = torch.empty_like(rhs[0])
     M = len(systems)
-
-    def step(k):
-        # one step: refactor with system k's values, then solve for its right-hand side (the
-        # combined call runs x0's lower sweep beside the refactorization; --separate makes
-        # the two calls one after the other)
-        if separate:
-            s.refactor(vals[k])
-            return s.solve(rhs[k], x, allow_noconv=True)[1]
-        return s.refactor_solve(vals[k], rhs[k], x, allow_noconv=True)[1]
     for i in range(warmup):
-        step(i % M)
+        s.refactor(vals[i % M])
+        s.solve(rhs[i % M], x, allow_noconv=True)
     torch.cuda.synchronize()
     # Untimed breakdown pass with every kernel class timed (two events per launch cost about
     # 10 % of a step); it names the dominant class, whose launches alone carry events in the
@@ -205,7 +197,8 @@ def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, resta
         s.set_profiling(True)
         for i in range(min(steps, 20)):
             k = (warmup + i) % M
-            step(k)
+            s.refactor(vals[k])
+            s.solve(rhs[k], x, allow_noconv=True)
         breakdown = s.kernel_times()
         cands = [c for c in ("refactor", "trsv_l", "trsv_u", "spmv") if breakdown[c][0] > 0]
         dom = max(cands, key=lambda c: breakdown[c][1])
@@ -218,7 +211,8 @@ def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, resta
     for i in range(steps):
         k = (warmup + i) % M
         ev[i][0].record()
-        info = step(k)
+        s.refactor(vals[k])
+        _, info = s.solve(rhs[k], x, allow_noconv=True)
         ev[i][1].record()
         infos.append(info)
     torch.cuda.synchronize()
@@ -239,7 +233,8 @@ def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, resta
             flush_dst.copy_(flush_src)
             a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
-            step(k)
+            s.refactor(vals[k])
+            s.solve(rhs[k], x, allow_noconv=True)
             b_.record()
             b_.synchronize()
             cold.append(a.elapsed_time(b_))
@@ -248,7 +243,8 @@ def run_gpu(P, torch, pattern, systems, steps, warmup, precision, profile, resta
     # with the CPU baseline's solutions)
     xs, nrbe_all = [], []
     for k in range(M):
-        info = step(k)
+        s.refactor(vals[k])
+        _, info = s.solve(rhs[k], x, allow_noconv=True)
         xs.append(x.cpu().numpy().copy())
         nrbe_all.append(info["nrbe"])
     return dict(nrbe_all=nrbe_all, solver=s, analysis_s=analysis_s, wall=wall, lat=lat, infos=infos, times=times,
@@ -437,9 +433,6 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--separate", action="store_true",
-                    help="a step as kkt_refactor then kkt_solve (default: kkt_refactor_solve, which runs "
-                         "x0's lower sweep beside the refactorization; same results bit for bit)")
     ap.add_argument("--serve", action="store_true",
                     help="serving workload: Poisson arrivals over 8 patterns, then saturation")
     ap.add_argument("--requests", type=int, default=2000)
@@ -503,7 +496,7 @@ def main():
     wname, restart = WORKLOADS[cfg]
     gs = P.GS_DCGS2 if args.gram_schmidt == "dcgs2" else P.GS_CGS2
     r64 = run_gpu(P, torch, pattern, systems, args.steps, args.warmup, P.PREC_FP64, not args.no_profile, restart, gs,
-                  args.tile_lds_kib, args.cold_steps, args.separate)
+                  args.tile_lds_kib, args.cold_steps)
     copy_gbs = copy_bandwidth(torch)
     ai = r64["solver"].info()
     print("fp64 done: %.1f ms/step" % (1e3 * r64["wall"] / args.steps), file=sys.stderr, flush=True)
@@ -531,7 +524,6 @@ def main():
         "config": {"workload": wname, "N": pattern.N,
                    "nnz": pattern.nnz, "systems": nsys, "restart": restart, "delta_tol": 1e-14,
                    "nrbe_target": 1e-12, "precision": "fp64", "gram_schmidt": args.gram_schmidt,
-                   "step_call": "kkt_refactor + kkt_solve" if args.separate else "kkt_refactor_solve",
                    "tile_lds_kib": args.tile_lds_kib},
         "p50_ms": percentile(r64["lat"], 50),
         "p99_ms": percentile(r64["lat"], 99),

@@ -276,17 +276,6 @@ kkt_status_t kkt_graph_launches(kkt_handle_t h, int64_t *launches);
 kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, double tol,
                        kkt_solve_info_t *info, void *stream);
 
-/* kkt_refactor(h, dev_values) followed by kkt_solve(h, dev_b, dev_x, tol, info): the same
- * operations in the same order and the same result bit for bit (Section 1.3 then Section 2.1),
- * with x0's lower triangular sweep running beside the refactorization: each L value is waited
- * for as it is published, so the sweep's tiles start as soon as the columns they read are
- * done.  The values and b must be ready on `stream` when the call is made; both calls' errors
- * apply.  The overlap covers precision KKT_PREC_FP64 with FGMRES-IR; other settings run the two
- * calls in turn.  Uses a second stream of the handle (created at the first call, default
- * priority) that waits for `stream`, and joins it before the upper sweep. */
-kkt_status_t kkt_refactor_solve(kkt_handle_t h, const double *dev_values, const double *dev_b, double *dev_x,
-                                double tol, kkt_solve_info_t *info, void *stream);
-
 /* Apply the current preconditioner once: x = Q U^-1 L^-1 P b with the last refactored
  * factors (the direct solve of Section 1.3, no refinement).  DEVICE arrays of n float64.
  * Enqueued on `stream`, not synchronized. */

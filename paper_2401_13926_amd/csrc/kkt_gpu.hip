@@ -30,7 +30,6 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
-#include <functional>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -75,14 +74,6 @@ template <typename T> __device__ __forceinline__ void store_ready(T *p, T v) {
     using U = typename Bits<T>::U;
     __hip_atomic_store(reinterpret_cast<U *>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-// A factor value into the solve layout: L entries (below the diagonal) with a coherent store,
-// since a lower triangular solve may run concurrently and wait for them (kkt_refactor_solve);
-// U entries and the diagonal with a plain store (read only after the refactorization ends).
-template <typename T> __device__ __forceinline__ void store_t(T *p, T v, bool lower) {
-    if (lower) store_ready(p, v);
-    else *p = v;
 }
 
 // Value of a solution entry produced by another wavefront: a plain load first (it can only
@@ -283,15 +274,6 @@ __global__ void k_arm(int64_t f, const int64_t *__restrict__ fsrc, const double 
             Ld64[t] = sentinel<double>();
         }
     }
-}
-
-// Arms the L entries of the solve layout with sentinels (their positions in tarm), so that a
-// lower sweep running beside the refactorization waits for each.
-template <typename T>
-__global__ void k_arm_t(int64_t cnt, const int32_t *__restrict__ tarm, T *__restrict__ Tv) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += stride)
-        Tv[tarm[k]] = sentinel<T>();
 }
 
 // Vectors between the caller's (original) order and the vector order of a solve:
@@ -625,7 +607,7 @@ __device__ void refactor_group(const RefactorArgs<T> &a, T *xs_wave, int src0, i
         if (e == nu) v = d;
         else if (e > nu) v = v / d;
         a.F[c0 + e] = v;
-        store_t(a.Tv + a.f2t[c0 + e], v, e > nu);
+        a.Tv[a.f2t[c0 + e]] = v;
     }
 }
 
@@ -717,7 +699,7 @@ __device__ void refactor_lanes(const RefactorArgs<T> &a, T *xs, int64_t cbeg, in
             if (e == nu) v = d;
             else if (e > nu) v = v / d;
             a.F[c0 + e] = v;
-            store_t(a.Tv + a.f2t[c0 + e], v, e > nu);
+            a.Tv[a.f2t[c0 + e]] = v;
         }
     }
 }
@@ -874,7 +856,7 @@ k_refactor(RefactorArgs<T> args, RefactorBatch<T> batch) {
             if (e == nu) v = d;
             else if (e > nu) v = v / d;
             a.F[c0 + e] = v;
-            store_t(a.Tv + a.f2t[c0 + e], v, e > nu);
+            a.Tv[a.f2t[c0 + e]] = v;
         }
         }
     }
@@ -1026,9 +1008,7 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
                     const int c = a.ent_ref[eb + e];
                     T xk = a.out[c];
                     if (is_sentinel(xk)) xk = load_ready<T, 1>(a.out + c, a.hang);
-                    T lv = a.val[eb + e];
-                    if (is_sentinel(lv)) lv = load_ready<T, 1>(a.val + eb + e, a.hang);
-                    const T prod = lv * xk;
+                    const T prod = a.val[eb + e] * xk;
                     acc = acc + prod;
                 }
                 for (int o = 1; o < 64; o <<= 1) acc = acc + __shfl_xor(acc, o, 64);
@@ -1115,15 +1095,14 @@ __global__ void __launch_bounds__(kTileThreads) k_trsv(TrsvArgs<T> a) {
             for (int u = 0; u < kStageEnt; ++u) {
                 const int k = pe + tid + u * kTileThreads;
                 if (k < ne) {
-                    // L values still being refactored (kkt_refactor_solve) hold the sentinel
-                    vals[k] = is_sentinel(v[u]) ? load_ready<T, 1>(a.val + eb + k, a.hang) : v[u];
+                    vals[k] = v[u];
                     refs[k] = (uint16_t)c[u];
                 }
             }
 #pragma unroll
             for (int u = 0; u < kStageDense; ++u) {
                 const int k = pd + tid + u * kTileThreads;
-                if (k < nd) dvs[k] = is_sentinel(dv[u]) ? load_ready<T, 1>(a.val + db + k, a.hang) : dv[u];
+                if (k < nd) dvs[k] = dv[u];
             }
 #pragma unroll
             for (int u = 0; u < kStageRow; ++u) {
@@ -1848,7 +1827,7 @@ struct DevLayout {
     int32_t *prow, *q;
     // the vector order of a solve: its permutation, the copy of K's entry sources, and the
     // pivot permutations composed with it
-    int32_t *vperm, *prow_k, *q_k, *fsrc32, *tarm;
+    int32_t *vperm, *prow_k, *q_k, *fsrc32;
     int64_t *ostart;
     // triangular-solve schedules (L, U): rows, level starts, lanes, tiles, references
     int32_t *l_rows, *l_seg, *l_tdesc, *l_ref, *l_esrc, *l_src, *l_src_k;
@@ -1892,10 +1871,6 @@ struct kkt_handle_s {
     kkt::StepRecord *host_rec = nullptr;      // pinned, kRestartMax + 1 records (one per step)
     kkt::StepRecord *dev_rec = nullptr;       // the same memory as seen by kernels
     hipEvent_t step_ev[2] = {nullptr, nullptr};
-    // kkt_refactor_solve: the stream of the lower sweep that runs beside the refactorization,
-    // and its two events (inputs staged; sweep done)
-    hipStream_t side = nullptr;
-    hipEvent_t ov_ev[2] = {nullptr, nullptr};
     int restart_alloc = 0;
     bool fp64_current = false;  // mixed mode: FP64 factors of the current system exist
     int64_t repivots = 0;       // re-pivoted factorizations so far
@@ -1998,7 +1973,7 @@ struct Planner {
 struct Offsets {
     size_t fp, fi, fdiag, order, clev, f2t, relptr, fsrc, relpos, relsrc, relslot, pc, pu, pnu, item, item_lane, krp, kci, l_rows, l_seg, l_tdesc,
         l_ref, l_slg, l_esrc, l_rent, l_sdof, l_src, l_src_k, u_rows, u_seg, u_tdesc, u_ref, u_slg, u_esrc,
-        u_rent, u_sdof, u_q, u_q_k, prow, q, vperm, prow_k, q_k, ostart, fsrc32, tarm, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
+        u_rent, u_sdof, u_q, u_q_k, prow, q, vperm, prow_k, q_k, ostart, fsrc32, kval, F64, T64, F32, T32, Ld64, Ld32, V, Z, w, r, y64, z64, y32,
         z32, dv, rr, xb, bi, xi, part, ctl, total;
 };
 
@@ -2055,7 +2030,6 @@ Offsets plan(const kkt_handle_t h) {
     o.prow_k = p.take<int32_t>(n);
     o.q_k = p.take<int32_t>(n);
     o.ostart = p.take<int64_t>(n);
-    o.tarm = p.take<int32_t>(a.nnz_l());
     o.kval = p.take<double>(a.nnz);
     o.F64 = p.take<double>(f);
     o.T64 = p.take<double>(a.t_size);
@@ -2151,7 +2125,7 @@ template <typename T>
 // the caller's original order)
 hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T *rhs_step, T *out, double *xout,
                        const Control *stopflag, hipStream_t s, bool vorder, unsigned int *work = nullptr,
-                       unsigned int *hang = nullptr, int grid_cap = 0) {
+                       unsigned int *hang = nullptr) {
     const Analysis &a = h->an;
     TrsvArgs<T> t{};
     const bool is64 = sizeof(T) == 8;
@@ -2182,8 +2156,7 @@ hipError_t launch_trsv(kkt_handle_t h, bool lower, const double *rhs64, const T 
     t.stopflag = stopflag;
     t.work = work ? work : lower ? &d.ctl->work_lower : &d.ctl->work_upper;
     t.hang = hang ? hang : &d.ctl->hang;
-    int grid = (int)std::max<int64_t>(1, std::min<int64_t>(is64 ? h->grid_trsv64 : h->grid_trsv32, t.ntiles));
-    if (grid_cap > 0) grid = std::min(grid, grid_cap);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(is64 ? h->grid_trsv64 : h->grid_trsv32, t.ntiles));
     // the variant without the dense-segment path when the schedule has none
     const bool dense = sc.values() > sc.packed;
     if (lower && dense) k_trsv<T, true, true><<<grid, kTileThreads, h->tile_lds, s>>>(t);
@@ -2222,9 +2195,8 @@ template <typename T> void rearm(kkt_handle_t h, hipStream_t s) {
 // (bound to the same analysis as hs[0]) gets the values at vals[b] (device; when null, the
 // values already in its workspace are re-ingested).  Ingest runs per system; the
 // refactorizations of all of them run in one launch, with hs[0]'s structure arrays.
-// between (optional): enqueued after the ingest and before the refactorization kernel.
 kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *vals, int count, int precision,
-                                 hipStream_t s, const std::function<kkt_status_t()> &between = nullptr) {
+                                 hipStream_t s) {
     const kkt_handle_t h = hs[0];
     const Analysis &a = h->an;
     const int64_t f = a.nnz_f();
@@ -2247,10 +2219,6 @@ kkt_status_t refactor_batch_impl(const kkt_handle_t *hs, const double *const *va
     prof_end(h, KKT_K_INGEST, e0, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail_all(std::string("ingest: ") + hipGetErrorString(e));
-    if (between) {
-        const kkt_status_t st = between();
-        if (st != KKT_OK) return st;
-    }
     e0 = prof_begin(h, KKT_K_REFACTOR, s);
     const DevLayout &d = h->d;
     const int64_t nitems = (int64_t)a.ref_item.size() - 1;
@@ -2315,11 +2283,9 @@ kkt_status_t read_ctl(kkt_handle_t h, hipStream_t s) {
 // the next step runs; at most one step is enqueued past the end of a cycle, and its kernels
 // return at once.
 // require_nrbe = false runs FGMRES as an inner solver (acceptance on its estimate only).
-// lower_done: the solve state was prepared and x0's lower sweep already ran (kkt_refactor_solve
-// overlaps it with the refactorization); only the upper sweep of x0 is left.
 template <typename T>
 kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, kkt_solve_info_t *info,
-                        hipStream_t s, int max_cycles, bool require_nrbe = true, bool lower_done = false) {
+                        hipStream_t s, int max_cycles, bool require_nrbe = true) {
     const Analysis &a = h->an;
     DevLayout &d = h->d;
     const int R = h->opts.restart;
@@ -2327,19 +2293,11 @@ kkt_status_t solve_impl(kkt_handle_t h, const double *b, double *x, double tol, 
     KrylovArgs ka = kargs<T>(h);
     T *y = (T *)(sizeof(T) == 8 ? (void *)d.y64 : (void *)d.y32);
     T *z = (T *)(sizeof(T) == 8 ? (void *)d.z64 : (void *)d.z32);
-    hipEvent_t e0;
-    if (lower_done) {
-        e0 = prof_begin(h, KKT_K_TRSV_U, s);
-        const hipError_t eu = launch_trsv<T>(h, false, nullptr, y, z, x, nullptr, s, true);
-        prof_end(h, KKT_K_TRSV_U, e0, s);
-        KKT_HIP(h, eu);
-    } else {
-        e0 = prof_begin(h, KKT_K_OTHER, s);
-        k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
-        prof_end(h, KKT_K_OTHER, e0, s);
-        rearm<T>(h, s);
-        KKT_HIP(h, precond<T>(h, b, x, nullptr, s, true));
-    }
+    hipEvent_t e0 = prof_begin(h, KKT_K_OTHER, s);
+    k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
+    prof_end(h, KKT_K_OTHER, e0, s);
+    rearm<T>(h, s);
+    KKT_HIP(h, precond<T>(h, b, x, nullptr, s, true));
     e0 = prof_begin(h, KKT_K_RESID, s);
     launch_resid(h, ka, b, x, d.r, s);
     k_resid_reduce<<<1, kStreamBlock, 0, s>>>(ka, G, h->dev_ctl_sum);
@@ -2808,7 +2766,7 @@ hipError_t direct_solve_scratch(kkt_handle_t h, const double *b, double *x, unsi
 }  // namespace kkt
 
 static kkt_status_t solve_vorder(kkt_handle_t h, const double *dev_b, double tol, kkt_solve_info_t *info,
-                                 hipStream_t s, bool lower_done = false);
+                                 hipStream_t s);
 
 extern "C" {
 
@@ -3000,7 +2958,6 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     d.prow_k = (int32_t *)(b + o.prow_k);
     d.q_k = (int32_t *)(b + o.q_k);
     d.ostart = (int64_t *)(b + o.ostart);
-    d.tarm = (int32_t *)(b + o.tarm);
     d.fsrc32 = (int32_t *)(b + o.fsrc32);
     d.kval = (double *)(b + o.kval);
     d.F64 = (double *)(b + o.F64);
@@ -3048,19 +3005,6 @@ kkt_status_t kkt_bind_workspace(kkt_handle_t h, void *dev_ptr, size_t bytes, voi
     KKT_HIP(h, up(b, o.item_lane, a.ref_item_lane, s));
     KKT_HIP(h, up(b, o.krp, a.krp, s));
     KKT_HIP(h, up(b, o.kci, a.kci, s));
-    {
-        // solve-layout positions of the L entries, ascending (armed by kkt_refactor_solve)
-        std::vector<int32_t> tarm;
-        tarm.reserve(a.nnz_l());
-        for (int64_t p = 0; p < a.n; ++p) {
-            const int64_t b0 = a.phys ? a.pc[p] + a.pnu[p] + 1 : a.fp[p] + a.fdiag[p] + 1;
-            const int64_t b1 = a.phys ? a.pc[p + 1] : a.fp[p + 1];
-            for (int64_t t = b0; t < b1; ++t) tarm.push_back(a.f2t[t]);
-        }
-        std::sort(tarm.begin(), tarm.end());
-        KKT_HIP(h, up(b, o.tarm, tarm, s));
-        KKT_HIP(h, hipStreamSynchronize(s));  // tarm is a local
-    }
     {
         std::vector<int64_t> ost(a.n);
         for (int64_t k = 0; k < a.n; ++k) ost[k] = a.rowptr[a.vperm[k]];
@@ -3261,14 +3205,13 @@ kkt_status_t kkt_solve(kkt_handle_t h, const double *dev_b, double *dev_x, doubl
 // is gathered into the workspace's b, the solution is left in its x.  A re-pivot re-lays out
 // the workspace, so both are taken from the layout after it (and b gathered again).
 static kkt_status_t solve_vorder(kkt_handle_t h, const double *dev_b, double tol, kkt_solve_info_t *info,
-                                 hipStream_t s, bool lower_done) {
+                                 hipStream_t s) {
     auto gather_b = [&]() -> kkt_status_t {
         k_vgather<<<h->grid_stream, kStreamBlock, 0, s>>>(h->an.n, h->d.vperm, dev_b, h->d.bi);
         KKT_HIP(h, hipGetLastError());
         return KKT_OK;
     };
-    // with lower_done, b is already gathered and x0's lower sweep has run (FP64 only)
-    if (!lower_done && gather_b() != KKT_OK) return KKT_EDEVICE;
+    if (gather_b() != KKT_OK) return KKT_EDEVICE;
     const int cycles = h->opts.max_restarts + 1;
     if (h->factor_precision == KKT_PREC_MIXED && !h->fp64_current) {
         const int mixed_cycles = h->opts.mixed_fallback ? std::min(cycles, std::max(1, h->opts.mixed_max_cycles))
@@ -3288,7 +3231,7 @@ static kkt_status_t solve_vorder(kkt_handle_t h, const double *dev_b, double tol
     } else {
         const bool rp = h->opts.repivot_cycles > 0;
         st = solve_impl<double>(h, h->d.bi, h->d.xi, tol, info, s,
-                                rp ? std::min(cycles, h->opts.repivot_cycles) : cycles, true, lower_done);
+                                rp ? std::min(cycles, h->opts.repivot_cycles) : cycles);
         if (st == KKT_ENOCONV && rp) {
             st = repivot_impl(h, s);
             if (st != KKT_OK) return st;
@@ -3302,66 +3245,6 @@ static kkt_status_t solve_vorder(kkt_handle_t h, const double *dev_b, double tol
 }
 
 extern "C" {
-
-kkt_status_t kkt_refactor_solve(kkt_handle_t h, const double *dev_values, const double *dev_b, double *dev_x,
-                                double tol, kkt_solve_info_t *info, void *stream) {
-    if (!h || !dev_values || !dev_b || !dev_x) return fail(h, KKT_EINVAL, "null argument");
-    if (dev_b == dev_x) return fail(h, KKT_EINVAL, "b and x must be distinct");
-    if (h->device_failed) return fail(h, KKT_EDEVICE, "handle unusable after a device error");
-    if (!h->bound) return fail(h, KKT_ESTATE, "no workspace bound");
-    hipStream_t s = (hipStream_t)stream;
-    // the overlap covers the FP64 FGMRES-IR path; other settings run the two calls in turn
-    if (h->opts.precision != KKT_PREC_FP64 || h->opts.ir_method == KKT_IR_RICHARDSON ||
-        h->opts.ir_method == KKT_IR_ERROR_FGMRES) {
-        const kkt_status_t st = kkt_refactor(h, dev_values, stream);
-        if (st != KKT_OK) return st;
-        return kkt_solve(h, dev_b, dev_x, tol, info, stream);
-    }
-    if (tol <= 0.0) tol = h->opts.delta_tol;
-    if (!h->side) KKT_HIP(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-    for (int e = 0; e < 2; ++e)
-        if (!h->ov_ev[e]) KKT_HIP(h, hipEventCreateWithFlags(&h->ov_ev[e], hipEventDisableTiming));
-    h->fp64_current = false;
-    const Analysis &a = h->an;
-    DevLayout &d = h->d;
-    // After the ingest: the L entries of the solve layout armed, the solve state prepared and b
-    // gathered; then x0's lower sweep starts on the side stream with at most one block per
-    // compute unit (so the refactorization's three blocks per unit always fit beside it: no
-    // wait of the sweep can hold back the columns it waits for) while the refactorization runs,
-    // and a second launch of the same sweep with the full grid takes the tiles left once the
-    // refactorization has ended.  The upper sweep waits for both.
-    auto between = [&]() -> kkt_status_t {
-        k_arm_t<double><<<2048, 256, 0, s>>>(a.nnz_l(), d.tarm, d.T64);
-        k_prep_solve<<<1, 1, 0, s>>>(d.ctl);
-        rearm<double>(h, s);
-        k_vgather<<<h->grid_stream, kStreamBlock, 0, s>>>(a.n, d.vperm, dev_b, d.bi);
-        KKT_HIP(h, hipGetLastError());
-        KKT_HIP(h, hipEventRecord(h->ov_ev[0], s));
-        KKT_HIP(h, hipStreamWaitEvent(h->side, h->ov_ev[0], 0));
-        int cus = 0;
-        KKT_HIP(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
-        hipEvent_t e0 = prof_begin(h, KKT_K_TRSV_L, h->side);
-        const hipError_t el = launch_trsv<double>(h, true, d.bi, nullptr, d.y64, nullptr, nullptr, h->side, true,
-                                                  nullptr, nullptr, std::max(cus, 1));
-        prof_end(h, KKT_K_TRSV_L, e0, h->side);
-        KKT_HIP(h, el);
-        KKT_HIP(h, hipEventRecord(h->ov_ev[1], h->side));
-        return KKT_OK;
-    };
-    kkt_status_t st = refactor_batch_impl(&h, &dev_values, 1, KKT_PREC_FP64, s, between);
-    if (st != KKT_OK) return st;
-    hipEvent_t e0 = prof_begin(h, KKT_K_TRSV_L, s);
-    const hipError_t el = launch_trsv<double>(h, true, d.bi, nullptr, d.y64, nullptr, nullptr, s, true);
-    prof_end(h, KKT_K_TRSV_L, e0, s);
-    KKT_HIP(h, el);
-    KKT_HIP(h, hipStreamWaitEvent(s, h->ov_ev[1], 0));
-    st = solve_vorder(h, dev_b, tol, info, s, true);
-    if (st == KKT_OK || st == KKT_ENOCONV) {
-        k_vscatter<<<h->grid_stream, kStreamBlock, 0, s>>>(a.n, d.vperm, d.xi, dev_x);
-        KKT_HIP(h, hipGetLastError());
-    }
-    return st;
-}
 
 kkt_status_t kkt_direct_solve(kkt_handle_t h, const double *dev_b, double *dev_x, void *stream) {
     if (!h || !dev_b || !dev_x) return fail(h, KKT_EINVAL, "null argument");
@@ -3489,9 +3372,6 @@ kkt_status_t kkt_release(kkt_handle_t h) {
     if (h->host_rec) (void)hipHostFree(h->host_rec);
     for (auto e : h->step_ev)
         if (e) (void)hipEventDestroy(e);
-    for (auto e : h->ov_ev)
-        if (e) (void)hipEventDestroy(e);
-    if (h->side) (void)hipStreamDestroy(h->side);
     delete h;
     return KKT_OK;
 }

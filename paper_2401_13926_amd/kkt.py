@@ -29,7 +29,7 @@ GS_CGS2, GS_DCGS2 = 0, 1
 EXPORTS = ["kkt_opts_default", "kkt_analyze", "kkt_get_analysis_info", "kkt_get_permutations",
            "kkt_get_factor_pattern", "kkt_get_analysis_values", "kkt_workspace_size",
            "kkt_bind_workspace", "kkt_refactor", "kkt_refactor_batch", "kkt_refactor_batch_graph",
-           "kkt_graph_launches", "kkt_solve", "kkt_refactor_solve", "kkt_direct_solve", "kkt_direct_solve_noalloc",
+           "kkt_graph_launches", "kkt_solve", "kkt_direct_solve", "kkt_direct_solve_noalloc",
            "kkt_residual",
            "kkt_get_factor_values", "kkt_set_profiling", "kkt_set_profiling_mask", "kkt_get_kernel_times",
            "kkt_release",
@@ -130,7 +130,6 @@ def lib():
         L.kkt_bind_workspace.argtypes = [vp, vp, C.c_size_t, vp]
         L.kkt_refactor.argtypes = [vp, vp, vp]
         L.kkt_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(SolveInfo), vp]
-        L.kkt_refactor_solve.argtypes = [vp, vp, vp, vp, C.c_double, C.POINTER(SolveInfo), vp]
         L.kkt_direct_solve.argtypes = [vp, vp, vp, vp]
         L.kkt_direct_solve_noalloc.argtypes = [vp, vp, vp, vp]
         L.kkt_residual.argtypes = [vp, vp, vp, vp, vp]
@@ -303,23 +302,6 @@ class Solver:
         rc = lib().kkt_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol),
                              C.byref(info), _stream_ptr(stream))
         self._check(rc, allow=(KKT_ENOCONV,) if allow_noconv else ())
-        d = info.as_dict()
-        d["status"] = rc
-        return x, d
-
-    def refactor_solve(self, values, b, x=None, tol: float = 0.0, stream=None, allow_noconv=False):
-        """kkt_refactor_solve: refactor with `values` and solve for b (x0's lower sweep beside
-        the refactorization); returns (x, info dict) like refactor() then solve()."""
-        import torch
-        assert values.is_cuda and values.element_size() == 8 and values.is_contiguous()
-        assert b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == self.n
-        if x is None:
-            x = torch.empty_like(b)
-        info = SolveInfo()
-        rc = lib().kkt_refactor_solve(self._h, C.c_void_p(values.data_ptr()), C.c_void_p(b.data_ptr()),
-                                      C.c_void_p(x.data_ptr()), float(tol), C.byref(info), _stream_ptr(stream))
-        self._check(rc, allow=(KKT_ENOCONV,) if allow_noconv else ())
-        self._values_ref = values
         d = info.as_dict()
         d["status"] = rc
         return x, d

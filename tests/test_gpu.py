@@ -196,33 +196,6 @@ def test_fgmres_ir_sequence(dev, cfg):
         assert rel <= 1.01 * reld + 1e-13
 
 
-@pytest.mark.parametrize("cfg,opts", [(1, {}), (2, {}), (2, dict(precision=1)), (2, dict(ir_method=1))])
-def test_refactor_solve_matches_separate_calls(dev, cfg, opts):
-    # kkt_refactor_solve runs x0's lower sweep beside the refactorization (FP64 FGMRES-IR; other
-    # settings run the two calls in turn): the same operations, so the same bits as kkt_refactor
-    # then kkt_solve, system after system, with the factors equal as well
-    say("refactor_solve config", cfg, opts)
-    p = ks.make_pattern(cfg)
-    v1, _ = p.system(1)
-    a = P.Solver(p.rowptr, p.colidx, v1, **opts).bind(dev)
-    c = P.Solver(p.rowptr, p.colidx, v1, **opts).bind(dev)
-    for step in (1, 2, 3) if cfg == 2 else (1,):
-        v, b = p.system(step)
-        vv, bb = cuda(v, dev), cuda(b, dev)
-        a.refactor(vv)
-        xa, ia = a.solve(bb, allow_noconv=True)
-        xc, ic = c.refactor_solve(vv, bb, allow_noconv=True)
-        assert torch.equal(xa, xc), "system %d" % step
-        for k in ("iterations", "cycles", "nrbe", "converged", "pivots_perturbed", "status"):
-            assert ia[k] == ic[k], k
-        la, ua = a.factor_values(0)
-        lc, uc = c.factor_values(0)
-        assert np.array_equal(la, lc) and np.array_equal(ua, uc)
-        # a plain solve after the combined call sees the same factors
-        xs, _ = c.solve(bb, allow_noconv=True)
-        assert torch.equal(xs, xc)
-
-
 def test_solve_repeatable_bitwise(dev):
     say("repeatability config 2")
     p, s, f = make(2, dev)
