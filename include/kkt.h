@@ -126,7 +126,11 @@ typedef struct {
                                wavefronts) and n/64 capped at 16,384; measured best at 60k,
                                500k and 2M unknowns); negative values are rejected
                                (KKT_EINVAL).  The factors do not depend on it. */
-    int32_t reserved;
+    int32_t deterministic;  /* 1 (default): bitwise-repeatable results.  Every kernel reduces in
+                               a fixed order and none uses floating-point atomics, so a solve
+                               gives the same bits alone, batched, in a serving mix or on a
+                               rerun; there is no faster nondeterministic mode, and any value
+                               other than 1 is rejected (KKT_EINVAL) */
 } kkt_opts_t;
 
 enum { KKT_IR_FGMRES = 0, KKT_IR_RICHARDSON = 1, KKT_IR_ERROR_FGMRES = 2 };

@@ -2792,6 +2792,7 @@ void kkt_opts_default(kkt_opts_t *o) {
     o->residual = KKT_RESID_FP64;
     o->repivot_cycles = 3;
     o->gram_schmidt = KKT_GS_CGS2;
+    o->deterministic = 1;
 }
 
 kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowptr, const int32_t *colidx,
@@ -2818,6 +2819,10 @@ kkt_status_t kkt_analyze(const kkt_opts_t *opts, int64_t n, const int64_t *rowpt
         (h->opts.tile_lds_kib * 1024 < kTileLdsMin || h->opts.tile_lds_kib * 1024 > kTileLdsMax)) {
         delete h;
         return fail(nullptr, KKT_EINVAL, "tile_lds_kib must be 0 or in 16..150");
+    }
+    if (h->opts.deterministic != 1) {
+        delete h;
+        return fail(nullptr, KKT_EINVAL, "deterministic must be 1 (results are always bitwise repeatable)");
     }
     if (h->opts.narrow_columns < 0) {
         delete h;

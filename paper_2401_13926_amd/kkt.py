@@ -51,7 +51,7 @@ class Opts(C.Structure):
                 ("mixed_fallback", C.c_int32), ("mixed_max_cycles", C.c_int32), ("ir_method", C.c_int32),
                 ("richardson_max_it", C.c_int32), ("ratio_stop", C.c_double), ("inner_tol", C.c_double),
                 ("residual", C.c_int32), ("repivot_cycles", C.c_int32), ("gram_schmidt", C.c_int32),
-                ("tile_lds_kib", C.c_int32), ("narrow_columns", C.c_int32), ("reserved", C.c_int32)]
+                ("tile_lds_kib", C.c_int32), ("narrow_columns", C.c_int32), ("deterministic", C.c_int32)]
 
 
 class AnalysisInfo(C.Structure):

@@ -121,7 +121,8 @@ def test_errors():
 
 
 @pytest.mark.parametrize("opt", [dict(tile_lds_kib=8), dict(tile_lds_kib=151), dict(gram_schmidt=2),
-                                 dict(restart=65), dict(residual=3), dict(narrow_columns=-1)])
+                                 dict(restart=65), dict(residual=3), dict(narrow_columns=-1),
+                                 dict(deterministic=0)])
 def test_option_validation(opt):
     p = ks.small_kkt(20, 10, 1)
     v, _ = p.system(1)
