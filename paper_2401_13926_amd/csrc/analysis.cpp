@@ -581,8 +581,14 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
     struct Size {
         int64_t rows = 0, ent = 0, ext = 0;  // ext: references to earlier windows (upper bound)
     };
-    // tiles are formed within a smaller budget, so that dense blocks fit in what remains
-    const int64_t stage_budget = opt.tile_lds - dense_reserve;
+    // Tiles of a window that starts at a narrow level (the top of the DAG, where runs of small
+    // levels become dense segments) are formed within a smaller budget, so that dense blocks
+    // fit in what remains; wide windows use the whole budget (fewer, larger tiles: at 2M
+    // unknowns the reserve in every window made the L sweep 30 % slower).
+    auto budget_at = [&](int32_t l) {
+        return lev_ptr[l + 1] - lev_ptr[l] <= kDenseWindowRows ? opt.tile_lds - dense_reserve : opt.tile_lds;
+    };
+    int64_t stage_budget = budget_at(0);
     auto stageable = [&](const Size &z) {
         return z.rows <= opt.tile_rows && tile_lds_bytes(z.rows, z.ext, z.ent) <= stage_budget;
     };
@@ -799,6 +805,7 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
         emit_window(w0, l - 1);
         clear_window(w0, l - 1);
         w0 = l;
+        stage_budget = budget_at(l);
         add_level(l, w0);
     }
     if (nlev) emit_window(w0, nlev - 1);

@@ -41,6 +41,9 @@ struct AnalysisOptions {
 constexpr int32_t kSegWave = 0x40;
 constexpr int32_t kSegDense = 0x80;
 constexpr int kDenseRows = 64;
+// A solve window whose first level has at most this many rows keeps part of its tile budget
+// for dense blocks (the narrow top of the DAG); wider windows use the whole budget.
+constexpr int kDenseWindowRows = 2048;
 
 // Schedule of one triangular solve.  A tile is a contiguous run of rows solved by one block;
 // it is cut into segments, each a set of mutually independent rows covered by one pass of the
