@@ -713,8 +713,9 @@ bool tri_schedule(const AnalysisOptions &opt, int64_t n, const std::vector<int64
                 tmax[l - w0] = 0;
             }
             // consecutive small levels are fused into dense segments while the LDS left over
-            // by the tile's entries holds their blocks
-            int64_t room = staged && dense_reserve > 0
+            // by the tile's entries holds their blocks, in windows that start at a narrow level
+            // only (fused blocks in the tiles of wide windows made the 2M L sweep 4 % slower)
+            int64_t room = staged && dense_reserve > 0 && stage_budget < opt.tile_lds
                                ? opt.tile_lds - tile_lds_bytes(tsize.rows, tsize.ext, tsize.ent)
                                : 0;
             int64_t dvals = 0;
