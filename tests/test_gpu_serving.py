@@ -150,3 +150,44 @@ def test_server_eight_patterns_match_alone(dev, max_batch, graphs):
     if graphs:
         assert st["graph_launches"] >= 1
     srv.close()
+
+
+def test_server_repivot_retires_slot(dev):
+    # A pattern whose inherited pivots fail on system 2 (D over 26 decades, tau = 0.1): the
+    # request re-pivots inside its slot, which the server then retires, so the next request of
+    # the pattern runs on a slot with the pattern's own analysis.  Every result equals the
+    # standalone refactor + solve of a fresh handle on that analysis, bit for bit, whatever the
+    # slot served before.
+    say("server re-pivoting pattern")
+    tau = 0.1
+    p = ks.small_kkt(35000, 25000, 17, (-13.0, 13.0))
+    v1, _ = p.system(1)
+    order = [2, 3, 2]
+    alone = {}
+    for k in set(order):
+        s = P.Solver(p.rowptr, p.colidx, v1, pivot_tau=tau).bind(dev)
+        v, b = p.system(k)
+        s.refactor(cuda(v, dev))
+        x, info = s.solve(cuda(b, dev))
+        assert info["converged"] == 1
+        alone[k] = (x.cpu().numpy(), info["repivoted"], info["iterations"])
+    assert alone[2][1] == 1
+    size = P.Solver(p.rowptr, p.colidx, v1, pivot_tau=tau).workspace_size()
+    srv = P.Server(int(size * 1.6 * 3), workers=1, device=dev, max_batch=1, graphs=False)
+    pid = srv.add_pattern(p.rowptr, p.colidx, v1, pivot_tau=tau)
+    for k in order:
+        v, b = p.system(k)
+        vv, bb = cuda(v, dev), cuda(b, dev)
+        x = torch.empty_like(bb)
+        rc, info, _ = srv.wait(srv.submit(pid, vv, bb, x))
+        say("   system %d: repivoted %d, iterations %d" % (k, info["repivoted"], info["iterations"]))
+        assert rc == P.KKT_OK and info["converged"] == 1 and info["nrbe"] <= 1e-12
+        xa, rpa, ita = alone[k]
+        assert np.array_equal(x.cpu().numpy(), xa), "system %d" % k
+        assert info["repivoted"] == rpa and info["iterations"] == ita
+    st = srv.stats()
+    say("   stats", st)
+    assert st["completed"] == len(order)
+    # a new slot for the first request and after every request that re-pivoted
+    assert st["slots_created"] == 1 + sum(alone[k][1] for k in order[:-1])
+    srv.close()
