@@ -3,12 +3,164 @@
 // (int64 n, int64 nnz, double tau, int32 ordering, int32 tile_kib; then rowptr, colidx, values),
 // runs the analysis and prints its sizes as one line of key=value pairs, or the status and the
 // message of a rejected input.  Any sanitizer report makes the process exit non-zero.
+//
+// It also replays both triangular-solve schedules on the CPU the way the solve kernel reads
+// them (tiles in hand-out order; a staged tile's rows and externals in LDS slots, its entries
+// referring to slots; unstaged one-row tiles reading global rows; dense segments as a block
+// pass over references outside the segment, then a column sweep over the column-major
+// strictly lower block) with random factor values, starting from a solution vector of NaN, and
+// compares the result with plain substitution over the triangle's CSR (sched_l / sched_u =
+// the relative difference, or the first violated property).  A reference to a value that is
+// not final yet, a wrong slot or block index, a row solved twice or never, a segment whose
+// rows do not fit its lanes, or a tile over its LDS budget all show up there.
+#include <cmath>
 #include <cstdio>
 #include <cstdint>
+#include <limits>
+#include <random>
 #include <string>
 #include <vector>
 
 #include "../../paper_2401_13926_amd/csrc/analysis.hpp"
+
+namespace {
+
+// rp/ci: the strict triangle's rows in pivot-step space (L: columns < row, U: columns > row);
+// lower: L (unit diagonal) or U (diagonal d).  Returns "ok=<max relative difference>" or an error.
+std::string replay(const kkt::TriSchedule &sc, int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
+                   bool lower, int64_t tile_lds, int threads) {
+    std::mt19937_64 gen(lower ? 11 : 12);
+    std::uniform_real_distribution<double> uni(-1.0, 1.0);
+    std::vector<double> val(ci.size()), b(n), d(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t len = rp[i + 1] - rp[i];
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) val[p] = 0.5 * uni(gen) / (double)(len ? len : 1);
+        b[i] = uni(gen);
+        d[i] = 1.5 + 0.5 * uni(gen);
+    }
+    // reference: plain substitution in the order the dependencies allow
+    std::vector<double> ref(n);
+    if (lower) {
+        for (int64_t i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) acc += val[p] * ref[ci[p]];
+            ref[i] = b[i] - acc;
+        }
+    } else {
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double acc = 0.0;
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) acc += val[p] * ref[ci[p]];
+            ref[i] = (b[i] - acc) / d[i];
+        }
+    }
+    // the triangle's values as the refactorization leaves them: packed entries, then dense blocks
+    if ((int64_t)sc.csr2ent.size() != (int64_t)ci.size()) return "csr2ent_size";
+    std::vector<double> tv(sc.values(), 0.0);
+    std::vector<int> hit(sc.values(), 0);
+    for (size_t p = 0; p < ci.size(); ++p) {
+        const int64_t e = sc.csr2ent[p];
+        if (e < 0 || e >= sc.values() || hit[e]++) return "csr2ent_slot";
+        tv[e] = val[p];
+    }
+    if ((int64_t)sc.rows.size() != n || (int64_t)sc.row_ent.size() != n + 1) return "rows_size";
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    std::vector<double> out(n, nan);
+    std::vector<int> solved(n, 0);
+    for (int64_t t = 0; t < sc.tiles(); ++t) {
+        const int32_t s0 = sc.tile_seg[t], s1 = sc.tile_seg[t + 1];
+        const int32_t rb = sc.seg_row[s0], re = sc.seg_row[s1];
+        const int32_t nr = re - rb;
+        const int64_t eb = sc.row_ent[rb], ne = sc.row_ent[re] - eb;
+        const int32_t xb = sc.tile_ext[t], nx = sc.tile_ext[t + 1] - xb;
+        const int64_t db = sc.tile_dense[t], nd = sc.tile_dense[t + 1] - db;
+        auto finish = [&](int32_t r, double res) -> bool {
+            const int32_t i = sc.rows[r];
+            if (i < 0 || i >= n || solved[i]++) return false;
+            out[i] = res;
+            return true;
+        };
+        if (!sc.tile_lds[t]) {  // one row, entries and sources in global memory
+            if (nr != 1 || nd != 0 || nx != 0) return "unstaged_shape";
+            double acc = 0.0;
+            for (int64_t e = 0; e < ne; ++e) {
+                const int32_t c = sc.ent_ref[eb + e];
+                if (c < 0 || c >= n || std::isnan(out[c])) return "unstaged_ref";
+                acc += tv[eb + e] * out[c];
+            }
+            const int32_t i = sc.rows[rb];
+            if (!finish(rb, lower ? b[i] - acc : (b[i] - acc) / d[i])) return "row_twice";
+            continue;
+        }
+        if (kkt::tile_lds_bytes(nr, nx, ne, nd) > tile_lds) return "tile_budget";
+        // LDS: the tile's rows, then its externals (final before the tile starts)
+        std::vector<double> xs(nr + nx, nan);
+        for (int32_t k = 0; k < nx; ++k) {
+            const int32_t c = sc.ext_src[xb + k];
+            if (c < 0 || c >= n || std::isnan(out[c])) return "external_not_final";
+            xs[nr + k] = out[c];
+        }
+        for (int64_t e = 0; e < ne; ++e)
+            if (sc.ent_ref[eb + e] < 0 || sc.ent_ref[eb + e] >= nr + nx || sc.ent_ref[eb + e] > 0xFFFF) return "slot_range";
+        auto row_sum = [&](int32_t r, double &acc) -> bool {  // r local
+            acc = 0.0;
+            for (int64_t e = sc.row_ent[rb + r] - eb; e < sc.row_ent[rb + r + 1] - eb; ++e) {
+                const double x = xs[sc.ent_ref[eb + e]];
+                if (std::isnan(x)) return false;
+                acc += tv[eb + e] * x;
+            }
+            return true;
+        };
+        for (int32_t g = s0; g < s1; ++g) {
+            const int32_t lb = sc.seg_row[g] - rb, le = sc.seg_row[g + 1] - rb, m = le - lb;
+            const int32_t code = sc.seg_lg[g], lg = code & 0xF;
+            if (m <= 0) return "empty_segment";
+            if (((int64_t)m << lg) > ((code & kkt::kSegWave) ? 64 : threads)) return "segment_lanes";
+            if (code & kkt::kSegDense) {
+                if (m > kkt::kDenseRows || sc.seg_dofs[g] < 0 || sc.seg_dofs[g] + kkt::dense_block_values(m) > nd)
+                    return "dense_block";
+                std::vector<double> y(m);
+                for (int32_t l = 0; l < m; ++l) {
+                    double acc;
+                    if (!row_sum(lb + l, acc)) return "dense_ref_not_final";
+                    y[l] = b[sc.rows[rb + lb + l]] - acc;
+                }
+                const double *D = tv.data() + db + sc.seg_dofs[g];
+                for (int32_t c = 0; c < m; ++c) {
+                    const double xc = lower ? y[c] : y[c] / d[sc.rows[rb + lb + c]];
+                    for (int32_t l = c + 1; l < m; ++l) y[l] -= D[(int64_t)c * m - (int64_t)c * (c + 1) / 2 + (l - c - 1)] * xc;
+                }
+                for (int32_t l = 0; l < m; ++l) {
+                    const double res = lower ? y[l] : y[l] / d[sc.rows[rb + lb + l]];
+                    xs[lb + l] = res;
+                    if (!finish(rb + lb + l, res)) return "row_twice";
+                }
+                continue;
+            }
+            std::vector<double> res(m);
+            for (int32_t l = 0; l < m; ++l) {  // rows of a segment are independent of each other
+                double acc;
+                if (!row_sum(lb + l, acc)) return "ref_not_final";
+                const int32_t i = sc.rows[rb + lb + l];
+                res[l] = lower ? b[i] - acc : (b[i] - acc) / d[i];
+            }
+            for (int32_t l = 0; l < m; ++l) {
+                xs[lb + l] = res[l];
+                if (!finish(rb + lb + l, res[l])) return "row_twice";
+            }
+        }
+    }
+    double scale = 0.0, diff = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!solved[i]) return "row_never_solved";
+        scale = std::fmax(scale, std::fabs(ref[i]));
+        diff = std::fmax(diff, std::fabs(out[i] - ref[i]));
+    }
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "ok:%.3e", scale > 0.0 ? diff / scale : diff);
+    return buf;
+}
+
+}  // namespace
 
 int main(int argc, char **argv) {
     if (argc != 2) {
@@ -46,10 +198,14 @@ int main(int argc, char **argv) {
     }
     int64_t offdiag = 0;
     for (int64_t k = 0; k < n; ++k) offdiag += a.prow[k] != a.q[k];
+    const std::string sl = replay(a.lsched, n, a.lrp, a.lci, true, opt.tile_lds, opt.tile_threads);
+    const std::string su = replay(a.usched, n, a.urp, a.uci, false, opt.tile_lds, opt.tile_threads);
+    int64_t dense_l = 0;
+    for (int32_t code : a.lsched.seg_lg) dense_l += (code & kkt::kSegDense) != 0;
     std::printf("status=0 nnz_l=%lld nnz_u=%lld levels_refactor=%lld levels_l=%lld levels_u=%lld updates=%lld "
-                "offdiag_pivots=%lld tiles_l=%lld tiles_u=%lld items=%lld\n",
+                "offdiag_pivots=%lld tiles_l=%lld tiles_u=%lld items=%lld dense_l=%lld sched_l=%s sched_u=%s\n",
                 (long long)a.nnz_l(), (long long)a.nnz_u(), (long long)a.levels_refactor, (long long)a.lsched.levels,
                 (long long)a.usched.levels, (long long)a.updates(), (long long)offdiag, (long long)a.lsched.tiles(),
-                (long long)a.usched.tiles(), (long long)a.ref_item.size() - 1);
+                (long long)a.usched.tiles(), (long long)a.ref_item.size() - 1, (long long)dense_l, sl.c_str(), su.c_str());
     return 0;
 }

@@ -1,7 +1,10 @@
 """The host analysis (analysis.cpp) built with AddressSanitizer and UndefinedBehaviorSanitizer
 (g++, host code only) and run on the workload's small systems, the arrow-head KKT, the
 moderate family, nested dissection, a tile budget of 16 KiB and rejected inputs: no sanitizer
-report, and the same sizes and schedule statistics as the library's own build."""
+report, and the same sizes and schedule statistics as the library's own build.  The driver also
+replays both triangular-solve schedules on the CPU as the solve kernel reads them (LDS slots,
+externals, unstaged rows, dense blocks) with random factors: the result must match plain
+substitution to rounding."""
 import os
 import pathlib
 import shutil
@@ -57,12 +60,20 @@ CASES = {
 }
 
 
+def assert_schedules_replay(out):
+    # "ok:<relative difference from plain substitution>", or the first violated property
+    for k in ("sched_l", "sched_u"):
+        assert out[k].startswith("ok:") and float(out[k][3:]) <= 1e-12, (k, out[k])
+
+
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_analysis_under_sanitizers_matches_library(driver, tmp_path, case):
     p, kw = CASES[case]()
     v, _ = p.system(1)
     out = run(driver, tmp_path, p.rowptr, p.colidx, v, **kw)
     assert out["status"] == "0"
+    assert_schedules_replay(out)
+    assert int(out["dense_l"]) > 0  # the replay covers dense segments
     opts = dict(pivot_tau=kw.get("tau", 1e-10), ordering=kw.get("ordering", 0), tile_lds_kib=kw.get("tile_kib", 0),
                 narrow_columns=1024)
     info = P.Solver(p.rowptr, p.colidx, v, **opts).info()
@@ -76,6 +87,7 @@ def test_arrow_head_under_sanitizers(driver, tmp_path):
     v, _ = a.system(1)
     out = run(driver, tmp_path, a.rowptr, a.colidx, v)
     assert out["status"] == "0" and int(out["nnz_u"]) > 0
+    assert_schedules_replay(out)
 
 
 def test_rejected_inputs_under_sanitizers(driver, tmp_path):
