@@ -160,11 +160,71 @@ std::string replay(const kkt::TriSchedule &sc, int64_t n, const std::vector<int6
     return buf;
 }
 
+// Replays the refactorization of another system with the same pattern from the hand-out
+// metadata, as the refactorization kernel reads it: K's values in the vector-order copy (ksrc),
+// items in hand-out order, each column staged through fsrc_k, its flat update list (relsrc,
+// relpos, relslot) applied in order, the pivot guard (unit roundoff 2^-53 times the staged
+// column's largest magnitude), L published to Ld (NaN until then: a source read before it is
+// final means an item depends on a later one, which the kernel's progress argument forbids),
+// and every value scattered into the solve layout through f2t.  lx/ux come back from the solve
+// layout in exchange layout, as kkt_get_factor_values reads them.
+std::string replay_refactor(const kkt::Analysis &a, const std::vector<double> &vals, std::vector<double> &lx,
+                            std::vector<double> &ux) {
+    if (!a.phys) return "no_flat_list";
+    const int64_t f = a.nnz_f();
+    std::vector<double> kval(a.ksrc.size());
+    for (size_t t = 0; t < kval.size(); ++t) kval[t] = vals[a.ksrc[t]];
+    std::vector<double> ld(f, std::numeric_limits<double>::quiet_NaN()), tv(a.t_size, 0.0);
+    std::vector<int> written(a.t_size, 0);
+    for (size_t it = 0; it + 1 < a.ref_item.size(); ++it) {
+        for (int64_t p = a.ref_item[it]; p < a.ref_item[it + 1]; ++p) {
+            const int64_t c0 = a.pc[p], len = a.pc[p + 1] - c0;
+            const int32_t nu = a.pnu[p];
+            if (len <= 0 || nu < 0 || nu >= len) return "column_shape";
+            std::vector<double> x(len);
+            double cm = 0.0;
+            for (int64_t e = 0; e < len; ++e) {
+                const int64_t src = a.fsrc_k[c0 + e];
+                x[e] = src >= 0 ? kval[src] : 0.0;
+                cm = std::fmax(cm, std::fabs(x[e]));
+            }
+            for (int64_t b = a.pu[p]; b < a.pu[p + 1]; ++b) {
+                const int64_t src = a.relsrc[b];
+                const int32_t pos = a.relpos[b], slot = a.relslot[b];
+                if (src < 0 || src >= f || pos <= 0 || pos >= len || slot < 0 || slot >= nu) return "update_index";
+                const double l = ld[src];
+                if (std::isnan(l)) return "source_not_final";
+                const double prod = l * x[slot];
+                x[pos] = x[pos] - prod;
+            }
+            double d = x[nu];
+            const double ur = 0x1p-53, cmx = cm > 0.0 ? cm : 1.0;
+            if (!(std::fabs(d) > ur * cmx) || !std::isfinite(d)) d = (d < 0.0 ? -1.0 : 1.0) * ur * cmx;
+            for (int64_t e = 0; e < len; ++e) {
+                double v = x[e];
+                if (e == nu) v = d;
+                else if (e > nu) v = v / d;
+                if (e > nu) ld[c0 + e] = v;
+                const int64_t t = a.f2t[c0 + e];
+                if (t < 0 || t >= a.t_size || written[t]++) return "f2t_slot";
+                tv[t] = v;
+            }
+        }
+    }
+    lx.resize(a.nnz_l());
+    ux.resize(a.nnz_u());
+    for (int64_t q = 0; q < a.nnz_l(); ++q) lx[q] = tv[a.f2t[a.l2f[q]]];
+    for (int64_t q = 0; q < a.nnz_u(); ++q) ux[q] = tv[a.f2t[a.u2f[q]]];
+    return "ok";
+}
+
 }  // namespace
 
 int main(int argc, char **argv) {
-    if (argc != 2) {
-        std::fprintf(stderr, "usage: %s input.bin\n", argv[0]);
+    // input.bin may end with a second system's values (nnz float64): then the refactorization
+    // is replayed with them and the factors written to factors.bin (float64 lx, then ux)
+    if (argc != 2 && argc != 3) {
+        std::fprintf(stderr, "usage: %s input.bin [factors.bin]\n", argv[0]);
         return 2;
     }
     std::FILE *f = std::fopen(argv[1], "rb");
@@ -179,6 +239,8 @@ int main(int argc, char **argv) {
     std::vector<double> v(ok ? nnz : 0);
     ok = ok && std::fread(rp.data(), 8, rp.size(), f) == rp.size() && std::fread(ci.data(), 4, ci.size(), f) == ci.size() &&
          std::fread(v.data(), 8, v.size(), f) == v.size();
+    std::vector<double> v2(ok ? nnz : 0);
+    const bool second = ok && argc == 3 && std::fread(v2.data(), 8, v2.size(), f) == v2.size();
     std::fclose(f);
     if (!ok) return 2;
     kkt::AnalysisOptions opt;
@@ -207,5 +269,18 @@ int main(int argc, char **argv) {
                 (long long)a.nnz_l(), (long long)a.nnz_u(), (long long)a.levels_refactor, (long long)a.lsched.levels,
                 (long long)a.usched.levels, (long long)a.updates(), (long long)offdiag, (long long)a.lsched.tiles(),
                 (long long)a.usched.tiles(), (long long)a.ref_item.size() - 1, (long long)dense_l, sl.c_str(), su.c_str());
+    if (second) {
+        std::vector<double> lx, ux;
+        const std::string r = replay_refactor(a, v2, lx, ux);
+        std::printf("refactor=%s\n", r.c_str());
+        if (r == "ok") {
+            std::FILE *o = std::fopen(argv[2], "wb");
+            if (!o) return 2;
+            const bool w = std::fwrite(lx.data(), 8, lx.size(), o) == lx.size() &&
+                           std::fwrite(ux.data(), 8, ux.size(), o) == ux.size();
+            std::fclose(o);
+            if (!w) return 2;
+        }
+    }
     return 0;
 }

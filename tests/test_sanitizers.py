@@ -4,7 +4,8 @@ moderate family, nested dissection, a tile budget of 16 KiB and rejected inputs:
 report, and the same sizes and schedule statistics as the library's own build.  The driver also
 replays both triangular-solve schedules on the CPU as the solve kernel reads them (LDS slots,
 externals, unstaged rows, dense blocks) with random factors: the result must match plain
-substitution to rounding."""
+substitution to rounding; and it replays the refactorization of a second system from the
+hand-out metadata: bit-identical to the oracle's static-pivot refactorization."""
 import os
 import pathlib
 import shutil
@@ -14,6 +15,7 @@ import numpy as np
 import pytest
 
 import kkt_synth as ks
+import oracle
 import paper_2401_13926_amd as P
 
 ROOT = pathlib.Path(__file__).resolve().parents[1]
@@ -33,7 +35,7 @@ def driver(tmp_path_factory):
     return out
 
 
-def run(driver, tmp_path, rowptr, colidx, values, tau=1e-10, ordering=0, tile_kib=0):
+def run(driver, tmp_path, rowptr, colidx, values, tau=1e-10, ordering=0, tile_kib=0, values2=None):
     f = tmp_path / "in.bin"
     rp = np.ascontiguousarray(rowptr, np.int64)
     ci = np.ascontiguousarray(colidx, np.int32)
@@ -43,9 +45,12 @@ def run(driver, tmp_path, rowptr, colidx, values, tau=1e-10, ordering=0, tile_ki
         fh.write(np.array([tau], np.float64).tobytes())
         fh.write(np.array([ordering, tile_kib], np.int32).tobytes())
         fh.write(rp.tobytes() + ci.tobytes() + v.tobytes())
+        if values2 is not None:
+            fh.write(np.ascontiguousarray(values2, np.float64).tobytes())
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=23",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1:exitcode=24")
-    r = subprocess.run([str(driver), str(f)], capture_output=True, text=True, env=env, timeout=600)
+    cmd = [str(driver), str(f)] + ([str(tmp_path / "factors.bin")] if values2 is not None else [])
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, r.stderr[-4000:]
     assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr[-4000:]
     return dict(kv.split("=", 1) for kv in r.stdout.split() if "=" in kv)
@@ -102,3 +107,31 @@ def test_rejected_inputs_under_sanitizers(driver, tmp_path):
     assert out["status"] != "0"
     out = run(driver, tmp_path, np.array([0, 1, 2], np.int64), np.array([0, 0], np.int32), np.ones(2))
     assert out["status"] != "0"
+
+
+REFACTOR_CASES = {
+    "7k": lambda: (ks.make_pattern(1), 1e-10),
+    "arrow": lambda: (ks.ArrowKKT(4000, 1500, 2500, seed=1), 1e-10),
+    # inherited threshold pivots that leave tiny static pivots in system 2: the guard fires
+    "60k-guarded": lambda: (ks.small_kkt(35000, 25000, 17, (-13.0, 13.0)), 0.1),
+}
+
+
+@pytest.mark.parametrize("case", sorted(REFACTOR_CASES))
+def test_refactor_metadata_replay_matches_oracle(driver, tmp_path, case):
+    # the refactorization of system 2 replayed on the CPU from the hand-out metadata (items
+    # in hand-out order, staging map into the vector-order copy of K, flat update lists, the
+    # scatter into the solve layout) equals the oracle's static-pivot refactorization bit for
+    # bit, and no item reads a source that a later item produces
+    p, tau = REFACTOR_CASES[case]()
+    v1, _ = p.system(1)
+    v2, _ = p.system(2)
+    out = run(driver, tmp_path, p.rowptr, p.colidx, v1, tau=tau, values2=v2)
+    assert out["status"] == "0" and out["refactor"] == "ok", out.get("refactor")
+    fac = np.fromfile(tmp_path / "factors.bin", np.float64)
+    nl = int(out["nnz_l"])
+    f = oracle.LU(p.rowptr, p.colidx, v1, tau=tau)
+    olx, oux, guarded = f.refactor64(p.rowptr, p.colidx, v2)
+    assert np.array_equal(fac[:nl], olx) and np.array_equal(fac[nl:], oux)
+    if case == "60k-guarded":
+        assert guarded > 0
