@@ -113,7 +113,7 @@ def _cpu_worker(cfg, rank, procs, seconds, q):
     import kkt_synth as ks
     import oracle
     pattern = ks.make_pattern(cfg)
-    nsys = ks.CONFIGS[cfg]["steps"]
+    nsys = ks.WORKLOAD_SHAPES[cfg]["steps"]
     Q = oracle.order(pattern.rowptr, pattern.colidx)
     done, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < seconds:
@@ -369,7 +369,7 @@ def run_hykkt(P, torch, args):
     dev = torch.device("cuda:0")
     cfg = args.config
     pattern = ks.make_pattern(cfg, delta=0.0)
-    nsys = ks.CONFIGS[cfg]["steps"]
+    nsys = ks.WORKLOAD_SHAPES[cfg]["steps"]
     systems = [pattern.system(k) for k in range(1, nsys + 1)]
     vals = [torch.as_tensor(v, device=dev) for v, _ in systems]
     rhs = [torch.as_tensor(b, device=dev) for _, b in systems]
@@ -488,7 +488,7 @@ def main():
 
     cfg = args.config
     pattern = ks.make_pattern(cfg)
-    nsys = ks.CONFIGS[cfg]["steps"]
+    nsys = ks.WORKLOAD_SHAPES[cfg]["steps"]
     systems = [pattern.system(k) for k in range(1, nsys + 1)]
     print("workload config %d: N=%d nnz=%d systems=%d" % (cfg, pattern.N, pattern.nnz, nsys),
           file=sys.stderr, flush=True)

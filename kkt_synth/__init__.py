@@ -37,7 +37,7 @@ BASE_SEED = 2401
 DUAL_REG = 1e-8
 
 #: Workload shapes: (n, m, log10 D range, number of systems in the sequence).
-CONFIGS = {
+WORKLOAD_SHAPES = {
     1: dict(n=4_000, m=3_000, dlog=(-8.0, 8.0), steps=1),
     2: dict(n=35_000, m=25_000, dlog=(-10.0, 10.0), steps=20),
     3: dict(n=290_000, m=210_000, dlog=(-12.0, 12.0), steps=10),
@@ -178,7 +178,7 @@ def make_pattern(config: int, pattern: int = 0, n: int | None = None, m: int | N
             m = dim - n
             dlog = SERVING_DLOG
         else:
-            c = CONFIGS[config]
+            c = WORKLOAD_SHAPES[config]
             n, m, dlog = c["n"], c["m"], c["dlog"]
     if dlog is None:
         dlog = (-8.0, 8.0)

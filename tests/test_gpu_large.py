@@ -90,7 +90,7 @@ def test_500k_sequence_fgmres_ir_every_system(dev):
     v1, _ = p.system(1)
     s = P.Solver(p.rowptr, p.colidx, v1, restart=30).bind(dev)
     f = oracle.LU(p.rowptr, p.colidx, v1)
-    for step in range(2, ks.CONFIGS[3]["steps"] + 1):
+    for step in range(2, ks.WORKLOAD_SHAPES[3]["steps"] + 1):
         v, b = p.system(step)
         x, xo, xd, rel, relo = refine_and_compare(p, s, f, v, b, 30, dev, "system %d" % step)
         # the GPU and the oracle refine the same factors: they land equally close to the
